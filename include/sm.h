@@ -1,0 +1,171 @@
+/*
+ * sm.h -- C ABI of an MI355X (gfx950) library for online exact string matching.
+ *
+ * The operation (Faro & Lecroq, "The Exact String Matching Problem: a
+ * Comprehensive Experimental Evaluation", Section 1): given a text t of length n
+ * and a pattern p of length m over an alphabet of size sigma, find ALL
+ * occurrences of p in t. Here:
+ *   - t and p are raw bytes (0..255); sigma is a property of the data, never an
+ *     argument; there is no case folding and no sentinel;
+ *   - an occurrence is a 0-based offset i with 0 <= i <= n-m and
+ *     t[i+k] == p[k] for 0 <= k < m; overlapping occurrences all count;
+ *   - positions are reported as int64 in strictly ascending order.
+ *
+ * Conventions shared by every entry point
+ *   - m == 0 is invalid (SM_EINVAL). m > n or n == 0 gives zero occurrences
+ *     (SM_OK). m must be < 2^32.
+ *   - `count` receives the TOTAL number of occurrences on SM_OK and on
+ *     SM_TRUNCATED. When the total exceeds `cap`, exactly the first `cap`
+ *     positions (the sorted prefix) are written and SM_TRUNCATED is returned.
+ *     Count first, then size the output, is the intended two-call pattern.
+ *   - Arguments are validated before any device work; a NULL text with n > 0, a
+ *     NULL pattern, a NULL count, or a NULL output with cap > 0 is SM_EINVAL.
+ *   - The caller owns every buffer passed in; the library keeps no caller
+ *     pointer after a call returns (a corpus opened with text_on_device borrows
+ *     its device text until sm_corpus_close).
+ *   - Results do not depend on the algorithm, tile size, q or any other tuning
+ *     choice: every algorithm is exact and results are bit-identical.
+ *   - Calls are reentrant. On failure, sm_last_error() returns a thread-local
+ *     message describing the last non-OK status of the calling thread.
+ *   - Device pointers are HIP device addresses on the current HIP device;
+ *     `stream` is a hipStream_t (NULL = the default stream).
+ */
+#ifndef SM_H
+#define SM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sm_status {
+    SM_OK = 0,
+    SM_TRUNCATED = 1,   /* not an error: more occurrences than `cap` */
+    SM_EINVAL = -1,     /* invalid argument; nothing was launched */
+    SM_ENOMEM = -2,     /* a device or host allocation failed */
+    SM_EDEVICE = -3,    /* a HIP call failed, or the device is not gfx950 */
+    SM_EBUSY = -4       /* the resource is in use (server queue full, closing) */
+};
+
+/* Scan algorithms (paper, Figs. 1 and 3). SM_ALGO_AUTO lets the planner choose. */
+enum sm_algo {
+    SM_ALGO_AUTO = 0,
+    SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel, m <= 64 (Fig. 3) */
+    SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */
+    SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
+    SM_ALGO_HASHQ = 4      /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
+};
+
+/*
+ * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
+ * Options change speed only, never results. Invalid combinations (a bit-parallel
+ * algorithm with m > 64, q > m or q > 16, lane_bytes not in {16,32,64,128},
+ * hbits outside [8,13]) are SM_EINVAL.
+ */
+typedef struct sm_opts {
+    int32_t algo;         /* enum sm_algo */
+    int32_t lane_bytes;   /* candidate starts per lane; a tile is 256 * lane_bytes starts */
+    int32_t q;            /* Hash-q gram length, 1..16 */
+    int32_t sigma_hint;   /* expected alphabet size of the text (planner input only) */
+    int32_t tiles_per_wg; /* consecutive tiles per workgroup, >= 1 */
+    int32_t hbits;        /* Hash-q table has 2^hbits buckets */
+    int32_t reserved[2];  /* must be zero */
+} sm_opts;
+
+/* What the planner chose for a pattern of length m (introspection). */
+typedef struct sm_plan_info {
+    int32_t algo, lane_bytes, q, hbits, tiles_per_wg, reserved;
+} sm_plan_info;
+
+const char *sm_version(void);
+const char *sm_last_error(void);
+
+/*
+ * sm_find_all -- all occurrences, host buffers, synchronous.
+ *   text[n], pat[m]: host bytes.  out_pos[cap]: host int64 output.
+ *   *count: total number of occurrences.
+ * The text is copied to the device for the call (PCIe included); use a corpus or
+ * the *_dev / *_async forms for device-resident texts.
+ */
+int sm_find_all(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m,
+                int64_t *out_pos, uint64_t cap, uint64_t *count);
+
+/* sm_count -- number of occurrences only (host buffers, synchronous). */
+int sm_count(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m, uint64_t *count);
+
+/*
+ * Device-resident text and output, synchronous with respect to `count`:
+ *   d_text[n]: device bytes (any alignment).  pat[m]: HOST bytes.
+ *   d_out[cap]: device int64.  *count: host.  Work is enqueued on `stream`, which
+ *   is synchronized before returning. A scratch workspace is allocated and cached
+ *   per calling thread.
+ */
+int sm_find_all_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                    int64_t *d_out, uint64_t cap, uint64_t *count, void *stream);
+int sm_count_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                 uint64_t *count, void *stream);
+
+/*
+ * Asynchronous form: no host synchronization, no allocation. The total is
+ * written to *d_count (device uint64) in stream order; d_out receives the first
+ * min(cap, total) positions. d_work is a caller-owned device workspace of at
+ * least sm_workspace_size(n, m, opts) bytes, 256-byte aligned; it must not be
+ * shared with work that may run concurrently. The pattern (host) is captured
+ * into kernel arguments when m <= 3072 bytes, so the host buffer may be reused
+ * as soon as the call returns; longer patterns are copied with a host-blocking
+ * hipMemcpyAsync.
+ */
+uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts);
+int sm_find_all_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                      int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
+                      uint64_t work_bytes, const sm_opts *opts, void *stream);
+int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                   uint64_t *d_count, void *d_work, uint64_t work_bytes, const sm_opts *opts,
+                   void *stream);
+
+/* Planner introspection: the plan a call with these arguments would use. The
+ * pattern is read on the host only (its byte statistics inform the planner). */
+int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_info *info);
+
+/*
+ * Corpus: a device-resident text reused across queries (the paper's fixed text
+ * buffers, Section 3). sm_corpus_open copies a host text to the device
+ * (text_on_device = 0) or borrows a device pointer (text_on_device = 1; the
+ * caller keeps it alive until close), and probes its byte histogram once; the
+ * planner then uses the measured alphabet size. A corpus is immutable after
+ * open; concurrent queries on it are allowed.
+ */
+typedef struct sm_corpus sm_corpus;
+int sm_corpus_open(const uint8_t *text, uint64_t n, int text_on_device, sm_corpus **corpus);
+int sm_corpus_close(sm_corpus *corpus);
+/* host output, synchronous */
+int sm_corpus_find_all(sm_corpus *corpus, const uint8_t *pat, uint64_t m, int64_t *out_pos,
+                       uint64_t cap, uint64_t *count);
+int sm_corpus_count(sm_corpus *corpus, const uint8_t *pat, uint64_t m, uint64_t *count);
+/* histogram[256] (may be NULL) and effective alphabet size (number of distinct bytes) */
+int sm_corpus_stats(const sm_corpus *corpus, uint64_t *histogram, int32_t *sigma);
+/* device address of the corpus text and its length */
+int sm_corpus_text(const sm_corpus *corpus, const uint8_t **d_text, uint64_t *n);
+
+/*
+ * Kernel timing (profiling aid). While enabled, every *_async/_dev call records
+ * HIP events on its stream around its scan kernels. sm_prof_collect waits for the
+ * recorded events, returns the accumulated times and clears them.
+ */
+typedef struct sm_prof {
+    uint64_t calls;        /* calls recorded */
+    double count_ms;       /* sum of count-kernel times (the dominant kernel) */
+    double write_ms;       /* sum of scan + write kernel times */
+    double total_ms;       /* sum of whole-call times (prep .. last kernel) */
+    uint64_t text_bytes;   /* sum of n over the calls */
+    uint64_t occurrences;  /* sum of totals over the calls (0 if not read back) */
+} sm_prof;
+int sm_prof_enable(int on);
+int sm_prof_collect(sm_prof *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SM_H */

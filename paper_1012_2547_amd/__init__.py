@@ -1,0 +1,219 @@
+"""MI355X-native online exact string matching (Python binding of include/sm.h).
+
+Every step of the search runs in the HIP kernels of ``libsm.so``; this module only
+marshals arguments. PyTorch tensors provide device memory and streams.
+
+    import torch, paper_1012_2547_amd as sm
+    text = torch.randint(0, 4, (1 << 30,), dtype=torch.uint8, device="cuda")
+    pos = sm.find_all(text, b"\\x00\\x01\\x02\\x03")     # int64 tensor on the GPU
+    n = sm.count(text, b"\\x00\\x01")
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._native import (ALGO_AUTO, ALGO_BNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
+                      ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError, check,
+                      last_error, load)
+
+__all__ = ["find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
+           "Corpus", "opts", "prof_enable", "prof_collect", "SmError", "ALGO_AUTO",
+           "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version"]
+
+
+def version() -> str:
+    return load().sm_version().decode()
+
+
+def opts(algo: int = 0, lane_bytes: int = 0, q: int = 0, sigma_hint: int = 0,
+         tiles_per_wg: int = 0, hbits: int = 0) -> Opts:
+    o = Opts()
+    o.algo, o.lane_bytes, o.q = algo, lane_bytes, q
+    o.sigma_hint, o.tiles_per_wg, o.hbits = sigma_hint, tiles_per_wg, hbits
+    return o
+
+
+def _pat(pat) -> tuple[bytes, int]:
+    if isinstance(pat, np.ndarray):
+        pat = pat.astype(np.uint8, copy=False).tobytes()
+    b = bytes(pat)
+    return b, len(b)
+
+
+def _pat_ptr(b: bytes):
+    # a non-NULL pointer even for an empty pattern (m == 0 is rejected by the library)
+    return ctypes.cast(ctypes.c_char_p(b if b else b"\0"), ctypes.c_void_p)
+
+
+def _is_dev(t) -> bool:
+    return hasattr(t, "is_cuda") and t.is_cuda
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+
+
+def workspace_size(n: int, m: int, o: Opts | None = None) -> int:
+    return int(load().sm_workspace_size(n, m, ctypes.byref(o) if o is not None else None))
+
+
+def plan_query(pat, o: Opts | None = None) -> dict:
+    b, m = _pat(pat)
+    info = PlanInfo()
+    check(load().sm_plan_query(_pat_ptr(b), m, ctypes.byref(o) if o is not None else None,
+                               ctypes.byref(info)))
+    return {"algo": ALGO_NAMES[info.algo], "lane_bytes": info.lane_bytes, "q": info.q,
+            "hbits": info.hbits, "tiles_per_wg": info.tiles_per_wg}
+
+
+def find_all_async(text, pat, out, d_count, work, o: Opts | None = None, stream=None) -> int:
+    """Enqueue a search; total -> d_count[0], first len(out) positions -> out. No sync."""
+    b, m = _pat(pat)
+    return check(load().sm_find_all_async(
+        ctypes.c_void_p(text.data_ptr()), text.numel(), _pat_ptr(b), m,
+        ctypes.c_void_p(out.data_ptr() if out is not None and out.numel() else 0),
+        out.numel() if out is not None else 0, ctypes.c_void_p(d_count.data_ptr()),
+        ctypes.c_void_p(work.data_ptr()), work.numel(),
+        ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+
+
+def count_async(text, pat, d_count, work, o: Opts | None = None, stream=None) -> int:
+    b, m = _pat(pat)
+    return check(load().sm_count_async(
+        ctypes.c_void_p(text.data_ptr()), text.numel(), _pat_ptr(b), m,
+        ctypes.c_void_p(d_count.data_ptr()), ctypes.c_void_p(work.data_ptr()), work.numel(),
+        ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+
+
+def count(text, pat, o: Opts | None = None, stream=None) -> int:
+    """Number of occurrences of pat in text (a uint8 device tensor, or host bytes/ndarray)."""
+    L = load()
+    b, m = _pat(pat)
+    c = ctypes.c_uint64(0)
+    if _is_dev(text):
+        if o is not None:
+            import torch
+            work = torch.empty(workspace_size(text.numel(), m, o), dtype=torch.uint8,
+                               device=text.device)
+            dc = torch.zeros(1, dtype=torch.int64, device=text.device)
+            count_async(text, pat, dc, work, o, stream)
+            return int(dc.item())
+        check(L.sm_count_dev(ctypes.c_void_p(text.data_ptr()), text.numel(), _pat_ptr(b), m,
+                             ctypes.byref(c), _stream_ptr(stream)))
+        return int(c.value)
+    t = np.ascontiguousarray(np.frombuffer(bytes(text), np.uint8) if not isinstance(
+        text, np.ndarray) else text, dtype=np.uint8)
+    check(L.sm_count(ctypes.c_void_p(t.ctypes.data if t.size else 0), t.size, _pat_ptr(b), m,
+                     ctypes.byref(c)))
+    return int(c.value)
+
+
+def find_all(text, pat, cap: int | None = None, o: Opts | None = None, stream=None):
+    """Sorted int64 occurrence positions.
+
+    Device tensor in -> device tensor out (counted first, then written, unless cap
+    is given). Host bytes/ndarray in -> numpy array out.
+    """
+    L = load()
+    b, m = _pat(pat)
+    if _is_dev(text):
+        import torch
+        n = text.numel()
+        if o is not None:
+            work = torch.empty(workspace_size(n, m, o), dtype=torch.uint8, device=text.device)
+            dc = torch.zeros(1, dtype=torch.int64, device=text.device)
+            if cap is None:
+                count_async(text, pat, dc, work, o, stream)
+                cap = int(dc.item())
+            out = torch.empty(max(cap, 0), dtype=torch.int64, device=text.device)
+            find_all_async(text, pat, out, dc, work, o, stream)
+            total = int(dc.item())
+            return out[:min(total, cap)]
+        if cap is None:
+            cap = count(text, pat, None, stream)
+        out = torch.empty(max(cap, 0), dtype=torch.int64, device=text.device)
+        c = ctypes.c_uint64(0)
+        check(L.sm_find_all_dev(ctypes.c_void_p(text.data_ptr()), n, _pat_ptr(b), m,
+                                ctypes.c_void_p(out.data_ptr() if cap else 0), cap, ctypes.byref(c),
+                                _stream_ptr(stream)))
+        return out[:min(int(c.value), cap)]
+    t = np.ascontiguousarray(np.frombuffer(bytes(text), np.uint8) if not isinstance(
+        text, np.ndarray) else text, dtype=np.uint8)
+    if cap is None:
+        cap = count(t, pat)
+    out = np.empty(max(cap, 1), dtype=np.int64)
+    c = ctypes.c_uint64(0)
+    check(L.sm_find_all(ctypes.c_void_p(t.ctypes.data if t.size else 0), t.size, _pat_ptr(b), m,
+                        ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(c)))
+    return out[:min(int(c.value), cap)]
+
+
+class Corpus:
+    """A device-resident text reused across queries (sm_corpus_*)."""
+
+    def __init__(self, text):
+        L = load()
+        self._h = ctypes.c_void_p(0)
+        self._keep = None
+        if _is_dev(text):
+            self._keep = text  # borrowed: keep the tensor alive
+            check(L.sm_corpus_open(ctypes.c_void_p(text.data_ptr()), text.numel(), 1,
+                                   ctypes.byref(self._h)))
+        else:
+            t = np.ascontiguousarray(np.frombuffer(bytes(text), np.uint8) if not isinstance(
+                text, np.ndarray) else text, dtype=np.uint8)
+            check(L.sm_corpus_open(ctypes.c_void_p(t.ctypes.data if t.size else 0), t.size, 0,
+                                   ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            check(load().sm_corpus_close(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> tuple[np.ndarray, int]:
+        h = np.zeros(256, dtype=np.uint64)
+        s = ctypes.c_int32(0)
+        check(load().sm_corpus_stats(self._h, ctypes.c_void_p(h.ctypes.data), ctypes.byref(s)))
+        return h, int(s.value)
+
+    def count(self, pat) -> int:
+        b, m = _pat(pat)
+        c = ctypes.c_uint64(0)
+        check(load().sm_corpus_count(self._h, _pat_ptr(b), m, ctypes.byref(c)))
+        return int(c.value)
+
+    def find_all(self, pat, cap: int | None = None) -> np.ndarray:
+        b, m = _pat(pat)
+        if cap is None:
+            cap = self.count(pat)
+        out = np.empty(max(cap, 1), dtype=np.int64)
+        c = ctypes.c_uint64(0)
+        check(load().sm_corpus_find_all(self._h, _pat_ptr(b), m, ctypes.c_void_p(out.ctypes.data),
+                                        cap, ctypes.byref(c)))
+        return out[:min(int(c.value), cap)]
+
+
+def prof_enable(on: bool = True) -> None:
+    check(load().sm_prof_enable(1 if on else 0))
+
+
+def prof_collect() -> dict:
+    p = Prof()
+    check(load().sm_prof_collect(ctypes.byref(p)))
+    return {"calls": p.calls, "count_ms": p.count_ms, "write_ms": p.write_ms,
+            "total_ms": p.total_ms, "text_bytes": p.text_bytes}

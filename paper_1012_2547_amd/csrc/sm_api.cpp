@@ -1,0 +1,567 @@
+// C ABI of the exact string matching library: argument validation, planning,
+// workspace management, corpora and kernel timing. Device work is delegated to
+// the launchers in sm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sm.h"
+#include "sm_internal.h"
+
+using namespace sm;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                 \
+    } while (0)
+
+extern "C" const char *sm_version(void) { return "sm 0.1 (gfx950)"; }
+extern "C" const char *sm_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// device check: the code objects are built for gfx950 only
+// ---------------------------------------------------------------------------
+static int check_device()
+{
+    static std::mutex mu;
+    static std::vector<int> ok;  // per device: 0 unknown, 1 ok, -1 bad
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)ok.size() <= dev) ok.resize(dev + 1, 0);
+    if (ok[dev] == 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        ok[dev] = (strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+        if (ok[dev] < 0)
+            return fail(SM_EDEVICE, "device %d is %s; this library is built for gfx950 only", dev,
+                        prop.gcnArchName);
+    }
+    if (ok[dev] < 0) return fail(SM_EDEVICE, "device %d is not gfx950", dev);
+    return SM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planner
+// ---------------------------------------------------------------------------
+static int distinct_bytes(const uint8_t *p, uint64_t m)
+{
+    bool seen[256] = {false};
+    int d = 0;
+    for (uint64_t k = 0; k < m; k++)
+        if (!seen[p[k]]) { seen[p[k]] = true; d++; }
+    return d;
+}
+
+// smallest q with sigma^q >= 64 * (m - q + 1): few pattern q-grams per q-gram space
+static int choose_q(uint64_t m, int sigma)
+{
+    if (sigma < 2) sigma = 2;
+    const double ls = std::log((double)sigma);
+    int q = 1;
+    for (; q < Q_MAX; q++) {
+        double windows = (double)(m >= (uint64_t)q ? m - q + 1 : 1);
+        if (q * ls >= std::log(64.0 * windows)) break;
+    }
+    if (q < 2) q = 2;
+    if ((uint64_t)q > m) q = (int)m;
+    return q;
+}
+
+static int choose_hbits(uint64_t m, int q)
+{
+    uint64_t grams = m - q + 1;
+    int b = 0;
+    while ((1ull << b) < grams) b++;
+    b += 2;
+    return std::min(H_MAX, std::max(H_MIN, b));
+}
+
+static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma_known, Plan &p)
+{
+    sm_opts z;
+    memset(&z, 0, sizeof z);
+    if (!o) o = &z;
+    if (o->reserved[0] || o->reserved[1]) return fail(SM_EINVAL, "sm_opts.reserved must be zero");
+    if (o->algo < 0 || o->algo >= ALGO_COUNT_) return fail(SM_EINVAL, "unknown algorithm %d", o->algo);
+    if (o->lane_bytes && o->lane_bytes != 16 && o->lane_bytes != 32 && o->lane_bytes != 64 &&
+        o->lane_bytes != 128)
+        return fail(SM_EINVAL, "lane_bytes must be 16, 32, 64 or 128 (got %d)", o->lane_bytes);
+    if (o->q < 0 || o->q > Q_MAX) return fail(SM_EINVAL, "q must be in [1, %d]", Q_MAX);
+    if (o->hbits && (o->hbits < H_MIN || o->hbits > H_MAX))
+        return fail(SM_EINVAL, "hbits must be in [%d, %d]", H_MIN, H_MAX);
+    if (o->tiles_per_wg < 0 || o->tiles_per_wg > 4096)
+        return fail(SM_EINVAL, "tiles_per_wg must be in [1, 4096]");
+
+    int sigma = o->sigma_hint > 0 ? o->sigma_hint : sigma_known;
+    if (sigma <= 0) sigma = m >= 16 ? distinct_bytes(pat, m) : 256;
+
+    p.m = m;
+    p.algo = o->algo;
+    if (p.algo == ALGO_AUTO) {
+        if (m <= 12) p.algo = ALGO_SHIFT_AND;
+        else if (m <= BP_MAX_M) p.algo = ALGO_SBNDM;
+        else p.algo = ALGO_HASHQ;
+    }
+    if (p.algo != ALGO_HASHQ && m > BP_MAX_M)
+        return fail(SM_EINVAL, "bit-parallel algorithms need m <= %d (m = %llu)", BP_MAX_M,
+                    (unsigned long long)m);
+    p.q = 0;
+    p.hbits = 0;
+    if (p.algo == ALGO_HASHQ) {
+        p.q = o->q ? o->q : choose_q(m, sigma);
+        if ((uint64_t)p.q > m) return fail(SM_EINVAL, "q = %d exceeds m = %llu", p.q, (unsigned long long)m);
+        p.hbits = o->hbits ? o->hbits : choose_hbits(m, p.q);
+    }
+    p.lane_bytes = o->lane_bytes ? o->lane_bytes : 64;
+    p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (p.algo == ALGO_HASHQ ? 4 : 1);
+    return SM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    hipEvent_t e0, e1, e2, e3;  // start, after prep, after count, end
+    uint64_t n;
+    uint64_t *d_count;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+extern "C" int sm_prof_enable(int on)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return SM_OK;
+}
+
+extern "C" int sm_prof_collect(sm_prof *out)
+{
+    if (!out) return fail(SM_EINVAL, "out is NULL");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    memset(out, 0, sizeof *out);
+    int st = SM_OK;
+    for (auto &r : recs) {
+        float a = 0, b = 0, c = 0;
+        if (hipEventSynchronize(r.e3) == hipSuccess && hipEventElapsedTime(&a, r.e1, r.e2) == hipSuccess &&
+            hipEventElapsedTime(&b, r.e2, r.e3) == hipSuccess && hipEventElapsedTime(&c, r.e0, r.e3) == hipSuccess) {
+            out->calls++;
+            out->count_ms += a;
+            out->write_ms += b;
+            out->total_ms += c;
+            out->text_bytes += r.n;
+        } else {
+            st = fail(SM_EDEVICE, "event timing failed");
+        }
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+        (void)hipEventDestroy(r.e2);
+        (void)hipEventDestroy(r.e3);
+    }
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// core: validated, planned, asynchronous
+// ---------------------------------------------------------------------------
+static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m)
+{
+    if (m == 0) return fail(SM_EINVAL, "empty pattern (m = 0)");
+    if (!pat) return fail(SM_EINVAL, "pattern is NULL");
+    if (!text && n > 0) return fail(SM_EINVAL, "text is NULL with n > 0");
+    if (m > 0xFFFFFFFFull) return fail(SM_EINVAL, "m must be < 2^32");
+    return SM_OK;
+}
+
+extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
+{
+    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : 16;  // smallest tile: most tiles
+    Plan p;
+    p.lane_bytes = lb;
+    WsLayout w = ws_layout(n, m, tile_starts(p));
+    return w.total;
+}
+
+static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                     int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
+                     uint64_t work_bytes, const sm_opts *opts, hipStream_t st, bool write,
+                     int sigma_known)
+{
+    int r = validate_common(d_text, n, pat, m);
+    if (r) return r;
+    if (!d_count) return fail(SM_EINVAL, "d_count is NULL");
+    if (write && !d_out && cap > 0) return fail(SM_EINVAL, "output is NULL with cap > 0");
+    Plan plan;
+    r = make_plan(pat, m, opts, sigma_known, plan);
+    if (r) return r;
+    if ((r = check_device())) return r;
+    if (n == 0 || m > n) {
+        HIP_TRY(launch_set_u64(d_count, 0, st));
+        return SM_OK;
+    }
+    const WsLayout w = ws_layout(n, m, tile_starts(plan));
+    if (!d_work || work_bytes < w.total)
+        return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)w.total);
+    if (((uintptr_t)d_work & 255) != 0) return fail(SM_EINVAL, "workspace must be 256-byte aligned");
+    uint8_t *ws = static_cast<uint8_t *>(d_work);
+    Params *prm = reinterpret_cast<Params *>(ws + w.params);
+    uint8_t *dpat = ws + w.params + sizeof(Params);
+    uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + w.tile_cnt);
+    uint64_t *toff = reinterpret_cast<uint64_t *>(ws + w.tile_off);
+
+    bool prof;
+    ProfRec rec{};
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        prof = g_prof_on;
+    }
+    if (prof) {
+        HIP_TRY(hipEventCreate(&rec.e0));
+        HIP_TRY(hipEventCreate(&rec.e1));
+        HIP_TRY(hipEventCreate(&rec.e2));
+        HIP_TRY(hipEventCreate(&rec.e3));
+        rec.n = n;
+        HIP_TRY(hipEventRecord(rec.e0, st));
+    }
+    HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, st));
+    if (prof) HIP_TRY(hipEventRecord(rec.e1, st));
+    HIP_TRY(launch_count(plan, d_text, n, prm, dpat, tcnt, d_count, w.ntiles, st));
+    if (prof) HIP_TRY(hipEventRecord(rec.e2, st));
+    if (write) {
+        HIP_TRY(launch_scan(tcnt, w.ntiles, toff, d_count, st));
+        HIP_TRY(launch_write(plan, d_text, n, prm, dpat, tcnt, toff, d_out, cap, w.ntiles, st));
+    }
+    if (prof) {
+        HIP_TRY(hipEventRecord(rec.e3, st));
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof.push_back(rec);
+    }
+    return SM_OK;
+}
+
+extern "C" int sm_find_all_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                                 int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
+                                 uint64_t work_bytes, const sm_opts *opts, void *stream)
+{
+    return run_async(d_text, n, pat, m, d_out, cap, d_count, d_work, work_bytes, opts,
+                     (hipStream_t)stream, true, 0);
+}
+
+extern "C" int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                              uint64_t *d_count, void *d_work, uint64_t work_bytes,
+                              const sm_opts *opts, void *stream)
+{
+    return run_async(d_text, n, pat, m, nullptr, 0, d_count, d_work, work_bytes, opts,
+                     (hipStream_t)stream, false, 0);
+}
+
+extern "C" int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_info *info)
+{
+    if (m == 0) return fail(SM_EINVAL, "empty pattern (m = 0)");
+    if (!pat || !info) return fail(SM_EINVAL, "NULL argument");
+    Plan p;
+    int r = make_plan(pat, m, opts, 0, p);
+    if (r) return r;
+    info->algo = p.algo;
+    info->lane_bytes = p.lane_bytes;
+    info->q = p.q;
+    info->hbits = p.hbits;
+    info->tiles_per_wg = p.tiles_per_wg;
+    info->reserved = 0;
+    return SM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// synchronous device forms: per-thread cached workspace
+// ---------------------------------------------------------------------------
+namespace {
+struct Scratch {
+    int dev = -1;
+    void *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    uint64_t *d_count = nullptr;
+    ~Scratch()
+    {
+        // process teardown: the HIP runtime may already be gone; leak silently
+    }
+};
+thread_local Scratch g_scratch;
+
+int scratch_get(uint64_t need, void **ws, uint64_t **d_count)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    Scratch &s = g_scratch;
+    if (s.dev != dev) {
+        s = Scratch();
+        s.dev = dev;
+    }
+    if (!s.d_count) HIP_TRY(hipMalloc((void **)&s.d_count, 256));
+    if (s.ws_bytes < need) {
+        if (s.ws) HIP_TRY(hipFree(s.ws));
+        s.ws = nullptr;
+        s.ws_bytes = 0;
+        uint64_t sz = std::max<uint64_t>(need, 1 << 20);
+        HIP_TRY(hipMalloc(&s.ws, sz));
+        s.ws_bytes = sz;
+    }
+    *ws = s.ws;
+    *d_count = s.d_count;
+    return SM_OK;
+}
+}  // namespace
+
+static int run_sync_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                        int64_t *d_out, uint64_t cap, uint64_t *count, hipStream_t st, bool write,
+                        int sigma_known)
+{
+    int r = validate_common(d_text, n, pat, m);
+    if (r) return r;
+    if (!count) return fail(SM_EINVAL, "count is NULL");
+    if (write && !d_out && cap > 0) return fail(SM_EINVAL, "output is NULL with cap > 0");
+    Plan plan;
+    if ((r = make_plan(pat, m, nullptr, sigma_known, plan))) return r;
+    if (n == 0 || m > n) {
+        *count = 0;
+        return SM_OK;
+    }
+    if ((r = check_device())) return r;
+    sm_opts o;
+    memset(&o, 0, sizeof o);
+    o.sigma_hint = sigma_known;
+    const uint64_t need = sm_workspace_size(n, m, &o);
+    void *ws;
+    uint64_t *dc;
+    if ((r = scratch_get(need, &ws, &dc))) return r;
+    r = run_async(d_text, n, pat, m, d_out, cap, dc, ws, need, &o, st, write, sigma_known);
+    if (r) return r;
+    uint64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, dc, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *count = total;
+    return (write && total > cap) ? SM_TRUNCATED : SM_OK;
+}
+
+extern "C" int sm_find_all_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                               int64_t *d_out, uint64_t cap, uint64_t *count, void *stream)
+{
+    return run_sync_dev(d_text, n, pat, m, d_out, cap, count, (hipStream_t)stream, true, 0);
+}
+
+extern "C" int sm_count_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                            uint64_t *count, void *stream)
+{
+    return run_sync_dev(d_text, n, pat, m, nullptr, 0, count, (hipStream_t)stream, false, 0);
+}
+
+// ---------------------------------------------------------------------------
+// host-buffer forms
+// ---------------------------------------------------------------------------
+namespace {
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+}  // namespace
+
+static int run_host(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m,
+                    int64_t *out_pos, uint64_t cap, uint64_t *count, bool write)
+{
+    int r = validate_common(text, n, pat, m);
+    if (r) return r;
+    if (!count) return fail(SM_EINVAL, "count is NULL");
+    if (write && !out_pos && cap > 0) return fail(SM_EINVAL, "out_pos is NULL with cap > 0");
+    Plan plan;
+    if ((r = make_plan(pat, m, nullptr, 0, plan))) return r;
+    if (n == 0 || m > n) {
+        *count = 0;
+        return SM_OK;
+    }
+    if ((r = check_device())) return r;
+    DevBuf dt, dout;
+    HIP_TRY(hipMalloc(&dt.p, align_up(n, 256)));
+    HIP_TRY(hipMemcpy(dt.p, text, n, hipMemcpyHostToDevice));
+    const uint64_t ncap = std::min<uint64_t>(cap, n - m + 1);
+    if (write && ncap) HIP_TRY(hipMalloc(&dout.p, ncap * 8));
+    uint64_t total = 0;
+    r = run_sync_dev((const uint8_t *)dt.p, n, pat, m, (int64_t *)dout.p, write ? ncap : 0, &total,
+                     nullptr, write, 0);
+    if (r < 0) return r;
+    if (write && ncap) {
+        const uint64_t k = std::min<uint64_t>(total, ncap);
+        if (k) HIP_TRY(hipMemcpy(out_pos, dout.p, k * 8, hipMemcpyDeviceToHost));
+    }
+    *count = total;
+    return (write && total > cap) ? SM_TRUNCATED : SM_OK;
+}
+
+extern "C" int sm_find_all(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m,
+                           int64_t *out_pos, uint64_t cap, uint64_t *count)
+{
+    return run_host(text, n, pat, m, out_pos, cap, count, true);
+}
+
+extern "C" int sm_count(const uint8_t *text, uint64_t n, const uint8_t *pat, uint64_t m, uint64_t *count)
+{
+    return run_host(text, n, pat, m, nullptr, 0, count, false);
+}
+
+// ---------------------------------------------------------------------------
+// corpora
+// ---------------------------------------------------------------------------
+struct sm_corpus {
+    const uint8_t *d_text = nullptr;
+    uint64_t n = 0;
+    bool owned = false;
+    uint64_t hist[256];
+    int32_t sigma = 0;
+    int dev = 0;
+};
+
+extern "C" int sm_corpus_open(const uint8_t *text, uint64_t n, int text_on_device, sm_corpus **corpus)
+{
+    if (!corpus) return fail(SM_EINVAL, "corpus is NULL");
+    if (!text && n > 0) return fail(SM_EINVAL, "text is NULL with n > 0");
+    int r = check_device();
+    if (r) return r;
+    sm_corpus *c = new sm_corpus();
+    memset(c->hist, 0, sizeof c->hist);
+    HIP_TRY(hipGetDevice(&c->dev));
+    if (text_on_device) {
+        c->d_text = text;
+        c->owned = false;
+    } else if (n > 0) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, align_up(n, 256));
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SM_ENOMEM, "corpus allocation of %llu bytes failed: %s", (unsigned long long)n,
+                        hipGetErrorString(e));
+        }
+        e = hipMemcpy(p, text, n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            delete c;
+            return fail(SM_EDEVICE, "corpus upload failed: %s", hipGetErrorString(e));
+        }
+        c->d_text = (const uint8_t *)p;
+        c->owned = true;
+    }
+    c->n = n;
+    if (n > 0) {
+        uint64_t *dh = nullptr;
+        hipError_t e = hipMalloc((void **)&dh, 256 * 8);
+        if (e == hipSuccess) e = hipMemset(dh, 0, 256 * 8);
+        if (e == hipSuccess) e = launch_histogram(c->d_text, n, dh, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(c->hist, dh, 256 * 8, hipMemcpyDeviceToHost);
+        if (dh) (void)hipFree(dh);
+        if (e != hipSuccess) {
+            if (c->owned) (void)hipFree((void *)c->d_text);
+            delete c;
+            return fail(SM_EDEVICE, "corpus histogram failed: %s", hipGetErrorString(e));
+        }
+        for (int k = 0; k < 256; k++) c->sigma += c->hist[k] ? 1 : 0;
+    }
+    *corpus = c;
+    return SM_OK;
+}
+
+extern "C" int sm_corpus_close(sm_corpus *c)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    if (c->owned && c->d_text) (void)hipFree((void *)c->d_text);
+    delete c;
+    return SM_OK;
+}
+
+extern "C" int sm_corpus_stats(const sm_corpus *c, uint64_t *histogram, int32_t *sigma)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    if (histogram) memcpy(histogram, c->hist, sizeof c->hist);
+    if (sigma) *sigma = c->sigma;
+    return SM_OK;
+}
+
+extern "C" int sm_corpus_text(const sm_corpus *c, const uint8_t **d_text, uint64_t *n)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    if (d_text) *d_text = c->d_text;
+    if (n) *n = c->n;
+    return SM_OK;
+}
+
+extern "C" int sm_corpus_find_all(sm_corpus *c, const uint8_t *pat, uint64_t m, int64_t *out_pos,
+                                  uint64_t cap, uint64_t *count)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    int r = validate_common(c->d_text, c->n, pat, m);
+    if (r) return r;
+    if (!count) return fail(SM_EINVAL, "count is NULL");
+    if (!out_pos && cap > 0) return fail(SM_EINVAL, "out_pos is NULL with cap > 0");
+    if (c->n == 0 || m > c->n) {
+        *count = 0;
+        return SM_OK;
+    }
+    HIP_TRY(hipSetDevice(c->dev));
+    DevBuf dout;
+    const uint64_t ncap = std::min<uint64_t>(cap, c->n - m + 1);
+    if (ncap) HIP_TRY(hipMalloc(&dout.p, ncap * 8));
+    uint64_t total = 0;
+    r = run_sync_dev(c->d_text, c->n, pat, m, (int64_t *)dout.p, ncap, &total, nullptr, true, c->sigma);
+    if (r < 0) return r;
+    const uint64_t k = std::min<uint64_t>(total, ncap);
+    if (k) HIP_TRY(hipMemcpy(out_pos, dout.p, k * 8, hipMemcpyDeviceToHost));
+    *count = total;
+    return total > cap ? SM_TRUNCATED : SM_OK;
+}
+
+extern "C" int sm_corpus_count(sm_corpus *c, const uint8_t *pat, uint64_t m, uint64_t *count)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    int r = validate_common(c->d_text, c->n, pat, m);
+    if (r) return r;
+    if (!count) return fail(SM_EINVAL, "count is NULL");
+    if (c->n == 0 || m > c->n) {
+        *count = 0;
+        return SM_OK;
+    }
+    HIP_TRY(hipSetDevice(c->dev));
+    return run_sync_dev(c->d_text, c->n, pat, m, nullptr, 0, count, nullptr, false, c->sigma);
+}

@@ -1,0 +1,99 @@
+// Internal declarations shared by the host library and the HIP kernels.
+// Not part of the public C ABI (include/sm.h).
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime.h>
+
+namespace sm {
+
+// Scan algorithms (values match SM_ALGO_* in include/sm.h).
+enum Algo : int32_t {
+    ALGO_AUTO = 0,
+    ALGO_SHIFT_AND = 1,  // bit-parallel prefix automaton, m <= 64 (Fig. 3, SA/SO)
+    ALGO_BNDM = 2,       // bit-parallel backward factor automaton, m <= 64 (Fig. 3, BNDM)
+    ALGO_SBNDM = 3,      // BNDM without prefix tracking, m <= 64 (Fig. 3, SBNDM)
+    ALGO_HASHQ = 4,      // hashed q-gram skip filter + verification, any m >= q (Fig. 1, HASHq)
+    ALGO_COUNT_ = 5
+};
+
+constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
+constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register
+constexpr int Q_MAX = 16;          // longest hashed q-gram
+constexpr int H_MIN = 8;           // hash table bits range
+constexpr int H_MAX = 13;
+constexpr int PREP_INLINE = 3072;  // pattern bytes carried in the prep kernel's arguments
+
+// Device-side parameter block, built by the prep kernel inside the caller's
+// workspace. The pattern follows the block (16-byte aligned, zero padded).
+struct alignas(16) Params {
+    uint32_t m, algo, q, hbits;
+    uint32_t sh1;     // Hash-q: shift after a verified window
+    uint32_t period;  // smallest period of the pattern (shift after an SBNDM hit)
+    uint32_t pad0, pad1;
+    uint64_t mask[256];          // Shift-And (complemented form) or BNDM masks
+    uint8_t shift[1 << H_MAX];   // Hash-q shift per hash bucket (capped at 255)
+};
+static_assert(sizeof(Params) % 16 == 0, "Params must keep the pattern 16-byte aligned");
+
+// Host-side plan: everything the launches need that is known on the host.
+struct Plan {
+    int32_t algo;
+    int32_t lane_bytes;   // L: candidate starts per lane; tile = BLOCK * L starts
+    int32_t q;            // Hash-q gram length
+    int32_t hbits;        // Hash-q table bits
+    int32_t tiles_per_wg; // consecutive tiles processed by one workgroup
+    uint64_t m;
+};
+
+// Workspace layout (offsets in bytes from the workspace base).
+struct WsLayout {
+    uint64_t params;    // Params + pattern
+    uint64_t tile_cnt;  // uint32_t[ntiles]
+    uint64_t tile_off;  // uint64_t[ntiles]
+    uint64_t total;     // bytes
+    uint64_t ntiles;
+};
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline uint64_t tile_starts(const Plan &p) { return (uint64_t)BLOCK * (uint64_t)p.lane_bytes; }
+
+inline uint64_t num_tiles(uint64_t n, uint64_t m, uint64_t tile)
+{
+    if (m == 0 || m > n) return 0;
+    return (n - m + 1 + tile - 1) / tile;
+}
+
+inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
+{
+    WsLayout w;
+    w.ntiles = num_tiles(n, m, tile);
+    w.params = 0;
+    uint64_t o = align_up(sizeof(Params) + align_up(m, 16) + 64, 256);
+    w.tile_cnt = o;
+    o = align_up(o + 4 * w.ntiles, 256);
+    w.tile_off = o;
+    o = align_up(o + 8 * w.ntiles, 256);
+    w.total = o;
+    return w;
+}
+
+// Kernel launchers (sm_kernels.hip). All are asynchronous on `stream` and
+// return the HIP error of the launch.
+hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_params,
+                       uint8_t *d_pat, uint64_t *d_zero, hipStream_t stream);
+hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n,
+                        const Params *d_params, const uint8_t *d_pat, uint32_t *d_tile_cnt,
+                        uint64_t *d_total, uint64_t ntiles, hipStream_t stream);
+hipError_t launch_scan(const uint32_t *d_tile_cnt, uint64_t ntiles, uint64_t *d_tile_off,
+                       uint64_t *d_total, hipStream_t stream);
+hipError_t launch_write(const Plan &plan, const uint8_t *d_text, uint64_t n,
+                        const Params *d_params, const uint8_t *d_pat,
+                        const uint32_t *d_tile_cnt, const uint64_t *d_tile_off, int64_t *d_out,
+                        uint64_t cap, uint64_t ntiles, hipStream_t stream);
+hipError_t launch_set_u64(uint64_t *d_dst, uint64_t value, hipStream_t stream);
+hipError_t launch_histogram(const uint8_t *d_text, uint64_t n, uint64_t *d_hist256,
+                            hipStream_t stream);
+
+}  // namespace sm

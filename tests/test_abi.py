@@ -1,0 +1,119 @@
+"""C ABI contract checks that need no GPU: exports, validation, planner.
+
+Every call here returns before any device work (argument errors, m > n, n == 0,
+planner introspection), so these run on a machine without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1012_2547_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_1012_2547_amd import build
+        build.build()
+    return _native.load()
+
+
+def header_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(sm_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_declares_every_header_function():
+    from paper_1012_2547_amd import _native
+    assert set(header_functions()) <= set(_native.PROTOTYPES)
+
+
+def test_version(L):
+    assert b"gfx950" in L.sm_version()
+
+
+def _u64():
+    return ctypes.c_uint64(12345)
+
+
+def test_validation_errors(L):
+    from paper_1012_2547_amd._native import SM_EINVAL, SM_OK
+    t = ctypes.create_string_buffer(b"abcabc")
+    p = ctypes.create_string_buffer(b"bc")
+    c = _u64()
+    # m == 0
+    assert L.sm_count(t, 6, p, 0, ctypes.byref(c)) == SM_EINVAL
+    assert b"m = 0" in L.sm_last_error()
+    # NULL pattern
+    assert L.sm_count(t, 6, None, 2, ctypes.byref(c)) == SM_EINVAL
+    # NULL text with n > 0
+    assert L.sm_count(None, 6, p, 2, ctypes.byref(c)) == SM_EINVAL
+    # NULL count
+    assert L.sm_count(t, 6, p, 2, None) == SM_EINVAL
+    # NULL output with cap > 0
+    assert L.sm_find_all(t, 6, p, 2, None, 5, ctypes.byref(c)) == SM_EINVAL
+    assert L.sm_find_all_dev(t, 6, p, 2, None, 5, ctypes.byref(c), None) == SM_EINVAL
+    # m too large for the ABI
+    assert L.sm_count(t, 6, p, 1 << 33, ctypes.byref(c)) == SM_EINVAL
+
+
+def test_degenerate_sizes_return_zero_without_device(L):
+    from paper_1012_2547_amd._native import SM_OK
+    t = ctypes.create_string_buffer(b"abc")
+    p = ctypes.create_string_buffer(b"abcd")
+    c = _u64()
+    assert L.sm_count(t, 3, p, 4, ctypes.byref(c)) == SM_OK and c.value == 0      # m > n
+    c = _u64()
+    assert L.sm_count(None, 0, p, 1, ctypes.byref(c)) == SM_OK and c.value == 0   # n == 0
+    c = _u64()
+    assert L.sm_find_all(t, 3, p, 4, None, 0, ctypes.byref(c)) == SM_OK and c.value == 0
+    c = _u64()
+    assert L.sm_count_dev(t, 3, p, 4, ctypes.byref(c), None) == SM_OK and c.value == 0
+
+
+def test_invalid_options(L):
+    import paper_1012_2547_amd as sm
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"a" * 65, sm.opts(algo=sm.ALGO_SHIFT_AND))   # bit-parallel needs m <= 64
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"abc", sm.opts(algo=sm.ALGO_HASHQ, q=4))       # q > m
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"abc", sm.opts(lane_bytes=48))
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"abc", sm.opts(algo=9))
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"a" * 100, sm.opts(algo=sm.ALGO_HASHQ, hbits=20))
+
+
+def test_planner_choices(L):
+    import paper_1012_2547_amd as sm
+    assert sm.plan_query(b"ab")["algo"] in ("shift_and", "bndm", "sbndm")
+    p = sm.plan_query(bytes(range(4)) * 64)   # m = 256 over 4 symbols
+    assert p["algo"] == "hashq" and 2 <= p["q"] <= 16 and 8 <= p["hbits"] <= 13
+    p2 = sm.plan_query(bytes(range(256)) * 2)  # m = 512 over 256 symbols: short grams suffice
+    assert p2["q"] < p["q"]
+    f = sm.plan_query(b"x" * 30, sm.opts(algo=sm.ALGO_BNDM, lane_bytes=32))
+    assert f["algo"] == "bndm" and f["lane_bytes"] == 32
+
+
+def test_workspace_size_monotone(L):
+    import paper_1012_2547_amd as sm
+    a = sm.workspace_size(1 << 20, 8)
+    b = sm.workspace_size(1 << 30, 8)
+    assert 0 < a < b
+    assert sm.workspace_size(10, 20) > 0

@@ -1,0 +1,240 @@
+"""GPU parity: every scan kernel, forced in turn, against the CPU oracle (bit-exact).
+
+Occurrence lists are integer data, so the bar is exact equality of the sorted
+int64 position lists (and of the totals).
+"""
+import numpy as np
+import pytest
+
+import datagen as dg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1012_2547_amd as sm
+    sm.version()  # fails loudly when libsm.so is missing
+    return sm
+
+
+DEV = "cuda:0"
+BP_ALGOS = (1, 2, 3)       # Shift-And, BNDM, SBNDM (m <= 64)
+ALL_ALGOS = (1, 2, 3, 4)   # + Hash-q
+
+
+def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0):
+    o = sm.opts(algo=algo, lane_bytes=lane, q=q, tiles_per_wg=tpw)
+    n, m = text_t.numel(), len(pat)
+    work = torch.empty(max(sm.workspace_size(n, m, o), 256), dtype=torch.uint8, device=DEV)
+    dc = torch.zeros(1, dtype=torch.int64, device=DEV)
+    sm.count_async(text_t, pat, dc, work, o)
+    total_c = int(dc.item())
+    if cap is None:
+        cap = total_c
+    out = torch.full((max(cap, 1),), -7, dtype=torch.int64, device=DEV)
+    sm.find_all_async(text_t, pat, out[:cap], dc, work, o)
+    total = int(dc.item())
+    assert total == total_c
+    res = out[:min(total, cap)].cpu().numpy()
+    # nothing written past min(total, cap)
+    assert np.all(out[min(total, cap):].cpu().numpy() == -7)
+    return res, total
+
+
+def applicable(algo, m, q=0):
+    if algo in BP_ALGOS:
+        return m <= 64
+    return m >= max(q, 1)
+
+
+def check_case(sm, t_np, t_dev, pat, algos=ALL_ALGOS, lanes=(64,)):
+    want = oracle.find_all(t_np, pat)
+    for a in algos:
+        if not applicable(a, len(pat)):
+            continue
+        for L in lanes:
+            got, tot = gpu_find(sm, t_dev, pat, algo=a, lane=L)
+            assert tot == want.size, (a, L, len(pat), tot, want.size)
+            assert np.array_equal(got, want), (a, L, len(pat))
+
+
+M_SET = (1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 18, 31, 32, 33, 48, 49, 50, 61, 62, 63, 64)
+M_LONG = (65, 100, 128, 255, 256, 513, 1024)
+
+
+@pytest.mark.parametrize("sigma", [2, 4, 16, 256])
+def test_grid_all_algorithms(sm, sigma):
+    n = 50_000 + 37  # several tiles at L=16, ragged tail
+    t_np = dg.uniform_text(n, sigma, seed=100 + sigma)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for i, m in enumerate(M_SET + M_LONG):
+        p_sub, _ = dg.substring_pattern(t_np, m, seed=5, idx=i)
+        check_case(sm, t_np, t_dev, p_sub, lanes=(16, 64))
+        if m <= 8:
+            check_case(sm, t_np, t_dev, dg.random_pattern(m, sigma, seed=6, idx=i), lanes=(32,))
+
+
+def test_hashq_every_q(sm):
+    n = 40_000
+    for sigma in (2, 4, 64):
+        t_np = dg.uniform_text(n, sigma, seed=3)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for m in (16, 17, 70, 300):
+            p, _ = dg.substring_pattern(t_np, m, seed=9, idx=m)
+            want = oracle.find_all(t_np, p)
+            for q in range(1, 17):
+                if q > m:
+                    continue
+                for L in (16, 128):
+                    got, tot = gpu_find(sm, t_dev, p, algo=4, lane=L, q=q)
+                    assert np.array_equal(got, want) and tot == want.size, (sigma, m, q, L)
+
+
+def test_tiles_per_workgroup_and_lanes_deterministic(sm):
+    t_np = dg.uniform_text(300_001, 4, seed=8)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for m in (6, 20, 200):
+        p, _ = dg.substring_pattern(t_np, m, seed=1, idx=m)
+        want = oracle.find_all(t_np, p)
+        for a in ALL_ALGOS:
+            if not applicable(a, m):
+                continue
+            for L in (16, 32, 64, 128):
+                for tpw in (1, 3, 8):
+                    got, _ = gpu_find(sm, t_dev, p, algo=a, lane=L, tpw=tpw)
+                    assert np.array_equal(got, want), (m, a, L, tpw)
+
+
+def test_closed_form_dense_output(sm):
+    n = (1 << 20) + 3
+    t_dev = torch.full((n,), ord("a"), dtype=torch.uint8, device=DEV)
+    for m in (1, 4, 16, 64, 256):
+        for a in ALL_ALGOS:
+            if not applicable(a, m):
+                continue
+            got, tot = gpu_find(sm, t_dev, b"a" * m, algo=a)
+            assert tot == n - m + 1
+            assert np.array_equal(got, np.arange(n - m + 1)), (m, a)
+
+
+def test_closed_form_periodic(sm):
+    P = 4096
+    n = P * 300 + 17
+    t_np = dg.periodic_text(n, ord("a"), ord("b"), P)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for m in (4, 16, 64, 256, 1024):
+        p = b"a" * (m - 1) + b"b"
+        want = np.array([P * k + P - m for k in range(n // P)], dtype=np.int64)
+        for a in ALL_ALGOS:
+            if not applicable(a, m):
+                continue
+            got, tot = gpu_find(sm, t_dev, p, algo=a)
+            assert np.array_equal(got, want), (m, a)
+
+
+def test_truncation(sm):
+    t_np = dg.uniform_text(100_000, 2, seed=4)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    p = bytes([0, 1, 0])
+    want = oracle.find_all(t_np, p)
+    assert want.size > 1000
+    for a in ALL_ALGOS:
+        for cap in (0, 1, 77, want.size - 1, want.size, want.size + 5):
+            got, tot = gpu_find(sm, t_dev, p, algo=a, cap=cap)
+            assert tot == want.size
+            assert np.array_equal(got, want[:cap]), (a, cap)
+
+
+def test_edges_and_alignment(sm):
+    rng = np.random.default_rng(0)
+    base_np = rng.integers(0, 3, 20_000, dtype=np.uint8)
+    base = torch.from_numpy(base_np).to(DEV)
+    for off in range(0, 16):
+        for n in (1, 2, 15, 16, 17, 255, 4097, 19_000 - off):
+            t_np = base_np[off:off + n]
+            t_dev = base[off:off + n]  # device pointer offset by `off` bytes
+            for m in (1, 2, 5, 16, 40, 64, 70):
+                if m > n:
+                    continue
+                for p in (bytes(t_np[:m]), bytes(t_np[n - m:])):
+                    want = oracle.find_all(t_np, p)
+                    assert want[0] == 0 or p != bytes(t_np[:m])
+                    for a in ALL_ALGOS:
+                        if not applicable(a, m):
+                            continue
+                        got, _ = gpu_find(sm, t_dev, p, algo=a, lane=16)
+                        assert np.array_equal(got, want), (off, n, m, a)
+
+
+def test_zero_bytes_at_text_end(sm):
+    """A pattern of 0x00 bytes must not match past the end of the text."""
+    for n in (1000, 1024, 4096 * 4 + 5):
+        t_np = np.ones(n, dtype=np.uint8)
+        t_np[-3:] = 0
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for m in (1, 2, 3, 4, 8, 64, 100):
+            want = oracle.find_all(t_np, bytes(m))
+            for a in ALL_ALGOS:
+                if not applicable(a, m):
+                    continue
+                got, tot = gpu_find(sm, t_dev, bytes(m), algo=a)
+                assert np.array_equal(got, want), (n, m, a)
+
+
+def test_m_equals_n_and_m_greater_than_n(sm):
+    t_np = dg.uniform_text(64, 4, seed=2)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for a in ALL_ALGOS:
+        got, tot = gpu_find(sm, t_dev, bytes(t_np), algo=a)
+        assert got.tolist() == [0]
+        got, tot = gpu_find(sm, t_dev, bytes(t_np[:63]) + b"\xff", algo=a)
+        assert tot == 0
+    got, tot = gpu_find(sm, t_dev, bytes(65))
+    assert tot == 0
+
+
+def test_config1_exact(sm):
+    """n = 2^20 uniform over 4 symbols (seed 1), m = 8 substring: full list."""
+    t_np = dg.uniform_text(1 << 20, 4, seed=1)
+    p, off = dg.substring_pattern(t_np, 8, seed=1, idx=0)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    want = oracle.find_all(t_np, p)
+    assert off in want.tolist()
+    got = sm.find_all(t_dev, p).cpu().numpy()
+    assert np.array_equal(got, want)
+    for a in ALL_ALGOS:
+        g2, _ = gpu_find(sm, t_dev, p, algo=a)
+        assert np.array_equal(g2, want), a
+
+
+def test_host_and_corpus_paths(sm):
+    t_np = dg.zipf_text(200_000, 64, 1.0, seed=1)
+    c = sm.Corpus(t_np)
+    hist, sigma = c.stats()
+    assert np.array_equal(hist, np.bincount(t_np, minlength=256).astype(np.uint64))
+    assert sigma == int((np.bincount(t_np, minlength=256) > 0).sum())
+    for m in (4, 16, 64, 256):
+        p, _ = dg.substring_pattern(t_np, m, seed=2, idx=m)
+        want = oracle.find_all(t_np, p)
+        assert np.array_equal(c.find_all(p), want)
+        assert c.count(p) == want.size
+        assert np.array_equal(sm.find_all(t_np, p), want)       # host buffers
+        assert sm.count(t_np, p) == want.size
+    c.close()
+
+
+def test_device_sync_paths(sm):
+    t_np = dg.uniform_text(123_457, 16, seed=9)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for m in (2, 9, 33, 64, 65, 500):
+        p, _ = dg.substring_pattern(t_np, m, seed=3, idx=m)
+        want = oracle.find_all(t_np, p)
+        got = sm.find_all(t_dev, p).cpu().numpy()
+        assert np.array_equal(got, want), m
+        assert sm.count(t_dev, p) == want.size
