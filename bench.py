@@ -1,0 +1,223 @@
+"""Benchmark: single-pattern exact matching sweep on one MI355X.
+
+Workload (the headline configuration): for each alphabet size sigma in
+{2, 4, 16, 64, 256} a text of n = 2^30 i.i.d. uniform bytes over {0..sigma-1}
+(text seed 1), and for each m in {2, 4, ..., 1024} 20 patterns copied from
+random offsets of that text (pattern seed 2) -- the shape of the paper's
+Section 3 experiments at 2^30 bytes instead of 5 MB. One step = the whole sweep:
+1000 find_all calls (device text, device output; count -> tile scan -> emit), texts
+resident in HBM before timing starts.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "text GB/s scanned (and % of HBM peak); batched patterns×GB/s; p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+SIGMAS = (2, 4, 16, 64, 256)
+MS = (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)
+PER_CELL = 20
+TEXT_SEED, PAT_SEED = 1, 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sm_kernels.hip", "sm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1012_2547_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-log2", type=int, default=30)
+    ap.add_argument("--per-cell", type=int, default=PER_CELL)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every box in this setup has a single MI355X; "
+              "--gpus %d is not supported (run with --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen as dg
+    import paper_1012_2547_amd as sm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 1 << args.n_log2
+    stream = torch.cuda.current_stream()
+
+    # ---- inputs: texts resident in HBM, patterns, exact output sizes -------
+    t0 = time.time()
+    host_texts, dev_texts, pats = {}, {}, {}
+    for s in SIGMAS:
+        h = dg.uniform_text(n, s, seed=TEXT_SEED)
+        host_texts[s] = h
+        dev_texts[s] = torch.from_numpy(h).to(dev)
+        for mi, m in enumerate(MS):
+            pats[(s, m)] = [dg.substring_pattern(h, m, seed=PAT_SEED, idx=mi * 1000 + j)[0]
+                            for j in range(args.per_cell)]
+    log("inputs ready in %.1fs" % (time.time() - t0))
+
+    calls = [(s, m, p) for s in SIGMAS for m in MS for p in pats[(s, m)]]
+    work = torch.empty(sm.workspace_size(n, 1024), dtype=torch.uint8, device=dev)
+    counts_dev = torch.zeros(len(calls), dtype=torch.int64, device=dev)
+    # exact counts (sizes the output buffer; checked after every step)
+    for k, (s, m, p) in enumerate(calls):
+        sm.count_async(dev_texts[s], p, counts_dev[k:k + 1], work, None, stream)
+    torch.cuda.synchronize()
+    expect = counts_dev.cpu().numpy().copy()
+    cap = int(expect.max())
+    out = torch.empty(cap, dtype=torch.int64, device=dev)
+    occ_total = int(expect.sum())
+    log("counts ready: max %d, total %d occurrences per step" % (cap, occ_total))
+
+    def step():
+        for k, (s, m, p) in enumerate(calls):
+            sm.find_all_async(dev_texts[s], p, out, counts_dev[k:k + 1], work, None, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    got = counts_dev.cpu().numpy()
+    assert np.array_equal(got, expect), "find_all totals differ from count totals"
+
+    sm.prof_collect()  # clear
+    sm.prof_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sm.prof_enable(False)
+    prof = sm.prof_collect()
+    assert np.array_equal(counts_dev.cpu().numpy(), expect)
+
+    elapsed = t2 - t1
+    bytes_per_step = n * len(calls)
+    gbs = bytes_per_step * args.steps / elapsed / 1e9
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    # dominant kernel: the count kernel, one pass over the text (n bytes per launch)
+    calls_n = max(prof["calls"], 1)
+    avg_count_s = prof["count_ms"] / calls_n / 1e3
+    count_gbs = n / avg_count_s / 1e9
+    algo_bytes_call = (n * len(calls) + 8 * occ_total) / len(calls)
+    call_gbs = algo_bytes_call / (prof["total_ms"] / calls_n / 1e3) / 1e9
+    traffic = load_traffic("count")
+    roofline = {"bound": "hbm", "achieved": round(count_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(count_gbs / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "count_kernel<algo, L, variant, find> (text pass)",
+                "avg_launch_us": round(avg_count_s * 1e6, 2), "launches": prof["calls"],
+                "bytes_per_launch": n,
+                "avg_emit_us": round(prof["emit_ms"] / calls_n * 1e3, 2),
+                "whole_call_algorithmic_gbs": round(call_gbs, 1)}
+    log("sweep: %.1f GB/s text, count kernel %.1f GB/s (%.1f%% of HBM), emit %.1f us avg, "
+        "%.2f ms/step" % (gbs, count_gbs, 100 * count_gbs / HBM_PEAK_GBS,
+                          roofline["avg_emit_us"], ms_per_step))
+
+    # per-cell rates (mean over the cell's patterns), from one extra timed pass
+    cells = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+    ev[0].record(stream)
+    for k, (s, m, p) in enumerate(calls):
+        sm.find_all_async(dev_texts[s], p, out, counts_dev[k:k + 1], work, None, stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    for k, (s, m, p) in enumerate(calls):
+        dt = ev[k].elapsed_time(ev[k + 1]) / 1e3
+        cells.setdefault("s%d_m%d" % (s, m), []).append(n / dt / 1e9)
+    cell_gbs = {c: round(float(np.median(v)), 1) for c, v in cells.items()}
+
+    # ---- CPU baseline: the oracle on host cores, plus full-size parity --------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        sample = [(s, m, pats[(s, m)][0]) for s in SIGMAS for m in MS]
+        tc = time.perf_counter()
+        mismatches = 0
+        for s, m, p in sample:
+            want = oracle.find_all(host_texts[s], p, threads=threads)
+            g = torch.empty(max(want.size, 1), dtype=torch.int64, device=dev)
+            dc = torch.zeros(1, dtype=torch.int64, device=dev)
+            sm.find_all_async(dev_texts[s], p, g, dc, work, None, stream)
+            torch.cuda.synchronize()
+            if int(dc.item()) != want.size or not np.array_equal(g[:want.size].cpu().numpy(), want):
+                mismatches += 1
+        # the GPU checks above are not timed separately; time the oracle alone
+        t_or = 0.0
+        for s, m, p in sample:
+            ta = time.perf_counter()
+            oracle.find_all(host_texts[s], p, threads=threads)
+            t_or += time.perf_counter() - ta
+        cpu = {"value": round(n * len(sample) / t_or / 1e9, 3), "unit": "GB/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "naive oracle find_all, one pattern per (sigma, m) cell of the sweep "
+                         "(50 patterns) over the full 2^30-byte texts, %d threads" % threads,
+               "seconds": round(t_or, 2), "fullsize_parity_mismatches": mismatches}
+        log("cpu baseline: %.2f GB/s on %d threads (%.1fs); full-size parity mismatches: %d" %
+            (cpu["value"], threads, t_or, mismatches))
+        if mismatches:
+            raise SystemExit("full-size parity failed on %d patterns" % mismatches)
+
+    res = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "single-pattern sweep, one launch per pattern: n=2^%d uniform "
+                               "sigma in %s, m in %s, %d substring patterns per cell, find_all "
+                               "(count -> tile scan -> emit)" % (args.n_log2, list(SIGMAS), list(MS),
+                                                              args.per_cell),
+                   "text_bytes_per_step": bytes_per_step, "occurrences_per_step": occ_total},
+        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "cells_median_gbs": cell_gbs,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

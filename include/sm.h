@@ -61,7 +61,7 @@ enum sm_algo {
  * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
  * Options change speed only, never results. Invalid combinations (a bit-parallel
  * algorithm with m > 64, q > m or q > 16, lane_bytes not in {16,32,64,128},
- * hbits outside [8,13]) are SM_EINVAL.
+ * hbits outside [8,12]) are SM_EINVAL.
  */
 typedef struct sm_opts {
     int32_t algo;         /* enum sm_algo */
@@ -110,11 +110,16 @@ int sm_count_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t
  * Asynchronous form: no host synchronization, no allocation. The total is
  * written to *d_count (device uint64) in stream order; d_out receives the first
  * min(cap, total) positions. d_work is a caller-owned device workspace of at
- * least sm_workspace_size(n, m, opts) bytes, 256-byte aligned; it must not be
- * shared with work that may run concurrently. The pattern (host) is captured
- * into kernel arguments when m <= 3072 bytes, so the host buffer may be reused
- * as soon as the call returns; longer patterns are copied with a host-blocking
- * hipMemcpyAsync.
+ * least sm_workspace_size(n, m, opts) bytes, 256-byte aligned, with no required
+ * initial contents; it must not be used by two calls that may run concurrently. The pattern (host) is
+ * captured into kernel arguments when m <= 3072 bytes, so the host buffer may be
+ * reused as soon as the call returns; longer patterns are copied with a
+ * host-blocking hipMemcpyAsync.
+ *
+ * find_all runs three kernels: a count pass over the text (which also keeps the
+ * hit offsets of tiles with few hits), a scan of the per-tile counts, and an
+ * emit pass that writes positions (re-reading the text only for tiles with many
+ * hits). count runs the first kernel only; its workspace may be smaller.
  */
 uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts);
 int sm_find_all_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
@@ -150,16 +155,15 @@ int sm_corpus_text(const sm_corpus *corpus, const uint8_t **d_text, uint64_t *n)
 
 /*
  * Kernel timing (profiling aid). While enabled, every *_async/_dev call records
- * HIP events on its stream around its scan kernels. sm_prof_collect waits for the
+ * HIP events on its stream around its kernels. sm_prof_collect waits for the
  * recorded events, returns the accumulated times and clears them.
  */
 typedef struct sm_prof {
     uint64_t calls;        /* calls recorded */
-    double count_ms;       /* sum of count-kernel times (the dominant kernel) */
-    double write_ms;       /* sum of scan + write kernel times */
-    double total_ms;       /* sum of whole-call times (prep .. last kernel) */
+    double count_ms;       /* count kernel (the pass over the text; the dominant kernel) */
+    double emit_ms;        /* tile scan + emit kernels (find_all only) */
+    double total_ms;       /* whole calls: pattern preparation + all kernels */
     uint64_t text_bytes;   /* sum of n over the calls */
-    uint64_t occurrences;  /* sum of totals over the calls (0 if not read back) */
 } sm_prof;
 int sm_prof_enable(int on);
 int sm_prof_collect(sm_prof *out);

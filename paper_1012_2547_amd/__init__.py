@@ -215,5 +215,5 @@ def prof_enable(on: bool = True) -> None:
 def prof_collect() -> dict:
     p = Prof()
     check(load().sm_prof_collect(ctypes.byref(p)))
-    return {"calls": p.calls, "count_ms": p.count_ms, "write_ms": p.write_ms,
+    return {"calls": p.calls, "count_ms": p.count_ms, "emit_ms": p.emit_ms,
             "total_ms": p.total_ms, "text_bytes": p.text_bytes}

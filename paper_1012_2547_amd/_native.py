@@ -36,8 +36,8 @@ class PlanInfo(ctypes.Structure):
 
 class Prof(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_uint64), ("count_ms", ctypes.c_double),
-                ("write_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("text_bytes", ctypes.c_uint64), ("occurrences", ctypes.c_uint64)]
+                ("emit_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("text_bytes", ctypes.c_uint64)]
 
 
 # every exported symbol and its prototype: (restype, argtypes)

@@ -149,9 +149,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
 // ---------------------------------------------------------------------------
 namespace {
 struct ProfRec {
-    hipEvent_t e0, e1, e2, e3;  // start, after prep, after count, end
+    hipEvent_t e0, e1, e2, e3;  // start, after prep, after the count kernel, end
     uint64_t n;
-    uint64_t *d_count;
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -181,7 +180,7 @@ extern "C" int sm_prof_collect(sm_prof *out)
             hipEventElapsedTime(&b, r.e2, r.e3) == hipSuccess && hipEventElapsedTime(&c, r.e0, r.e3) == hipSuccess) {
             out->calls++;
             out->count_ms += a;
-            out->write_ms += b;
+            out->emit_ms += b;
             out->total_ms += c;
             out->text_bytes += r.n;
         } else {
@@ -209,11 +208,11 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
 
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
-    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : 16;  // smallest tile: most tiles
+    // the planner never picks lanes below AUTO_MIN_LANE on its own
+    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : AUTO_MIN_LANE;
     Plan p;
     p.lane_bytes = lb;
-    WsLayout w = ws_layout(n, m, tile_starts(p));
-    return w.total;
+    return ws_layout(n, m, tile_starts(p)).need;
 }
 
 static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
@@ -234,14 +233,20 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         return SM_OK;
     }
     const WsLayout w = ws_layout(n, m, tile_starts(plan));
-    if (!d_work || work_bytes < w.total)
-        return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)w.total);
+    const uint64_t need = write ? w.need : w.tile_cnt;
+    if (!d_work || work_bytes < need)
+        return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)need);
     if (((uintptr_t)d_work & 255) != 0) return fail(SM_EINVAL, "workspace must be 256-byte aligned");
     uint8_t *ws = static_cast<uint8_t *>(d_work);
     Params *prm = reinterpret_cast<Params *>(ws + w.params);
-    uint8_t *dpat = ws + w.params + sizeof(Params);
-    uint32_t *tcnt = reinterpret_cast<uint32_t *>(ws + w.tile_cnt);
-    uint64_t *toff = reinterpret_cast<uint64_t *>(ws + w.tile_off);
+    uint8_t *dpat = ws + w.pat;
+    FindWs fw;
+    fw.tile_cnt = reinterpret_cast<uint32_t *>(ws + w.tile_cnt);
+    fw.tile_off = reinterpret_cast<uint64_t *>(ws + w.tile_off);
+    fw.list = reinterpret_cast<uint32_t *>(ws + w.list);
+    fw.nlist = reinterpret_cast<uint64_t *>(ws + w.nlist);
+    fw.stash = reinterpret_cast<uint16_t *>(ws + w.stash);
+    fw.ntiles = w.ntiles;
 
     bool prof;
     ProfRec rec{};
@@ -259,11 +264,12 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     }
     HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, st));
     if (prof) HIP_TRY(hipEventRecord(rec.e1, st));
-    HIP_TRY(launch_count(plan, d_text, n, prm, dpat, tcnt, d_count, w.ntiles, st));
-    if (prof) HIP_TRY(hipEventRecord(rec.e2, st));
     if (write) {
-        HIP_TRY(launch_scan(tcnt, w.ntiles, toff, d_count, st));
-        HIP_TRY(launch_write(plan, d_text, n, prm, dpat, tcnt, toff, d_out, cap, w.ntiles, st));
+        HIP_TRY(launch_find(plan, d_text, n, prm, dpat, fw, d_out, cap, d_count, st,
+                            prof ? rec.e2 : nullptr));
+    } else {
+        HIP_TRY(launch_count(plan, d_text, n, prm, dpat, d_count, w.ntiles, st));
+        if (prof) HIP_TRY(hipEventRecord(rec.e2, st));
     }
     if (prof) {
         HIP_TRY(hipEventRecord(rec.e3, st));

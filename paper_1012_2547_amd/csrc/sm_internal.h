@@ -21,11 +21,15 @@ constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
 constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register
 constexpr int Q_MAX = 16;          // longest hashed q-gram
 constexpr int H_MIN = 8;           // hash table bits range
-constexpr int H_MAX = 13;
+constexpr int H_MAX = 12;
 constexpr int PREP_INLINE = 3072;  // pattern bytes carried in the prep kernel's arguments
 
-// Device-side parameter block, built by the prep kernel inside the caller's
-// workspace. The pattern follows the block (16-byte aligned, zero padded).
+constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass
+constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
+constexpr int AUTO_MIN_LANE = 64;    // smallest lane_bytes the planner picks on its own
+
+// Device-side parameter block at the start of the caller's workspace; the
+// pattern follows it (16-byte aligned, zero padded).
 struct alignas(16) Params {
     uint32_t m, algo, q, hbits;
     uint32_t sh1;     // Hash-q: shift after a verified window
@@ -42,16 +46,15 @@ struct Plan {
     int32_t lane_bytes;   // L: candidate starts per lane; tile = BLOCK * L starts
     int32_t q;            // Hash-q gram length
     int32_t hbits;        // Hash-q table bits
-    int32_t tiles_per_wg; // consecutive tiles processed by one workgroup
+    int32_t tiles_per_wg; // consecutive tiles per workgroup (count kernel)
     uint64_t m;
 };
 
-// Workspace layout (offsets in bytes from the workspace base).
+// Workspace layout (offsets in bytes from the workspace base):
+// [Params][pattern][tile_cnt u32][tile_off u64][list u32][nlist u64][stash u16 x STASH_K per tile]
 struct WsLayout {
-    uint64_t params;    // Params + pattern
-    uint64_t tile_cnt;  // uint32_t[ntiles]
-    uint64_t tile_off;  // uint64_t[ntiles]
-    uint64_t total;     // bytes
+    uint64_t params, pat, tile_cnt, tile_off, list, nlist, stash;
+    uint64_t need;     // minimum workspace size for find_all (count needs only params + pat)
     uint64_t ntiles;
 };
 
@@ -69,29 +72,49 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
 {
     WsLayout w;
     w.ntiles = num_tiles(n, m, tile);
-    w.params = 0;
-    uint64_t o = align_up(sizeof(Params) + align_up(m, 16) + 64, 256);
+    uint64_t o = 0;
+    w.params = o;
+    o = align_up(o + sizeof(Params), 256);
+    w.pat = o;
+    o = align_up(o + m + 64, 256);
     w.tile_cnt = o;
     o = align_up(o + 4 * w.ntiles, 256);
     w.tile_off = o;
     o = align_up(o + 8 * w.ntiles, 256);
-    w.total = o;
+    w.list = o;
+    o = align_up(o + 4 * w.ntiles, 256);
+    w.nlist = o;
+    o = align_up(o + 8, 256);
+    w.stash = o;
+    o = align_up(o + 2ull * STASH_K * w.ntiles, 256);
+    w.need = o;
     return w;
 }
 
+// Device pointers of the find_all workspace.
+struct FindWs {
+    uint32_t *tile_cnt;
+    uint64_t *tile_off;
+    uint32_t *list;
+    uint64_t *nlist;
+    uint16_t *stash;
+    uint64_t ntiles;
+};
+
 // Kernel launchers (sm_kernels.hip). All are asynchronous on `stream` and
 // return the HIP error of the launch.
+// Builds the pattern's tables in d_params; zeroes *d_zero when not null.
 hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_params,
                        uint8_t *d_pat, uint64_t *d_zero, hipStream_t stream);
+// sum of occurrences -> *d_total (zeroed by the prep kernel)
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n,
-                        const Params *d_params, const uint8_t *d_pat, uint32_t *d_tile_cnt,
-                        uint64_t *d_total, uint64_t ntiles, hipStream_t stream);
-hipError_t launch_scan(const uint32_t *d_tile_cnt, uint64_t ntiles, uint64_t *d_tile_off,
-                       uint64_t *d_total, hipStream_t stream);
-hipError_t launch_write(const Plan &plan, const uint8_t *d_text, uint64_t n,
-                        const Params *d_params, const uint8_t *d_pat,
-                        const uint32_t *d_tile_cnt, const uint64_t *d_tile_off, int64_t *d_out,
-                        uint64_t cap, uint64_t ntiles, hipStream_t stream);
+                        const Params *d_params, const uint8_t *d_pat, uint64_t *d_total,
+                        uint64_t ntiles, hipStream_t stream);
+// count -> scan -> emit: positions -> d_out[0 .. min(total, cap)), total -> *d_total.
+// `after_count` (may be null) is recorded after the count kernel.
+hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
+                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t cap,
+                       uint64_t *d_total, hipStream_t stream, hipEvent_t after_count);
 hipError_t launch_set_u64(uint64_t *d_dst, uint64_t value, hipStream_t stream);
 hipError_t launch_histogram(const uint8_t *d_text, uint64_t n, uint64_t *d_hist256,
                             hipStream_t stream);

@@ -18,15 +18,26 @@
 //     length of the non-factor suffix (SBNDM).
 //   * Hash-q (Fig. 1, HASHq): Horspool-style skip on the hash of the q-gram that
 //     ends the window; a zero shift triggers byte-exact verification.
-// Every lane produces its hits in ascending order; lane counts are combined by a
-// workgroup scan, and tiles by the tile-count scan, so positions land in the
-// output sorted and deterministically (count -> scan -> write).
+// Every lane produces its hits in ascending order. find_all is three launches
+// with no waiting between workgroups:
+//   count: one pass over the text from HBM; per-tile hit counts, and for a tile
+//          with at most STASH_K hits, the hits' offsets in the tile (u16) are
+//          kept in a per-tile stash;
+//   scan:  exclusive scan of the tile counts (tile output offsets, total) and
+//          the ascending list of tiles that have hits;
+//   emit:  for each listed tile, positions are written at the tile's offset,
+//          from the stash, or -- for tiles with more than STASH_K hits -- by
+//          rescanning the tile.
+// Positions land sorted and deterministically (count -> scan -> write).
 //
 // Bounds. Only starts i <= n - m are ever reported, and every window that is
 // reported reads bytes < n only. LDS bytes beyond the text are never consulted
 // for a reported position. Global loads are 16-byte aligned blocks that contain
 // at least one byte of the text, so they never leave the text's pages.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
+
 #include "sm_internal.h"
 
 namespace sm {
@@ -110,28 +121,46 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
 // per-lane sequential readers (conflict-free 16-byte LDS reads at any segment
 // stride that is a power of two >= 16).
 // ---------------------------------------------------------------------------
-template <bool SWZ>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool SWZ, int PER>
 __device__ __forceinline__ int stage(uint4 *lds, const uint8_t *text, uint64_t x0, uint64_t x1)
 {
     const uintptr_t a0 = (uintptr_t)(text + x0);
     const uintptr_t c0 = a0 & ~(uintptr_t)15;
     const uintptr_t c1 = ((uintptr_t)(text + x1 - 1)) & ~(uintptr_t)15;
     const uint32_t nch = (uint32_t)((c1 - c0) >> 4) + 1;
-    const uint4 *src = reinterpret_cast<const uint4 *>(c0);
-    for (uint32_t u = threadIdx.x; u < nch; u += BLOCK) {
-        uint4 v = src[u];
-        lds[SWZ ? swz(u) : u] = v;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(c0);
+    u32x4 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const uint32_t u = threadIdx.x + BLOCK * k;
+        if (u < nch) v[k] = __builtin_nontemporal_load(src + u);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const uint32_t u = threadIdx.x + BLOCK * k;
+        if (u < nch) {
+            uint4 w;
+            w.x = v[k].x;
+            w.y = v[k].y;
+            w.z = v[k].z;
+            w.w = v[k].w;
+            lds[SWZ ? swz(u) : u] = w;
+        }
     }
     return (int)(a0 & 15);
 }
 
 // ---------------------------------------------------------------------------
-// Lane scanners. Coordinates are relative to the tile start s. A lane owns
-// starts [lo, hi] (hi >= lo). `li0` is the LDS byte index of relative position 0.
-// WRITE=false: return the number of hits. WRITE=true: write each hit's global
-// position at out[idx++] while idx < cap.
+// Emitters: where a lane's hits go.
 // ---------------------------------------------------------------------------
-struct Out {
+struct NoEmit {
+    __device__ __forceinline__ void put(int) {}
+};
+
+// int64 global positions, bounded by cap
+struct PosEmit {
     int64_t *out;
     uint64_t idx, cap;
     uint64_t base;  // global position of relative position 0
@@ -142,11 +171,18 @@ struct Out {
     }
 };
 
+// u16 offsets inside the tile (tile-local stash)
+struct StashEmit {
+    uint16_t *dst;
+    uint32_t idx;
+    __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+};
+
 // Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
 // hit checks (requires m - 1 + CHECK <= bits of W).
-template <typename W, int CHECK, bool WRITE>
+template <typename W, int CHECK, bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *mask, int m, int li0,
-                                                  int lo, int hi, Out &o)
+                                                  int lo, int hi, E &o)
 {
     const int e_lo = lo + m - 1, e_hi = hi + m - 1;  // relative ends owned by this lane
     const int u0 = (lo + li0) >> 4, u1 = (e_hi + li0) >> 4;
@@ -190,9 +226,9 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *ma
 }
 
 // BNDM: masks B[c] bit i set iff p[m-1-i] == c.
-template <bool WRITE>
+template <bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_t *B, int m,
-                                             int li0, int lo, int hi, Out &o)
+                                             int li0, int lo, int hi, E &o)
 {
     const uint64_t HB = 1ull << (m - 1);
     const uint64_t ALL = ~0ull >> (64 - m);
@@ -222,9 +258,9 @@ __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_
 
 // SBNDM: same masks; no prefix tracking; shift m-k+1 when the k-byte suffix is
 // not a factor of p; after a hit, shift by the smallest period of p.
-template <bool WRITE>
+template <bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_sbndm(const uint8_t *lds8, const uint64_t *B, int m,
-                                              int period, int li0, int lo, int hi, Out &o)
+                                              int period, int li0, int lo, int hi, E &o)
 {
     const uint64_t HB = 1ull << (m - 1);
     uint32_t cnt = 0;
@@ -272,11 +308,11 @@ __device__ __noinline__ bool verify_global(const uint8_t *text, uint64_t gpos, c
 
 // Hash-q over the lane's windows. The LDS holds text positions from m-q on;
 // li0 is the LDS index of relative position 0 (may be negative).
-template <int NW, bool WRITE>
+template <int NW, bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint8_t *shift, int m,
                                               int q, int hbits, int sh1, int li0, int lo, int hi,
                                               const uint8_t *text, uint64_t s, const uint8_t *pat,
-                                              Out &o)
+                                              E &o)
 {
     uint32_t cnt = 0;
     int pos = lo;
@@ -304,8 +340,7 @@ __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint
 }
 
 // ---------------------------------------------------------------------------
-// Scan kernel: COUNT (WRITE=false) writes per-tile counts and adds them to the
-// total; WRITE=true re-scans tiles with hits and writes their positions.
+// Tiles
 // ---------------------------------------------------------------------------
 struct ScanArgs {
     const uint8_t *text;
@@ -314,9 +349,12 @@ struct ScanArgs {
     const uint8_t *pat;
     uint32_t m, q, hbits, tiles_per_wg;
     uint64_t ntiles;
-    uint32_t *tile_cnt;
-    const uint64_t *tile_off;
-    uint64_t *total;
+    uint64_t *total;      // count mode: occurrences are added here
+    uint32_t *tile_cnt;   // find mode: per-tile counts (count kernel writes, emit reads)
+    uint16_t *stash;      // find mode: STASH_K offsets per tile
+    const uint64_t *tile_off;  // emit: exclusive prefix of tile_cnt
+    const uint32_t *list;      // emit: tiles with hits, ascending
+    const uint64_t *nlist;     // emit: list length
     int64_t *out;
     uint64_t cap;
 };
@@ -328,136 +366,235 @@ struct Geometry {
     static constexpr int HALO = (ALGO == ALGO_HASHQ) ? (Q_MAX + 32) : (BP_MAX_M + 32);
     // whole groups of 8 chunks: the swizzle permutes chunks inside such groups
     static constexpr int CHUNKS = (((T + HALO + 15) / 16 + 1) + 7) & ~7;
+    static constexpr int PER = (CHUNKS + BLOCK - 1) / BLOCK;  // chunk loads per thread
 };
 
-template <int ALGO, int L, int VAR, bool WRITE>
-__global__ __launch_bounds__(BLOCK) void scan_kernel(ScanArgs a)
+template <int ALGO, int L>
+struct TileShared {
+    uint4 text[Geometry<ALGO, L>::CHUNKS];
+    uint64_t mask[(ALGO == ALGO_HASHQ) ? 1 : 256];
+    uint8_t shift[(ALGO == ALGO_HASHQ) ? (1 << H_MAX) : 1];
+    uint32_t w[BLOCK / 64];
+};
+
+// Tables into LDS (once per workgroup).
+template <int ALGO, int VAR>
+__device__ __forceinline__ void load_tables(const Params *prm, uint64_t *s_mask, uint8_t *s_shift,
+                                            uint32_t hbits)
 {
-    using G = Geometry<ALGO, L>;
-    constexpr int T = G::T;
-    __shared__ uint4 s_text[G::CHUNKS];
-    __shared__ uint64_t s_mask[(ALGO == ALGO_HASHQ) ? 1 : 256];
-    __shared__ uint8_t s_shift[(ALGO == ALGO_HASHQ) ? (1 << H_MAX) : 1];
-    __shared__ uint32_t s_w[BLOCK / 64];
-
     const int tid = threadIdx.x;
-    const int m = (int)a.m;
-
-    // tables: once per workgroup
     if (ALGO == ALGO_HASHQ) {
-        const uint32_t nb = 1u << a.hbits;
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.prm->shift);
+        const uint32_t nb = 1u << hbits;
+        const uint4 *src = reinterpret_cast<const uint4 *>(prm->shift);
         for (uint32_t k = tid; k < nb / 16; k += BLOCK) reinterpret_cast<uint4 *>(s_shift)[k] = src[k];
     } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
-        reinterpret_cast<uint32_t *>(s_mask)[tid] = (uint32_t)a.prm->mask[tid];
+        reinterpret_cast<uint32_t *>(s_mask)[tid] = (uint32_t)prm->mask[tid];
     } else {
-        s_mask[tid] = a.prm->mask[tid];
+        s_mask[tid] = prm->mask[tid];
     }
+}
+
+// Stage tile t (t < ntiles) and return the lane's start range [lo, hi] (relative
+// to the tile start s) and the LDS index li0 of relative position 0.
+template <int ALGO, int L>
+__device__ __forceinline__ void stage_tile(TileShared<ALGO, L> &S, const ScanArgs &a, uint64_t t,
+                                           uint64_t &s, int &li0, int &lo, int &hi)
+{
+    using G = Geometry<ALGO, L>;
+    const int m = (int)a.m;
+    const uint64_t last_start = a.n - a.m;  // n >= m guaranteed by the host
+    s = t * (uint64_t)G::T;
+    const uint64_t lim = last_start - s;    // >= 0 since t < ntiles
+    const int hi_rel = lim >= (uint64_t)(G::T - 1) ? G::T - 1 : (int)lim;
+    const uint64_t r0 = (ALGO == ALGO_HASHQ) ? (uint64_t)(m - (int)a.q) : 0;
+    const uint64_t x0 = s + r0;
+    uint64_t x1 = s + (uint64_t)hi_rel + a.m;  // one past the last byte any window reads
+    if (x1 > a.n) x1 = a.n;
+    const int boff = stage<ALGO == ALGO_SHIFT_AND, G::PER>(S.text, a.text, x0, x1);
+    li0 = boff - (int)r0;
+    lo = threadIdx.x * L;
+    hi = (lo + L - 1) < hi_rel ? (lo + L - 1) : hi_rel;
+}
+
+template <int ALGO, int L, int VAR, bool WRITE, class E>
+__device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanArgs &a, int m,
+                                             int sh1, int period, uint64_t s, int li0, int lo,
+                                             int hi, E &o)
+{
+    if (lo > hi) return 0u;
+    if (ALGO == ALGO_SHIFT_AND) {
+        if (VAR == 0)
+            return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
+                                                       m, li0, lo, hi, o);
+        if (VAR == 1) return lane_shift_and<uint64_t, 16, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
+        if (VAR == 2) return lane_shift_and<uint64_t, 4, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
+        return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
+    } else if (ALGO == ALGO_BNDM) {
+        return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
+    } else if (ALGO == ALGO_SBNDM) {
+        return lane_sbndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
+                                 lo, hi, o);
+    } else {
+        return lane_hashq<VAR, WRITE>(reinterpret_cast<const uint32_t *>(S.text), S.shift, m,
+                                      (int)a.q, (int)a.hbits, sh1, li0, lo, hi, a.text, s, a.pat, o);
+    }
+}
+
+// Count kernel. FIND=false: occurrences are added to *total. FIND=true: per-tile
+// counts go to tile_cnt, and tiles with 1..STASH_K hits stash their offsets.
+template <int ALGO, int L, int VAR, bool FIND>
+__global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
+{
+    __shared__ TileShared<ALGO, L> S;
+    const int m = (int)a.m;
+    load_tables<ALGO, VAR>(a.prm, S.mask, S.shift, a.hbits);
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
 
-    const uint64_t nblk = gridDim.x;
-    const uint64_t g = xcd_remap(blockIdx.x, nblk);
+    const uint64_t g = xcd_remap(blockIdx.x, gridDim.x);
     const uint64_t t_begin = g * a.tiles_per_wg;
     uint64_t t_end = t_begin + a.tiles_per_wg;
     if (t_end > a.ntiles) t_end = a.ntiles;
-
-    const uint64_t last_start = a.n - a.m;  // n >= m guaranteed by the host
-
+    uint32_t acc = 0;
     for (uint64_t t = t_begin; t < t_end; t++) {
-        uint64_t out_base = 0;
-        if (WRITE) {
-            const uint32_t tc = a.tile_cnt[t];
-            out_base = a.tile_off[t];
-            if (tc == 0 || out_base >= a.cap) continue;  // uniform over the workgroup
-        }
-        const uint64_t s = t * (uint64_t)T;
-        const uint64_t lim = last_start - s;  // >= 0 since t < ntiles
-        const int hi_rel = lim >= (uint64_t)(T - 1) ? T - 1 : (int)lim;
-
-        // staged span [x0, x1)
-        const uint64_t r0 = (ALGO == ALGO_HASHQ) ? (uint64_t)(m - (int)a.q) : 0;
-        const uint64_t x0 = s + r0;
-        uint64_t x1 = s + (uint64_t)hi_rel + a.m;  // one past the last byte any window reads
-        if (x1 > a.n) x1 = a.n;
-
+        uint64_t s;
+        int li0, lo, hi;
         __syncthreads();  // previous tile's LDS readers are done
-        const int boff = stage<ALGO == ALGO_SHIFT_AND>(s_text, a.text, x0, x1);
+        stage_tile<ALGO, L>(S, a, t, s, li0, lo, hi);
         __syncthreads();
-
-        // LDS byte index of relative position 0
-        const int li0 = boff - (int)r0;
-        const int lo = tid * L;
-        const int hi = (lo + L - 1) < hi_rel ? (lo + L - 1) : hi_rel;
-
-        Out o;
-        o.out = a.out;
-        o.cap = a.cap;
-        o.base = s;
-        o.idx = 0;
-
-
-        uint32_t c = 0;
-        if (ALGO == ALGO_SHIFT_AND) {
-            if (lo <= hi) {
-                if (VAR == 0) {
-                    // 32-bit state, check every 16 bytes: m <= 17
-                    const uint32_t *msk = reinterpret_cast<const uint32_t *>(s_mask);
-                    c = lane_shift_and<uint32_t, 16, false>(s_text, msk, m, li0, lo, hi, o);
-                } else if (VAR == 1) {
-                    c = lane_shift_and<uint64_t, 16, false>(s_text, s_mask, m, li0, lo, hi, o);
-                } else if (VAR == 2) {
-                    c = lane_shift_and<uint64_t, 4, false>(s_text, s_mask, m, li0, lo, hi, o);
-                } else {
-                    c = lane_shift_and<uint64_t, 1, false>(s_text, s_mask, m, li0, lo, hi, o);
-                }
-            }
-        } else if (ALGO == ALGO_BNDM) {
-            if (lo <= hi) c = lane_bndm<false>((const uint8_t *)s_text, s_mask, m, li0, lo, hi, o);
-        } else if (ALGO == ALGO_SBNDM) {
-            if (lo <= hi)
-                c = lane_sbndm<false>((const uint8_t *)s_text, s_mask, m, period, li0, lo, hi, o);
-        } else {
-            if (lo <= hi)
-                c = lane_hashq<VAR, false>((const uint32_t *)s_text, s_shift, m, (int)a.q,
-                                           (int)a.hbits, sh1, li0, lo, hi, a.text, s, a.pat, o);
+        NoEmit ne;
+        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, s, li0, lo, hi, ne);
+        if (!FIND) {
+            acc += c;
+            continue;
         }
+        uint32_t tot;
+        const uint32_t before = block_excl_scan(c, S.w, tot);
+        if (threadIdx.x == 0) a.tile_cnt[t] = tot;
+        if (c && tot <= STASH_K) {
+            StashEmit se;
+            se.dst = a.stash + t * STASH_K;
+            se.idx = before;
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, s, li0, lo, hi, se);
+        }
+    }
+    if (!FIND) {
+        uint32_t tot;
+        block_excl_scan(acc, S.w, tot);
+        if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)a.total, (unsigned long long)tot);
+    }
+}
 
-        if (!WRITE) {
-            uint32_t tot;
-            block_excl_scan(c, s_w, tot);
-            if (tid == 0) {
-                a.tile_cnt[t] = tot;
-                if (tot) atomicAdd((unsigned long long *)a.total, (unsigned long long)tot);
-            }
-        } else {
-            uint32_t tot;
-            const uint32_t before = block_excl_scan(c, s_w, tot);
-            if (c) {
-                o.idx = out_base + before;
-                if (o.idx < a.cap) {
-                    if (ALGO == ALGO_SHIFT_AND) {
-                        if (VAR == 0) {
-                            const uint32_t *msk = reinterpret_cast<const uint32_t *>(s_mask);
-                            lane_shift_and<uint32_t, 16, true>(s_text, msk, m, li0, lo, hi, o);
-                        } else if (VAR == 1) {
-                            lane_shift_and<uint64_t, 16, true>(s_text, s_mask, m, li0, lo, hi, o);
-                        } else if (VAR == 2) {
-                            lane_shift_and<uint64_t, 4, true>(s_text, s_mask, m, li0, lo, hi, o);
-                        } else {
-                            lane_shift_and<uint64_t, 1, true>(s_text, s_mask, m, li0, lo, hi, o);
-                        }
-                    } else if (ALGO == ALGO_BNDM) {
-                        lane_bndm<true>((const uint8_t *)s_text, s_mask, m, li0, lo, hi, o);
-                    } else if (ALGO == ALGO_SBNDM) {
-                        lane_sbndm<true>((const uint8_t *)s_text, s_mask, m, period, li0, lo, hi, o);
-                    } else {
-                        lane_hashq<VAR, true>((const uint32_t *)s_text, s_shift, m, (int)a.q,
-                                              (int)a.hbits, sh1, li0, lo, hi, a.text, s, a.pat, o);
-                    }
-                }
+// Emit kernel: positions of the listed tiles, at their offsets, bounded by cap.
+template <int ALGO, int L, int VAR>
+__global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
+{
+    __shared__ TileShared<ALGO, L> S;
+    const int m = (int)a.m;
+    const uint64_t nl = *a.nlist;
+    if ((uint64_t)blockIdx.x >= nl) return;
+    bool tables = false;
+    const int sh1 = (int)a.prm->sh1;
+    const int period = (int)a.prm->period;
+    for (uint64_t e = blockIdx.x; e < nl; e += gridDim.x) {
+        const uint64_t t = a.list[e];
+        const uint32_t tot = a.tile_cnt[t];
+        const uint64_t off = a.tile_off[t];
+        if (off >= a.cap) continue;  // uniform over the workgroup
+        const uint64_t s = t * (uint64_t)Geometry<ALGO, L>::T;
+        if (tot <= STASH_K) {
+            const uint16_t *src = a.stash + t * STASH_K;
+            for (uint32_t k = threadIdx.x; k < tot; k += BLOCK)
+                if (off + k < a.cap) a.out[off + k] = (int64_t)(s + src[k]);
+            continue;
+        }
+        if (!tables) {
+            load_tables<ALGO, VAR>(a.prm, S.mask, S.shift, a.hbits);
+            tables = true;
+        }
+        uint64_t s2;
+        int li0, lo, hi;
+        __syncthreads();
+        stage_tile<ALGO, L>(S, a, t, s2, li0, lo, hi);
+        __syncthreads();
+        NoEmit ne;
+        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, s2, li0, lo, hi, ne);
+        uint32_t tt;
+        const uint32_t before = block_excl_scan(c, S.w, tt);
+        if (c && off + before < a.cap) {
+            PosEmit pe;
+            pe.out = a.out;
+            pe.cap = a.cap;
+            pe.base = s2;
+            pe.idx = off + before;
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, s2, li0, lo, hi, pe);
+        }
+    }
+}
+
+// Tile-count scan: one workgroup of 1024 threads, coalesced 4-count loads.
+// Writes exclusive offsets, the total and the ascending list of tiles with hits.
+__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint64_t nt,
+                                                         uint64_t *off, uint64_t *total,
+                                                         uint32_t *list, uint64_t *nlist)
+{
+    __shared__ uint64_t s_sum[16];
+    __shared__ uint32_t s_nz[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t run = 0;     // occurrences before this chunk
+    uint64_t nrun = 0;    // listed tiles before this chunk
+    for (uint64_t base = 0; base < nt; base += 4096) {
+        uint32_t c[4];
+        const uint64_t i0 = base + 4 * (uint64_t)tid;
+#pragma unroll
+        for (int k = 0; k < 4; k++) c[k] = (i0 + k < nt) ? cnt[i0 + k] : 0u;
+        uint64_t my = (uint64_t)c[0] + c[1] + c[2] + c[3];
+        uint32_t nz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0) + (c[3] != 0);
+        // wave inclusive scans
+        uint64_t incl = my;
+        uint32_t nzi = nz;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t o = __shfl_up(incl, d, 64);
+            const uint32_t p = __shfl_up(nzi, d, 64);
+            if (lane >= d) {
+                incl += o;
+                nzi += p;
             }
         }
+        if (lane == 63) {
+            s_sum[wv] = incl;
+            s_nz[wv] = nzi;
+        }
+        __syncthreads();
+        uint64_t wbefore = 0, ctot = 0;
+        uint32_t zbefore = 0, ztot = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const uint64_t x = s_sum[k];
+            const uint32_t z = s_nz[k];
+            wbefore += (k < wv) ? x : 0;
+            zbefore += (k < wv) ? z : 0;
+            ctot += x;
+            ztot += z;
+        }
+        __syncthreads();
+        uint64_t o = run + wbefore + incl - my;
+        uint64_t zpos = nrun + zbefore + nzi - nz;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i0 + k < nt) {
+                off[i0 + k] = o;
+                if (c[k]) list[zpos++] = (uint32_t)(i0 + k);
+            }
+            o += c[k];
+        }
+        run += ctot;
+        nrun += ztot;
+    }
+    if (tid == 0) {
+        *total = run;
+        *nlist = nrun;
     }
 }
 
@@ -554,36 +691,6 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Tile-count scan (single workgroup of 1024 threads) -> exclusive offsets, total.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint64_t nt,
-                                                         uint64_t *off, uint64_t *total)
-{
-    __shared__ uint64_t s_part[1024];
-    const uint64_t per = (nt + 1023) / 1024;
-    const uint64_t b = threadIdx.x * per;
-    uint64_t e = b + per;
-    if (e > nt) e = nt;
-    uint64_t sum = 0;
-    for (uint64_t k = b; k < e; k++) sum += cnt[k];
-    s_part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over 1024 partial sums
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint64_t v = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0;
-        __syncthreads();
-        s_part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint64_t run = s_part[threadIdx.x] - sum;
-    for (uint64_t k = b; k < e; k++) {
-        off[k] = run;
-        run += cnt[k];
-    }
-    if (threadIdx.x == 1023) *total = s_part[1023];
-}
-
 __global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }
 
 // 256-bin byte histogram (alphabet probe).
@@ -602,50 +709,78 @@ __global__ __launch_bounds__(BLOCK) void hist_kernel(const uint8_t *text, uint64
 // ---------------------------------------------------------------------------
 // dispatch helpers
 // ---------------------------------------------------------------------------
-template <int ALGO, int L, int VAR, bool WRITE>
-hipError_t launch_scan_t(const Plan &p, const ScanArgs &a, hipStream_t st)
+enum Kind { K_COUNT, K_FIND_COUNT, K_EMIT };
+
+template <int ALGO, int L, int VAR, int KIND>
+hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
 {
-    const uint64_t nblk = (a.ntiles + a.tiles_per_wg - 1) / a.tiles_per_wg;
-    if (nblk == 0) return hipSuccess;
-    if (nblk > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((scan_kernel<ALGO, L, VAR, WRITE>), dim3((uint32_t)nblk), dim3(BLOCK), 0, st, a);
+    if (grid == 0) return hipSuccess;
+    if (KIND == K_COUNT)
+        hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    else if (KIND == K_FIND_COUNT)
+        hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+    else
+        hipLaunchKernelGGL((emit_kernel<ALGO, L, VAR>), dim3(grid), dim3(BLOCK), 0, st, a);
     return hipGetLastError();
 }
 
-template <int ALGO, int VAR, bool WRITE>
-hipError_t launch_scan_l(const Plan &p, const ScanArgs &a, hipStream_t st)
+template <int ALGO, int VAR, int KIND>
+hipError_t launch_l(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream_t st)
 {
     switch (p.lane_bytes) {
-    case 16: return launch_scan_t<ALGO, 16, VAR, WRITE>(p, a, st);
-    case 32: return launch_scan_t<ALGO, 32, VAR, WRITE>(p, a, st);
-    case 64: return launch_scan_t<ALGO, 64, VAR, WRITE>(p, a, st);
-    case 128: return launch_scan_t<ALGO, 128, VAR, WRITE>(p, a, st);
+    case 16: return launch_t<ALGO, 16, VAR, KIND>(a, grid, st);
+    case 32: return launch_t<ALGO, 32, VAR, KIND>(a, grid, st);
+    case 64: return launch_t<ALGO, 64, VAR, KIND>(a, grid, st);
+    case 128: return launch_t<ALGO, 128, VAR, KIND>(a, grid, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <bool WRITE>
-hipError_t launch_scan_any(const Plan &p, const ScanArgs &a, hipStream_t st)
+template <int KIND>
+hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream_t st)
 {
     switch (p.algo) {
     case ALGO_SHIFT_AND: {
         const int m = (int)p.m;
-        if (m <= 17) return launch_scan_l<ALGO_SHIFT_AND, 0, WRITE>(p, a, st);
-        if (m <= 49) return launch_scan_l<ALGO_SHIFT_AND, 1, WRITE>(p, a, st);
-        if (m <= 61) return launch_scan_l<ALGO_SHIFT_AND, 2, WRITE>(p, a, st);
-        return launch_scan_l<ALGO_SHIFT_AND, 3, WRITE>(p, a, st);
+        if (m <= 17) return launch_l<ALGO_SHIFT_AND, 0, KIND>(p, a, grid, st);
+        if (m <= 49) return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
+        if (m <= 61) return launch_l<ALGO_SHIFT_AND, 2, KIND>(p, a, grid, st);
+        return launch_l<ALGO_SHIFT_AND, 3, KIND>(p, a, grid, st);
     }
-    case ALGO_BNDM: return launch_scan_l<ALGO_BNDM, 0, WRITE>(p, a, st);
-    case ALGO_SBNDM: return launch_scan_l<ALGO_SBNDM, 0, WRITE>(p, a, st);
+    case ALGO_BNDM: return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
+    case ALGO_SBNDM: return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);
     case ALGO_HASHQ: {
         const int nw = (p.q + 3) / 4;
-        if (nw <= 1) return launch_scan_l<ALGO_HASHQ, 1, WRITE>(p, a, st);
-        if (nw == 2) return launch_scan_l<ALGO_HASHQ, 2, WRITE>(p, a, st);
-        if (nw == 3) return launch_scan_l<ALGO_HASHQ, 3, WRITE>(p, a, st);
-        return launch_scan_l<ALGO_HASHQ, 4, WRITE>(p, a, st);
+        if (nw <= 1) return launch_l<ALGO_HASHQ, 1, KIND>(p, a, grid, st);
+        if (nw == 2) return launch_l<ALGO_HASHQ, 2, KIND>(p, a, grid, st);
+        if (nw == 3) return launch_l<ALGO_HASHQ, 3, KIND>(p, a, grid, st);
+        return launch_l<ALGO_HASHQ, 4, KIND>(p, a, grid, st);
     }
     default: return hipErrorInvalidValue;
     }
+}
+
+ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
+                   const uint8_t *d_pat, uint64_t ntiles)
+{
+    ScanArgs a;
+    memset(&a, 0, sizeof a);
+    a.text = d_text;
+    a.n = n;
+    a.prm = d_params;
+    a.pat = d_pat;
+    a.m = (uint32_t)plan.m;
+    a.q = (uint32_t)plan.q;
+    a.hbits = (uint32_t)plan.hbits;
+    a.tiles_per_wg = (uint32_t)plan.tiles_per_wg;
+    a.ntiles = ntiles;
+    return a;
+}
+
+uint32_t count_grid(const ScanArgs &a)
+{
+    const uint64_t nblk = (a.ntiles + a.tiles_per_wg - 1) / a.tiles_per_wg;
+    return nblk > 0x7FFFFFFFull ? 0u : (uint32_t)nblk;
 }
 
 }  // namespace
@@ -678,58 +813,45 @@ hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_para
     return hipGetLastError();
 }
 
-static ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                          const uint8_t *d_pat, uint64_t ntiles)
-{
-    ScanArgs a;
-    a.text = d_text;
-    a.n = n;
-    a.prm = d_params;
-    a.pat = d_pat;
-    a.m = (uint32_t)plan.m;
-    a.q = (uint32_t)plan.q;
-    a.hbits = (uint32_t)plan.hbits;
-    a.tiles_per_wg = (uint32_t)plan.tiles_per_wg;
-    a.ntiles = ntiles;
-    a.tile_cnt = nullptr;
-    a.tile_off = nullptr;
-    a.total = nullptr;
-    a.out = nullptr;
-    a.cap = 0;
-    return a;
-}
-
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                        const uint8_t *d_pat, uint32_t *d_tile_cnt, uint64_t *d_total,
-                        uint64_t ntiles, hipStream_t stream)
+                        const uint8_t *d_pat, uint64_t *d_total, uint64_t ntiles, hipStream_t stream)
 {
     ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, ntiles);
-    a.tile_cnt = d_tile_cnt;
     a.total = d_total;
-    return launch_scan_any<false>(plan, a, stream);
+    const uint32_t g = count_grid(a);
+    if (ntiles && !g) return hipErrorInvalidValue;
+    return launch_any<K_COUNT>(plan, a, g, stream);
 }
 
-hipError_t launch_scan(const uint32_t *d_tile_cnt, uint64_t ntiles, uint64_t *d_tile_off,
-                       uint64_t *d_total, hipStream_t stream)
+hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
+                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t cap,
+                       uint64_t *d_total, hipStream_t stream, hipEvent_t after_count)
 {
-    if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, stream, d_tile_cnt, ntiles,
-                       d_tile_off, d_total);
-    return hipGetLastError();
-}
-
-hipError_t launch_write(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                        const uint8_t *d_pat, const uint32_t *d_tile_cnt,
-                        const uint64_t *d_tile_off, int64_t *d_out, uint64_t cap, uint64_t ntiles,
-                        hipStream_t stream)
-{
-    if (cap == 0) return hipSuccess;
-    ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, ntiles);
-    a.tile_cnt = const_cast<uint32_t *>(d_tile_cnt);
-    a.tile_off = d_tile_off;
+    if (w.ntiles == 0) return hipSuccess;
+    if (w.ntiles > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, w.ntiles);
+    a.tile_cnt = w.tile_cnt;
+    a.stash = w.stash;
+    a.tile_off = w.tile_off;
+    a.list = w.list;
+    a.nlist = w.nlist;
     a.out = d_out;
     a.cap = cap;
-    return launch_scan_any<true>(plan, a, stream);
+    const uint32_t g = count_grid(a);
+    if (!g) return hipErrorInvalidValue;
+    hipError_t e = launch_any<K_FIND_COUNT>(plan, a, g, stream);
+    if (e != hipSuccess) return e;
+    if (after_count) {
+        e = hipEventRecord(after_count, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, stream, w.tile_cnt, w.ntiles,
+                       w.tile_off, d_total, w.list, w.nlist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (cap == 0) return hipSuccess;
+    uint64_t eg = w.ntiles < EMIT_GRID ? w.ntiles : EMIT_GRID;
+    return launch_any<K_EMIT>(plan, a, (uint32_t)eg, stream);
 }
 
 hipError_t launch_set_u64(uint64_t *d_dst, uint64_t value, hipStream_t stream)

@@ -238,3 +238,33 @@ def test_device_sync_paths(sm):
         got = sm.find_all(t_dev, p).cpu().numpy()
         assert np.array_equal(got, want), m
         assert sm.count(t_dev, p) == want.size
+
+
+def test_workspace_reuse_across_calls(sm):
+    """One workspace, many calls with varying n, m, algorithm and workspace size:
+    nothing left in the workspace by earlier calls may leak into later ones."""
+    rng = np.random.default_rng(5)
+    big = torch.empty(sm.workspace_size(1 << 19, 4096) + (1 << 16), dtype=torch.uint8, device=DEV)
+    base_np = dg.uniform_text(1 << 19, 4, seed=77)
+    base = torch.from_numpy(base_np).to(DEV)
+    for i in range(400):
+        n = int(rng.integers(1, 1 << 19))
+        m = int(rng.integers(1, 1200)) if i % 3 else int(rng.integers(1, 20))
+        if m > n:
+            m = n
+        algo = int(rng.choice([1, 2, 3, 4])) if m <= 64 else 4
+        o = sm.opts(algo=algo, lane_bytes=int(rng.choice([16, 64])))
+        need = sm.workspace_size(n, m, o)
+        work = big[:need + int(rng.integers(0, 1 << 16)) // 256 * 256]
+        t_np = base_np[:n]
+        if rng.random() < 0.7:
+            r = int(rng.integers(0, n - m + 1))
+            p = bytes(t_np[r:r + m])
+        else:
+            p = bytes(rng.integers(0, 4, m, dtype=np.uint8))
+        want = oracle.find_all(t_np, p)
+        out = torch.empty(max(want.size, 1), dtype=torch.int64, device=DEV)
+        dc = torch.zeros(1, dtype=torch.int64, device=DEV)
+        sm.find_all_async(base[:n], p, out[:want.size], dc, work, o)
+        assert int(dc.item()) == want.size, (i, n, m, algo)
+        assert np.array_equal(out[:want.size].cpu().numpy(), want), (i, n, m, algo)
