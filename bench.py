@@ -98,12 +98,17 @@ def main():
                             for j in range(args.per_cell)]
     log("inputs ready in %.1fs" % (time.time() - t0))
 
+    # corpora: device-resident texts with their byte histogram probed once; the
+    # planner uses each corpus's measured effective alphabet size
+    corpora = {s: sm.Corpus(dev_texts[s]) for s in SIGMAS}
+    sigma_eff = {s: round(corpora[s].stats()[2], 2) for s in SIGMAS}
     calls = [(s, m, p) for s in SIGMAS for m in MS for p in pats[(s, m)]]
-    work = torch.empty(sm.workspace_size(n, 1024), dtype=torch.uint8, device=dev)
+    work = torch.empty(sm.workspace_size(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
+                       device=dev)
     counts_dev = torch.zeros(len(calls), dtype=torch.int64, device=dev)
     # exact counts (sizes the output buffer; checked after every step)
     for k, (s, m, p) in enumerate(calls):
-        sm.count_async(dev_texts[s], p, counts_dev[k:k + 1], work, None, stream)
+        corpora[s].count_async(p, counts_dev[k:k + 1], work, None, stream)
     torch.cuda.synchronize()
     expect = counts_dev.cpu().numpy().copy()
     cap = int(expect.max())
@@ -113,7 +118,7 @@ def main():
 
     def step():
         for k, (s, m, p) in enumerate(calls):
-            sm.find_all_async(dev_texts[s], p, out, counts_dev[k:k + 1], work, None, stream)
+            corpora[s].find_all_async(p, out, counts_dev[k:k + 1], work, None, stream)
 
     for _ in range(args.warmup):
         step()
@@ -161,7 +166,7 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
     ev[0].record(stream)
     for k, (s, m, p) in enumerate(calls):
-        sm.find_all_async(dev_texts[s], p, out, counts_dev[k:k + 1], work, None, stream)
+        corpora[s].find_all_async(p, out, counts_dev[k:k + 1], work, None, stream)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     for k, (s, m, p) in enumerate(calls):
@@ -181,7 +186,7 @@ def main():
             want = oracle.find_all(host_texts[s], p, threads=threads)
             g = torch.empty(max(want.size, 1), dtype=torch.int64, device=dev)
             dc = torch.zeros(1, dtype=torch.int64, device=dev)
-            sm.find_all_async(dev_texts[s], p, g, dc, work, None, stream)
+            corpora[s].find_all_async(p, g, dc, work, None, stream)
             torch.cuda.synchronize()
             if int(dc.item()) != want.size or not np.array_equal(g[:want.size].cpu().numpy(), want):
                 mismatches += 1
@@ -215,6 +220,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cells_median_gbs": cell_gbs,
+        "sigma_eff": sigma_eff,
     }
     print(json.dumps(res), flush=True)
 

@@ -129,6 +129,22 @@ int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64
                    uint64_t *d_count, void *d_work, uint64_t work_bytes, const sm_opts *opts,
                    void *stream);
 
+/*
+ * Planner tuning table. The planner picks the first entry whose alphabet-size
+ * range and pattern-length range contain (sigma, m); sigma is the corpus's
+ * sigma_eff, opts->sigma_hint, or an estimate from the pattern's byte counts.
+ * Zero fields mean "planner default". Entries whose algorithm cannot handle m
+ * are skipped. The library carries a table measured on MI355X (see the package's
+ * tune module); sm_tune_set replaces it (count = 0 restores it).
+ */
+typedef struct sm_tune_entry {
+    int32_t sigma_lo, sigma_hi;
+    uint32_t m_lo, m_hi;
+    int32_t algo, lane_bytes, q, tiles_per_wg, hbits, reserved;
+} sm_tune_entry;
+int sm_tune_set(const sm_tune_entry *entries, uint32_t count);
+int sm_tune_get(sm_tune_entry *entries, uint32_t cap, uint32_t *count);
+
 /* Planner introspection: the plan a call with these arguments would use. The
  * pattern is read on the host only (its byte statistics inform the planner). */
 int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_info *info);
@@ -148,8 +164,18 @@ int sm_corpus_close(sm_corpus *corpus);
 int sm_corpus_find_all(sm_corpus *corpus, const uint8_t *pat, uint64_t m, int64_t *out_pos,
                        uint64_t cap, uint64_t *count);
 int sm_corpus_count(sm_corpus *corpus, const uint8_t *pat, uint64_t m, uint64_t *count);
-/* histogram[256] (may be NULL) and effective alphabet size (number of distinct bytes) */
-int sm_corpus_stats(const sm_corpus *corpus, uint64_t *histogram, int32_t *sigma);
+/* histogram[256], number of distinct bytes (sigma) and the effective alphabet size
+ * sigma_eff = 1 / sum_c p_c^2 (the size of the uniform alphabet with the same
+ * probability that two random bytes are equal); any pointer may be NULL. */
+int sm_corpus_stats(const sm_corpus *corpus, uint64_t *histogram, int32_t *sigma,
+                    double *sigma_eff);
+/* Asynchronous corpus queries: as sm_find_all_async / sm_count_async on the
+ * corpus text, planned with the corpus's measured sigma_eff. */
+int sm_corpus_find_all_async(sm_corpus *corpus, const uint8_t *pat, uint64_t m, int64_t *d_out,
+                             uint64_t cap, uint64_t *d_count, void *d_work, uint64_t work_bytes,
+                             const sm_opts *opts, void *stream);
+int sm_corpus_count_async(sm_corpus *corpus, const uint8_t *pat, uint64_t m, uint64_t *d_count,
+                          void *d_work, uint64_t work_bytes, const sm_opts *opts, void *stream);
 /* device address of the corpus text and its length */
 int sm_corpus_text(const sm_corpus *corpus, const uint8_t **d_text, uint64_t *n);
 

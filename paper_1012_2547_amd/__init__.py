@@ -15,11 +15,11 @@ import ctypes
 import numpy as np
 
 from ._native import (ALGO_AUTO, ALGO_BNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
-                      ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError, check,
-                      last_error, load)
+                      ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError,
+                      TuneEntry, check, last_error, load)
 
 __all__ = ["find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
-           "Corpus", "opts", "prof_enable", "prof_collect", "SmError", "ALGO_AUTO",
+           "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
            "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version"]
 
 
@@ -185,11 +185,30 @@ class Corpus:
         except Exception:
             pass
 
-    def stats(self) -> tuple[np.ndarray, int]:
+    def stats(self) -> tuple[np.ndarray, int, float]:
+        """(byte histogram, distinct bytes, effective alphabet size 1/sum p^2)"""
         h = np.zeros(256, dtype=np.uint64)
         s = ctypes.c_int32(0)
-        check(load().sm_corpus_stats(self._h, ctypes.c_void_p(h.ctypes.data), ctypes.byref(s)))
-        return h, int(s.value)
+        se = ctypes.c_double(0)
+        check(load().sm_corpus_stats(self._h, ctypes.c_void_p(h.ctypes.data), ctypes.byref(s),
+                                     ctypes.byref(se)))
+        return h, int(s.value), float(se.value)
+
+    def find_all_async(self, pat, out, d_count, work, o: Opts | None = None, stream=None) -> int:
+        b, m = _pat(pat)
+        return check(load().sm_corpus_find_all_async(
+            self._h, _pat_ptr(b), m,
+            ctypes.c_void_p(out.data_ptr() if out is not None and out.numel() else 0),
+            out.numel() if out is not None else 0, ctypes.c_void_p(d_count.data_ptr()),
+            ctypes.c_void_p(work.data_ptr()), work.numel(),
+            ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+
+    def count_async(self, pat, d_count, work, o: Opts | None = None, stream=None) -> int:
+        b, m = _pat(pat)
+        return check(load().sm_corpus_count_async(
+            self._h, _pat_ptr(b), m, ctypes.c_void_p(d_count.data_ptr()),
+            ctypes.c_void_p(work.data_ptr()), work.numel(),
+            ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
 
     def count(self, pat) -> int:
         b, m = _pat(pat)
@@ -206,6 +225,26 @@ class Corpus:
         check(load().sm_corpus_find_all(self._h, _pat_ptr(b), m, ctypes.c_void_p(out.ctypes.data),
                                         cap, ctypes.byref(c)))
         return out[:min(int(c.value), cap)]
+
+
+def tune_get() -> list[dict]:
+    L = load()
+    n = ctypes.c_uint32(0)
+    check(L.sm_tune_get(None, 0, ctypes.byref(n)))
+    arr = (TuneEntry * max(n.value, 1))()
+    check(L.sm_tune_get(arr, n.value, ctypes.byref(n)))
+    keys = [f[0] for f in TuneEntry._fields_ if f[0] != "reserved"]
+    return [{k: getattr(arr[i], k) for k in keys} for i in range(n.value)]
+
+
+def tune_set(entries: list[dict]) -> None:
+    """Replace the planner's tuning table ([] restores the built-in table)."""
+    arr = (TuneEntry * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        for k, v in e.items():
+            if k in dict(TuneEntry._fields_):
+                setattr(arr[i], k, int(v))
+    check(load().sm_tune_set(arr, len(entries)))
 
 
 def prof_enable(on: bool = True) -> None:

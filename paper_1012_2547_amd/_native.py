@@ -34,6 +34,14 @@ class PlanInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("sigma_lo", ctypes.c_int32), ("sigma_hi", ctypes.c_int32),
+                ("m_lo", ctypes.c_uint32), ("m_hi", ctypes.c_uint32), ("algo", ctypes.c_int32),
+                ("lane_bytes", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("tiles_per_wg", ctypes.c_int32), ("hbits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Prof(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_uint64), ("count_ms", ctypes.c_double),
                 ("emit_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
@@ -59,7 +67,13 @@ PROTOTYPES = {
     "sm_corpus_close": (_i32, [_vp]),
     "sm_corpus_find_all": (_i32, [_vp, _vp, _u64, _vp, _u64, _pu64]),
     "sm_corpus_count": (_i32, [_vp, _vp, _u64, _pu64]),
-    "sm_corpus_stats": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]),
+    "sm_corpus_stats": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_double)]),
+    "sm_corpus_find_all_async": (_i32, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
+                                        ctypes.POINTER(Opts), _vp]),
+    "sm_corpus_count_async": (_i32, [_vp, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(Opts), _vp]),
+    "sm_tune_set": (_i32, [ctypes.POINTER(TuneEntry), _u32]),
+    "sm_tune_get": (_i32, [ctypes.POINTER(TuneEntry), _u32, ctypes.POINTER(ctypes.c_uint32)]),
     "sm_corpus_text": (_i32, [_vp, ctypes.POINTER(_vp), _pu64]),
     "sm_prof_enable": (_i32, [_i32]),
     "sm_prof_collect": (_i32, [ctypes.POINTER(Prof)]),

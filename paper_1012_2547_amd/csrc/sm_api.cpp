@@ -70,13 +70,25 @@ static int check_device()
 // ---------------------------------------------------------------------------
 // planner
 // ---------------------------------------------------------------------------
-static int distinct_bytes(const uint8_t *p, uint64_t m)
+// Effective alphabet size from the pattern alone: the sigma for which a random
+// text of that alphabet shows d distinct bytes in m draws, d the pattern's
+// distinct-byte count (sigma (1 - (1 - 1/sigma)^m) = d, solved by bisection).
+// m == d gives no upper bound: 256.
+static int sigma_from_pattern(const uint8_t *p, uint64_t m)
 {
     bool seen[256] = {false};
     int d = 0;
     for (uint64_t k = 0; k < m; k++)
         if (!seen[p[k]]) { seen[p[k]] = true; d++; }
-    return d;
+    if ((uint64_t)d >= m) return 256;
+    double lo = 1.0, hi = 256.0;
+    for (int it = 0; it < 40; it++) {
+        const double s = 0.5 * (lo + hi);
+        const double e = s * (1.0 - std::pow(1.0 - 1.0 / s, (double)m));
+        if (e < d) lo = s; else hi = s;
+    }
+    int s = (int)std::lround(0.5 * (lo + hi));
+    return s < 1 ? 1 : s;
 }
 
 // smallest q with sigma^q >= 64 * (m - q + 1): few pattern q-grams per q-gram space
@@ -103,6 +115,70 @@ static int choose_hbits(uint64_t m, int q)
     return std::min(H_MAX, std::max(H_MIN, b));
 }
 
+namespace {
+// Built-in tuning table, measured on MI355X by paper_1012_2547_amd/tune.py.
+const sm_tune_entry k_builtin_tune[] = {
+#include "tune_table.inc"
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+std::mutex g_tune_mu;
+std::vector<sm_tune_entry> g_tune;  // empty: the built-in table
+bool g_tune_custom = false;
+
+bool tune_lookup(int sigma, uint64_t m, sm_tune_entry &out)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const sm_tune_entry *e = g_tune_custom ? g_tune.data() : k_builtin_tune;
+    const size_t n = g_tune_custom ? g_tune.size() : sizeof(k_builtin_tune) / sizeof(k_builtin_tune[0]) - 1;
+    for (size_t k = 0; k < n; k++)
+        if (sigma >= e[k].sigma_lo && sigma <= e[k].sigma_hi && m >= e[k].m_lo && m <= e[k].m_hi) {
+            out = e[k];
+            return true;
+        }
+    return false;
+}
+}  // namespace
+
+// Smallest lane_bytes the planner may choose for a pattern of length m (any sigma).
+static int min_auto_lane(uint64_t m)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const sm_tune_entry *e = g_tune_custom ? g_tune.data() : k_builtin_tune;
+    const size_t n = g_tune_custom ? g_tune.size() : sizeof(k_builtin_tune) / sizeof(k_builtin_tune[0]) - 1;
+    int lane = AUTO_MIN_LANE;
+    for (size_t k = 0; k < n; k++)
+        if (m >= e[k].m_lo && m <= e[k].m_hi && e[k].lane_bytes && e[k].lane_bytes < lane)
+            lane = e[k].lane_bytes;
+    return lane;
+}
+
+extern "C" int sm_tune_set(const sm_tune_entry *entries, uint32_t count)
+{
+    if (count && !entries) return fail(SM_EINVAL, "entries is NULL");
+    for (uint32_t k = 0; k < count; k++) {
+        const sm_tune_entry &e = entries[k];
+        if (e.algo < ALGO_SHIFT_AND || e.algo >= ALGO_COUNT_ || e.m_lo > e.m_hi || e.sigma_lo > e.sigma_hi ||
+            (e.lane_bytes && e.lane_bytes != 16 && e.lane_bytes != 32 && e.lane_bytes != 64 && e.lane_bytes != 128) ||
+            e.q < 0 || e.q > Q_MAX || e.tiles_per_wg < 0 || e.tiles_per_wg > 4096 ||
+            (e.hbits && (e.hbits < H_MIN || e.hbits > H_MAX)))
+            return fail(SM_EINVAL, "invalid tuning entry %u", k);
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.assign(entries, entries + count);
+    g_tune_custom = count > 0;
+    return SM_OK;
+}
+
+extern "C" int sm_tune_get(sm_tune_entry *entries, uint32_t cap, uint32_t *count)
+{
+    if (!count || (cap && !entries)) return fail(SM_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const sm_tune_entry *e = g_tune_custom ? g_tune.data() : k_builtin_tune;
+    const size_t n = g_tune_custom ? g_tune.size() : sizeof(k_builtin_tune) / sizeof(k_builtin_tune[0]) - 1;
+    for (size_t k = 0; k < n && k < cap; k++) entries[k] = e[k];
+    *count = (uint32_t)n;
+    return SM_OK;
+}
+
 static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma_known, Plan &p)
 {
     sm_opts z;
@@ -118,29 +194,40 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
         return fail(SM_EINVAL, "hbits must be in [%d, %d]", H_MIN, H_MAX);
     if (o->tiles_per_wg < 0 || o->tiles_per_wg > 4096)
         return fail(SM_EINVAL, "tiles_per_wg must be in [1, 4096]");
-
-    int sigma = o->sigma_hint > 0 ? o->sigma_hint : sigma_known;
-    if (sigma <= 0) sigma = m >= 16 ? distinct_bytes(pat, m) : 256;
-
-    p.m = m;
-    p.algo = o->algo;
-    if (p.algo == ALGO_AUTO) {
-        if (m <= 12) p.algo = ALGO_SHIFT_AND;
-        else if (m <= BP_MAX_M) p.algo = ALGO_SBNDM;
-        else p.algo = ALGO_HASHQ;
-    }
-    if (p.algo != ALGO_HASHQ && m > BP_MAX_M)
+    if (o->algo != ALGO_AUTO && o->algo != ALGO_HASHQ && m > BP_MAX_M)
         return fail(SM_EINVAL, "bit-parallel algorithms need m <= %d (m = %llu)", BP_MAX_M,
                     (unsigned long long)m);
+    if (o->q && (uint64_t)o->q > m)
+        return fail(SM_EINVAL, "q = %d exceeds m = %llu", o->q, (unsigned long long)m);
+
+    int sigma = o->sigma_hint > 0 ? o->sigma_hint : sigma_known;
+    if (sigma <= 0) sigma = sigma_from_pattern(pat, m);
+    if (sigma > 256) sigma = 256;
+
+    // the tuning table's choice for (sigma, m), then explicit options on top
+    sm_tune_entry te;
+    const bool have = tune_lookup(sigma, m, te);
+    int algo = have ? te.algo : 0;
+    if (algo != ALGO_HASHQ && m > BP_MAX_M) algo = 0;  // entry not applicable to this m
+    if (have && te.algo == ALGO_HASHQ && te.q && (uint64_t)te.q > m) algo = 0;
+    const bool use_entry = algo != 0 && (o->algo == ALGO_AUTO || o->algo == algo);
+    if (o->algo != ALGO_AUTO) algo = o->algo;
+    if (algo == 0) {  // heuristic when no table entry applies
+        if (m <= 12) algo = ALGO_SHIFT_AND;
+        else if (m <= BP_MAX_M) algo = ALGO_SBNDM;
+        else algo = ALGO_HASHQ;
+    }
+    p.m = m;
+    p.algo = algo;
     p.q = 0;
     p.hbits = 0;
-    if (p.algo == ALGO_HASHQ) {
-        p.q = o->q ? o->q : choose_q(m, sigma);
-        if ((uint64_t)p.q > m) return fail(SM_EINVAL, "q = %d exceeds m = %llu", p.q, (unsigned long long)m);
-        p.hbits = o->hbits ? o->hbits : choose_hbits(m, p.q);
+    if (algo == ALGO_HASHQ) {
+        p.q = o->q ? o->q : (use_entry && te.q ? te.q : choose_q(m, sigma));
+        if ((uint64_t)p.q > m) p.q = (int)m;
+        p.hbits = o->hbits ? o->hbits : (use_entry && te.hbits ? te.hbits : choose_hbits(m, p.q));
     }
-    p.lane_bytes = o->lane_bytes ? o->lane_bytes : 64;
-    p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (p.algo == ALGO_HASHQ ? 4 : 1);
+    p.lane_bytes = o->lane_bytes ? o->lane_bytes : (use_entry && te.lane_bytes ? te.lane_bytes : 64);
+    p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (use_entry && te.tiles_per_wg ? te.tiles_per_wg : 1);
     return SM_OK;
 }
 
@@ -208,8 +295,8 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
 
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
-    // the planner never picks lanes below AUTO_MIN_LANE on its own
-    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : AUTO_MIN_LANE;
+    // explicit lanes, else the smallest the planner could pick for this m
+    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : min_auto_lane(m);
     Plan p;
     p.lane_bytes = lb;
     return ws_layout(n, m, tile_starts(p)).need;
@@ -233,7 +320,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         return SM_OK;
     }
     const WsLayout w = ws_layout(n, m, tile_starts(plan));
-    const uint64_t need = write ? w.need : w.tile_cnt;
+    const uint64_t need = write ? w.need : w.need_count;
     if (!d_work || work_bytes < need)
         return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)need);
     if (((uintptr_t)d_work & 255) != 0) return fail(SM_EINVAL, "workspace must be 256-byte aligned");
@@ -268,8 +355,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         HIP_TRY(launch_find(plan, d_text, n, prm, dpat, fw, d_out, cap, d_count, st,
                             prof ? rec.e2 : nullptr));
     } else {
-        HIP_TRY(launch_count(plan, d_text, n, prm, dpat, d_count, w.ntiles, st));
-        if (prof) HIP_TRY(hipEventRecord(rec.e2, st));
+        HIP_TRY(launch_count(plan, d_text, n, prm, dpat, fw, d_count, st, prof ? rec.e2 : nullptr));
     }
     if (prof) {
         HIP_TRY(hipEventRecord(rec.e3, st));
@@ -457,7 +543,8 @@ struct sm_corpus {
     uint64_t n = 0;
     bool owned = false;
     uint64_t hist[256];
-    int32_t sigma = 0;
+    int32_t sigma = 0;        // distinct bytes
+    double sigma_eff = 0;     // 1 / sum_c p_c^2: alphabet size with the same collision rate
     int dev = 0;
 };
 
@@ -503,7 +590,13 @@ extern "C" int sm_corpus_open(const uint8_t *text, uint64_t n, int text_on_devic
             delete c;
             return fail(SM_EDEVICE, "corpus histogram failed: %s", hipGetErrorString(e));
         }
-        for (int k = 0; k < 256; k++) c->sigma += c->hist[k] ? 1 : 0;
+        double s2 = 0;
+        for (int k = 0; k < 256; k++) {
+            c->sigma += c->hist[k] ? 1 : 0;
+            const double pk = (double)c->hist[k] / (double)n;
+            s2 += pk * pk;
+        }
+        c->sigma_eff = s2 > 0 ? 1.0 / s2 : 0;
     }
     *corpus = c;
     return SM_OK;
@@ -517,12 +610,38 @@ extern "C" int sm_corpus_close(sm_corpus *c)
     return SM_OK;
 }
 
-extern "C" int sm_corpus_stats(const sm_corpus *c, uint64_t *histogram, int32_t *sigma)
+extern "C" int sm_corpus_stats(const sm_corpus *c, uint64_t *histogram, int32_t *sigma,
+                               double *sigma_eff)
 {
     if (!c) return fail(SM_EINVAL, "corpus is NULL");
     if (histogram) memcpy(histogram, c->hist, sizeof c->hist);
     if (sigma) *sigma = c->sigma;
+    if (sigma_eff) *sigma_eff = c->sigma_eff;
     return SM_OK;
+}
+
+static int corpus_sigma(const sm_corpus *c)
+{
+    int s = (int)std::lround(c->sigma_eff);
+    return s < 1 ? 1 : (s > 256 ? 256 : s);
+}
+
+extern "C" int sm_corpus_find_all_async(sm_corpus *c, const uint8_t *pat, uint64_t m, int64_t *d_out,
+                                        uint64_t cap, uint64_t *d_count, void *d_work,
+                                        uint64_t work_bytes, const sm_opts *opts, void *stream)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    return run_async(c->d_text, c->n, pat, m, d_out, cap, d_count, d_work, work_bytes, opts,
+                     (hipStream_t)stream, true, corpus_sigma(c));
+}
+
+extern "C" int sm_corpus_count_async(sm_corpus *c, const uint8_t *pat, uint64_t m, uint64_t *d_count,
+                                     void *d_work, uint64_t work_bytes, const sm_opts *opts,
+                                     void *stream)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    return run_async(c->d_text, c->n, pat, m, nullptr, 0, d_count, d_work, work_bytes, opts,
+                     (hipStream_t)stream, false, corpus_sigma(c));
 }
 
 extern "C" int sm_corpus_text(const sm_corpus *c, const uint8_t **d_text, uint64_t *n)
@@ -550,7 +669,7 @@ extern "C" int sm_corpus_find_all(sm_corpus *c, const uint8_t *pat, uint64_t m, 
     const uint64_t ncap = std::min<uint64_t>(cap, c->n - m + 1);
     if (ncap) HIP_TRY(hipMalloc(&dout.p, ncap * 8));
     uint64_t total = 0;
-    r = run_sync_dev(c->d_text, c->n, pat, m, (int64_t *)dout.p, ncap, &total, nullptr, true, c->sigma);
+    r = run_sync_dev(c->d_text, c->n, pat, m, (int64_t *)dout.p, ncap, &total, nullptr, true, corpus_sigma(c));
     if (r < 0) return r;
     const uint64_t k = std::min<uint64_t>(total, ncap);
     if (k) HIP_TRY(hipMemcpy(out_pos, dout.p, k * 8, hipMemcpyDeviceToHost));
@@ -569,5 +688,5 @@ extern "C" int sm_corpus_count(sm_corpus *c, const uint8_t *pat, uint64_t m, uin
         return SM_OK;
     }
     HIP_TRY(hipSetDevice(c->dev));
-    return run_sync_dev(c->d_text, c->n, pat, m, nullptr, 0, count, nullptr, false, c->sigma);
+    return run_sync_dev(c->d_text, c->n, pat, m, nullptr, 0, count, nullptr, false, corpus_sigma(c));
 }

@@ -23,18 +23,22 @@ constexpr int Q_MAX = 16;          // longest hashed q-gram
 constexpr int H_MIN = 8;           // hash table bits range
 constexpr int H_MAX = 12;
 constexpr int PREP_INLINE = 3072;  // pattern bytes carried in the prep kernel's arguments
+constexpr uint32_t PERIOD_MAX = 64;  // periods searched by the prep kernel
 
 constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass
 constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
-constexpr int AUTO_MIN_LANE = 64;    // smallest lane_bytes the planner picks on its own
+constexpr int EMIT_SUB = 4096;       // starts per sub-tile when a dense tile is rescanned
+constexpr uint64_t SCAN_CHUNK = 4096; // tile counts per workgroup of the tile-count scan
+constexpr int AUTO_MIN_LANE = 64;    // lane_bytes of the planner's heuristic (no table entry)
 
 // Device-side parameter block at the start of the caller's workspace; the
 // pattern follows it (16-byte aligned, zero padded).
 struct alignas(16) Params {
     uint32_t m, algo, q, hbits;
-    uint32_t sh1;     // Hash-q: shift after a verified window
-    uint32_t period;  // smallest period of the pattern (shift after an SBNDM hit)
-    uint32_t pad0, pad1;
+    uint32_t sh1;        // Hash-q: shift after a verified window
+    uint32_t period;     // smallest period of p if it is <= PERIOD_MAX or p has none (= m); else 0
+    uint32_t period_lb;  // lower bound on the smallest period
+    uint32_t pad0;
     uint64_t mask[256];          // Shift-And (complemented form) or BNDM masks
     uint8_t shift[1 << H_MAX];   // Hash-q shift per hash bucket (capped at 255)
 };
@@ -54,7 +58,8 @@ struct Plan {
 // [Params][pattern][tile_cnt u32][tile_off u64][list u32][nlist u64][stash u16 x STASH_K per tile]
 struct WsLayout {
     uint64_t params, pat, tile_cnt, tile_off, list, nlist, stash;
-    uint64_t need;     // minimum workspace size for find_all (count needs only params + pat)
+    uint64_t need;        // minimum workspace size for find_all
+    uint64_t need_count;  // minimum workspace size for count (params, pattern, tile_cnt)
     uint64_t ntiles;
 };
 
@@ -79,6 +84,7 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
     o = align_up(o + m + 64, 256);
     w.tile_cnt = o;
     o = align_up(o + 4 * w.ntiles, 256);
+    w.need_count = align_up(o, 256);
     w.tile_off = o;
     o = align_up(o + 8 * w.ntiles, 256);
     w.list = o;
@@ -106,10 +112,11 @@ struct FindWs {
 // Builds the pattern's tables in d_params; zeroes *d_zero when not null.
 hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_params,
                        uint8_t *d_pat, uint64_t *d_zero, hipStream_t stream);
-// sum of occurrences -> *d_total (zeroed by the prep kernel)
+// count -> sum: total -> *d_total (uses w.tile_cnt only).
+// `after_count` (may be null) is recorded after the count kernel.
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n,
-                        const Params *d_params, const uint8_t *d_pat, uint64_t *d_total,
-                        uint64_t ntiles, hipStream_t stream);
+                        const Params *d_params, const uint8_t *d_pat, const FindWs &w,
+                        uint64_t *d_total, hipStream_t stream, hipEvent_t after_count);
 // count -> scan -> emit: positions -> d_out[0 .. min(total, cap)), total -> *d_total.
 // `after_count` (may be null) is recorded after the count kernel.
 hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,

@@ -123,33 +123,50 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
 // ---------------------------------------------------------------------------
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <bool SWZ, int PER>
-__device__ __forceinline__ int stage(uint4 *lds, const uint8_t *text, uint64_t x0, uint64_t x1)
+// Text bytes in flight from HBM to LDS: positions [x0, x1) (0 <= x0 < x1 <= n)
+// as aligned 16-byte chunks, PER chunk loads per thread.
+template <int PER>
+struct Staged {
+    u32x4 v[PER];
+    uint32_t nch;
+    int boff;  // byte offset in LDS of position x0 (inside the first aligned chunk)
+};
+
+template <int PER>
+__device__ __forceinline__ void stage_issue(Staged<PER> &st, const uint8_t *text, uint64_t x0,
+                                            uint64_t x1)
 {
     const uintptr_t a0 = (uintptr_t)(text + x0);
     const uintptr_t c0 = a0 & ~(uintptr_t)15;
     const uintptr_t c1 = ((uintptr_t)(text + x1 - 1)) & ~(uintptr_t)15;
-    const uint32_t nch = (uint32_t)((c1 - c0) >> 4) + 1;
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(c0);
-    u32x4 v[PER];
+    st.nch = (uint32_t)((c1 - c0) >> 4) + 1;
+    st.boff = (int)(a0 & 15);
+    typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
+    global_u32x4 *src = (global_u32x4 *)(c0);  // the text is in global memory
 #pragma unroll
     for (int k = 0; k < PER; k++) {
         const uint32_t u = threadIdx.x + BLOCK * k;
-        if (u < nch) v[k] = __builtin_nontemporal_load(src + u);
+        if (u < st.nch) st.v[k] = __builtin_nontemporal_load(src + u);
     }
+}
+
+// SWZ selects the XOR-swizzled chunk layout used by the per-lane sequential
+// readers (conflict-free 16-byte LDS reads at any power-of-two segment stride).
+template <bool SWZ, int PER>
+__device__ __forceinline__ void stage_commit(const Staged<PER> &st, uint4 *lds)
+{
 #pragma unroll
     for (int k = 0; k < PER; k++) {
         const uint32_t u = threadIdx.x + BLOCK * k;
-        if (u < nch) {
+        if (u < st.nch) {
             uint4 w;
-            w.x = v[k].x;
-            w.y = v[k].y;
-            w.z = v[k].z;
-            w.w = v[k].w;
+            w.x = st.v[k].x;
+            w.y = st.v[k].y;
+            w.z = st.v[k].z;
+            w.w = st.v[k].w;
             lds[SWZ ? swz(u) : u] = w;
         }
     }
-    return (int)(a0 & 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,58 +300,142 @@ __device__ __forceinline__ uint32_t lane_sbndm(const uint8_t *lds8, const uint64
     return cnt;
 }
 
-// Byte-exact check of the window starting at global position gpos against p.
-// Reads aligned text words that contain window bytes only.
-__device__ __noinline__ bool verify_global(const uint8_t *text, uint64_t gpos, const uint8_t *pat,
-                                            uint32_t m)
+// 16 bytes starting at byte address p, assembled from aligned words. Only words
+// whose first byte is <= last (the last byte that may be read) are loaded; the
+// others read as zero.
+__device__ __forceinline__ uint4 load16(const uint8_t *p, const uint8_t *last)
 {
-    const uintptr_t a = (uintptr_t)(text + gpos);
-    const uint32_t *T = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *W = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)(a & 3);
-    const uint32_t klast = (uint32_t)(((a + m - 1) >> 2) - (a >> 2));
-    const uint32_t *P = reinterpret_cast<const uint32_t *>(pat);
-    uint32_t prev = T[0];
-    for (uint32_t i = 0; i < m; i += 4) {
-        const uint32_t kk = (i >> 2) + 1;
-        const uint32_t cur = kk <= klast ? T[kk] : 0u;
-        const uint32_t w = alignbyte(cur, prev, sh);
-        const uint32_t rem = m - i;
-        const uint32_t msk = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
-        if ((w ^ P[i >> 2]) & msk) return false;
-        prev = cur;
+    const uintptr_t wl = (uintptr_t)last & ~(uintptr_t)3;  // last loadable word
+    uint32_t w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = ((uintptr_t)(W + k) <= wl) ? W[k] : 0u;
+    uint4 r;
+    r.x = alignbyte(w[1], w[0], sh);
+    r.y = alignbyte(w[2], w[1], sh);
+    r.z = alignbyte(w[3], w[2], sh);
+    r.w = alignbyte(w[4], w[3], sh);
+    return r;
+}
+
+// nonzero iff the first nb (<= 16) bytes of x and y differ
+__device__ __forceinline__ uint32_t diff16(uint4 x, uint4 y, uint32_t nb)
+{
+    uint32_t d = 0;
+    d |= (x.x ^ y.x) & byte_mask((int)nb);
+    d |= (x.y ^ y.y) & byte_mask((int)nb - 4 < 0 ? 0 : (int)nb - 4);
+    d |= (x.z ^ y.z) & byte_mask((int)nb - 8 < 0 ? 0 : (int)nb - 8);
+    d |= (x.w ^ y.w) & byte_mask((int)nb - 12 < 0 ? 0 : (int)nb - 12);
+    return d;
+}
+
+// Compare t[g + off, g + off + len) with p[off, off + len) for len <= 16, where
+// g is the window's global start and the window [g, g + m) lies inside the text.
+__device__ __forceinline__ bool verify_lane16(const uint8_t *text, uint64_t g, const uint8_t *pat,
+                                              uint32_t m, uint32_t off, uint32_t len)
+{
+    return diff16(load16(text + g + off, text + g + m - 1), load16(pat + off, pat + m + 15), len) == 0;
+}
+
+// The same comparison, any len, by a whole wave: lane k takes bytes [16k, 16k + 16) of
+// each 1024-byte block. Every lane of the wave must call it with the same
+// arguments; the result is the same on all lanes.
+__device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, const uint8_t *pat,
+                                            uint32_t m, uint32_t off, uint32_t len)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint8_t *tlast = text + g + m - 1;
+    const uint8_t *plast = pat + m + 15;
+    uint32_t d = 0;
+    for (uint32_t b = 0; b < len; b += 1024) {
+        const uint32_t o = b + 16 * lane;
+        if (o < len)
+            d |= diff16(load16(text + g + off + o, tlast), load16(pat + off + o, plast),
+                        len - o < 16 ? len - o : 16);
+        if (__ballot(d != 0)) return false;
     }
     return true;
 }
 
 // Hash-q over the lane's windows. The LDS holds text positions from m-q on;
 // li0 is the LDS index of relative position 0 (may be negative).
+// Wave-cooperative: all 64 lanes of the wave call it (lanes without starts have
+// lo > hi). A lane advances to its next candidate window (zero shift); a
+// candidate is settled by the pattern's period when possible (two occurrences are
+// at least the smallest period apart, period_lb bounds it from below; at distance
+// exactly `period` -- the smallest period when known, else 0 -- from a verified
+// occurrence only the last `period` bytes are new), by the lane itself when at most 64
+// bytes remain to compare, and otherwise by the whole wave.
 template <int NW, bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint8_t *shift, int m,
-                                              int q, int hbits, int sh1, int li0, int lo, int hi,
-                                              const uint8_t *text, uint64_t s, const uint8_t *pat,
-                                              E &o)
+                                              int q, int hbits, int sh1, int period, int period_lb,
+                                              int li0, int lo, int hi, const uint8_t *text,
+                                              uint64_t s, const uint8_t *pat, E &o)
 {
     uint32_t cnt = 0;
     int pos = lo;
-    while (pos <= hi) {
-        const int gs = li0 + pos + m - q;  // LDS index of the q-gram's first byte
-        const int wi = gs >> 2, sb = gs & 3;
-        uint32_t d[NW + 1];
+    bool active = lo <= hi;
+    bool have_prev = false;  // a verified occurrence of this lane at prev
+    int prev = 0;
+    for (;;) {
+        // 1. next candidate of this lane
+        bool cand = false;
+        while (active && !cand) {
+            const int gs = li0 + pos + m - q;  // LDS index of the q-gram's first byte
+            const int wi = gs >> 2, sb = gs & 3;
+            uint32_t d[NW + 1];
 #pragma unroll
-        for (int k = 0; k <= NW; k++) d[k] = lds32[wi + k];
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (int k = 0; k <= NW; k++) d[k] = lds32[wi + k];
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int k = 0; k < NW; k++) w[k] = alignbyte(d[k + 1], d[k], (uint32_t)sb) & byte_mask(q - 4 * k);
-        const uint32_t h = qhash(w[0], w[1], w[2], w[3], (uint32_t)hbits);
-        const int sh = shift[h];
-        if (sh == 0) {
-            if (verify_global(text, s + (uint64_t)pos, pat, (uint32_t)m)) {
+            for (int k = 0; k < NW; k++)
+                w[k] = alignbyte(d[k + 1], d[k], (uint32_t)sb) & byte_mask(q - 4 * k);
+            const int sh = shift[qhash(w[0], w[1], w[2], w[3], (uint32_t)hbits)];
+            if (sh == 0) {
+                cand = true;
+            } else {
+                pos += sh;
+                active = pos <= hi;
+            }
+        }
+        // 2. settle it: period rule, lane check, or mark for the wave
+        bool hit = false, need_wave = false;
+        uint32_t voff = 0, vlen = (uint32_t)m;
+        if (cand) {
+            const int dist = pos - prev;
+            if (have_prev && dist < period_lb) {
+                hit = false;  // closer than the smallest period to an occurrence: impossible
+            } else {
+                if (have_prev && dist == period && period < m) {
+                    voff = (uint32_t)(m - period);
+                    vlen = (uint32_t)period;
+                }
+                if (vlen <= 16) hit = verify_lane16(text, s + (uint64_t)pos, pat, (uint32_t)m, voff, vlen);
+                else need_wave = true;
+            }
+        }
+        uint64_t pend = __ballot(need_wave);
+        while (pend) {
+            const int k = __builtin_ctzll(pend);
+            pend &= pend - 1;
+            const int kpos = __shfl(pos, k, 64);
+            const uint32_t koff = __shfl(voff, k, 64), klen = __shfl(vlen, k, 64);
+            const bool ok = verify_wave(text, s + (uint64_t)kpos, pat, (uint32_t)m, koff, klen);
+            if ((int)(threadIdx.x & 63) == k) hit = ok;
+        }
+        // 3. record and move on
+        if (cand) {
+            if (hit) {
                 if (WRITE) o.put(pos); else cnt++;
+                have_prev = true;
+                prev = pos;
             }
             pos += sh1;
-        } else {
-            pos += sh;
+            active = pos <= hi;
         }
+        if (!__ballot(active)) break;
     }
     return cnt;
 }
@@ -377,51 +478,83 @@ struct TileShared {
     uint32_t w[BLOCK / 64];
 };
 
-// Tables into LDS (once per workgroup).
-template <int ALGO, int VAR>
-__device__ __forceinline__ void load_tables(const Params *prm, uint64_t *s_mask, uint8_t *s_shift,
-                                            uint32_t hbits)
+// Pattern tables, read from the parameter block into registers (issue), then
+// written to LDS (commit): each thread carries one mask entry or 16 Hash-q
+// buckets.
+template <int ALGO>
+__device__ __forceinline__ uint4 tables_issue(const Params *prm, uint32_t hbits)
 {
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    uint4 r = {0u, 0u, 0u, 0u};
     if (ALGO == ALGO_HASHQ) {
-        const uint32_t nb = 1u << hbits;
-        const uint4 *src = reinterpret_cast<const uint4 *>(prm->shift);
-        for (uint32_t k = tid; k < nb / 16; k += BLOCK) reinterpret_cast<uint4 *>(s_shift)[k] = src[k];
-    } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
-        reinterpret_cast<uint32_t *>(s_mask)[tid] = (uint32_t)prm->mask[tid];
+        if (tid < ((1u << hbits) >> 4)) r = reinterpret_cast<const uint4 *>(prm->shift)[tid];
     } else {
-        s_mask[tid] = prm->mask[tid];
+        const uint64_t w = prm->mask[tid];
+        r.x = (uint32_t)w;
+        r.y = (uint32_t)(w >> 32);
+    }
+    return r;
+}
+
+template <int ALGO, int VAR>
+__device__ __forceinline__ void tables_commit(uint4 r, uint64_t *s_mask, uint8_t *s_shift,
+                                              uint32_t hbits)
+{
+    const uint32_t tid = threadIdx.x;
+    if (ALGO == ALGO_HASHQ) {
+        if (tid < ((1u << hbits) >> 4)) reinterpret_cast<uint4 *>(s_shift)[tid] = r;
+    } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
+        reinterpret_cast<uint32_t *>(s_mask)[tid] = r.x;
+    } else {
+        s_mask[tid] = ((uint64_t)r.y << 32) | r.x;
     }
 }
 
-// Stage tile t (t < ntiles) and return the lane's start range [lo, hi] (relative
-// to the tile start s) and the LDS index li0 of relative position 0.
+// Geometry of tile t (t < ntiles): tile start s, staged span [x0, x1), last
+// admissible relative start hi_rel, and the span's offset r0 from s.
+struct TileGeom {
+    uint64_t s, x0, x1;
+    int hi_rel, r0;
+};
+
+template <int ALGO, int L>
+__device__ __forceinline__ TileGeom tile_geom(const ScanArgs &a, uint64_t t)
+{
+    constexpr int T = Geometry<ALGO, L>::T;
+    TileGeom g;
+    const uint64_t last_start = a.n - a.m;  // n >= m guaranteed by the host
+    g.s = t * (uint64_t)T;
+    const uint64_t lim = last_start - g.s;  // >= 0 since t < ntiles
+    g.hi_rel = lim >= (uint64_t)(T - 1) ? T - 1 : (int)lim;
+    g.r0 = (ALGO == ALGO_HASHQ) ? (int)(a.m - a.q) : 0;
+    g.x0 = g.s + (uint64_t)g.r0;
+    g.x1 = g.s + (uint64_t)g.hi_rel + a.m;  // one past the last byte any window reads
+    if (g.x1 > a.n) g.x1 = a.n;
+    return g;
+}
+
+// Stage tile t synchronously (used by the emit kernel's rescans).
 template <int ALGO, int L>
 __device__ __forceinline__ void stage_tile(TileShared<ALGO, L> &S, const ScanArgs &a, uint64_t t,
                                            uint64_t &s, int &li0, int &lo, int &hi)
 {
     using G = Geometry<ALGO, L>;
-    const int m = (int)a.m;
-    const uint64_t last_start = a.n - a.m;  // n >= m guaranteed by the host
-    s = t * (uint64_t)G::T;
-    const uint64_t lim = last_start - s;    // >= 0 since t < ntiles
-    const int hi_rel = lim >= (uint64_t)(G::T - 1) ? G::T - 1 : (int)lim;
-    const uint64_t r0 = (ALGO == ALGO_HASHQ) ? (uint64_t)(m - (int)a.q) : 0;
-    const uint64_t x0 = s + r0;
-    uint64_t x1 = s + (uint64_t)hi_rel + a.m;  // one past the last byte any window reads
-    if (x1 > a.n) x1 = a.n;
-    const int boff = stage<ALGO == ALGO_SHIFT_AND, G::PER>(S.text, a.text, x0, x1);
-    li0 = boff - (int)r0;
+    const TileGeom g = tile_geom<ALGO, L>(a, t);
+    Staged<G::PER> st;
+    stage_issue(st, a.text, g.x0, g.x1);
+    stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+    s = g.s;
+    li0 = st.boff - g.r0;
     lo = threadIdx.x * L;
-    hi = (lo + L - 1) < hi_rel ? (lo + L - 1) : hi_rel;
+    hi = (lo + L - 1) < g.hi_rel ? (lo + L - 1) : g.hi_rel;
 }
 
 template <int ALGO, int L, int VAR, bool WRITE, class E>
 __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanArgs &a, int m,
-                                             int sh1, int period, uint64_t s, int li0, int lo,
-                                             int hi, E &o)
+                                             int sh1, int period, int period_lb, uint64_t s,
+                                             int li0, int lo, int hi, E &o)
 {
-    if (lo > hi) return 0u;
+    if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if (ALGO == ALGO_SHIFT_AND) {
         if (VAR == 0)
             return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
@@ -436,66 +569,93 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
                                  lo, hi, o);
     } else {
         return lane_hashq<VAR, WRITE>(reinterpret_cast<const uint32_t *>(S.text), S.shift, m,
-                                      (int)a.q, (int)a.hbits, sh1, li0, lo, hi, a.text, s, a.pat, o);
+                                      (int)a.q, (int)a.hbits, sh1, period, period_lb, li0, lo, hi,
+                                      a.text, s, a.pat, o);
     }
 }
 
-// Count kernel. FIND=false: occurrences are added to *total. FIND=true: per-tile
-// counts go to tile_cnt, and tiles with 1..STASH_K hits stash their offsets.
-template <int ALGO, int L, int VAR, bool FIND>
+// Count kernel: per-tile counts go to tile_cnt (the tile-count scan then sums
+// them: one atomic per workgroup on a single address would serialize). FIND:
+// tiles with 1..STASH_K hits also stash their hits' offsets.
+// A workgroup owns tiles_per_wg consecutive tiles. PREFETCH: the next tile's
+// loads are in flight while the current tile is scanned (costs registers);
+// otherwise each tile is loaded after the previous one is done.
+template <int ALGO, int L, int VAR, bool FIND, bool PREFETCH>
 __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
 {
+    using G = Geometry<ALGO, L>;
     __shared__ TileShared<ALGO, L> S;
     const int m = (int)a.m;
-    load_tables<ALGO, VAR>(a.prm, S.mask, S.shift, a.hbits);
-    const int sh1 = (int)a.prm->sh1;
-    const int period = (int)a.prm->period;
 
-    const uint64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    const uint64_t t_begin = g * a.tiles_per_wg;
+    const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+    const uint64_t t_begin = wg * a.tiles_per_wg;
     uint64_t t_end = t_begin + a.tiles_per_wg;
     if (t_end > a.ntiles) t_end = a.ntiles;
-    uint32_t acc = 0;
+
+    // tile loads first, then the tables: one round trip for both
+    Staged<G::PER> st;
+    TileGeom g = tile_geom<ALGO, L>(a, t_begin);
+    stage_issue(st, a.text, g.x0, g.x1);
+    const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
+    const int sh1 = (int)a.prm->sh1;
+    const int period = (int)a.prm->period;
+    const int period_lb = (int)a.prm->period_lb;
+    tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
+
     for (uint64_t t = t_begin; t < t_end; t++) {
-        uint64_t s;
-        int li0, lo, hi;
-        __syncthreads();  // previous tile's LDS readers are done
-        stage_tile<ALGO, L>(S, a, t, s, li0, lo, hi);
-        __syncthreads();
-        NoEmit ne;
-        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, s, li0, lo, hi, ne);
-        if (!FIND) {
-            acc += c;
-            continue;
+        if (!PREFETCH && t != t_begin) {
+            g = tile_geom<ALGO, L>(a, t);
+            stage_issue(st, a.text, g.x0, g.x1);
         }
+        __syncthreads();  // previous tile's LDS readers are done
+        stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+        const TileGeom cur = g;
+        const int li0 = st.boff - cur.r0;
+        __syncthreads();
+        if (PREFETCH && t + 1 < t_end) {  // the next tile's loads overlap this tile's scan
+            g = tile_geom<ALGO, L>(a, t + 1);
+            stage_issue(st, a.text, g.x0, g.x1);
+        }
+        const int lo = threadIdx.x * L;
+        const int hi = (lo + L - 1) < cur.hi_rel ? (lo + L - 1) : cur.hi_rel;
+        NoEmit ne;
+        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne);
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
         if (threadIdx.x == 0) a.tile_cnt[t] = tot;
-        if (c && tot <= STASH_K) {
+        if (FIND && tot && tot <= STASH_K) {  // uniform: Hash-q lanes verify together
             StashEmit se;
             se.dst = a.stash + t * STASH_K;
             se.idx = before;
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, s, li0, lo, hi, se);
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
         }
-    }
-    if (!FIND) {
-        uint32_t tot;
-        block_excl_scan(acc, S.w, tot);
-        if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)a.total, (unsigned long long)tot);
     }
 }
 
+// u16 offsets into an LDS list
+struct ListEmit {
+    uint16_t *dst;
+    uint32_t idx;
+    __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+};
+
 // Emit kernel: positions of the listed tiles, at their offsets, bounded by cap.
+// Tiles with at most STASH_K hits copy their stash. Denser tiles are rescanned
+// from LDS in sub-tiles of EMIT_SUB starts (16 per lane): each sub-tile's hits
+// are gathered in an LDS list in order, then written out coalesced.
 template <int ALGO, int L, int VAR>
 __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
 {
+    constexpr int SUB_LANE = EMIT_SUB / BLOCK;
     __shared__ TileShared<ALGO, L> S;
+    __shared__ uint16_t s_list[EMIT_SUB];
     const int m = (int)a.m;
     const uint64_t nl = *a.nlist;
     if ((uint64_t)blockIdx.x >= nl) return;
     bool tables = false;
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
+    const int period_lb = (int)a.prm->period_lb;
     for (uint64_t e = blockIdx.x; e < nl; e += gridDim.x) {
         const uint64_t t = a.list[e];
         const uint32_t tot = a.tile_cnt[t];
@@ -509,92 +669,150 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
             continue;
         }
         if (!tables) {
-            load_tables<ALGO, VAR>(a.prm, S.mask, S.shift, a.hbits);
+            const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
+            tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
             tables = true;
         }
         uint64_t s2;
-        int li0, lo, hi;
+        int li0, lo_t, hi_t;
         __syncthreads();
-        stage_tile<ALGO, L>(S, a, t, s2, li0, lo, hi);
+        stage_tile<ALGO, L>(S, a, t, s2, li0, lo_t, hi_t);
         __syncthreads();
-        NoEmit ne;
-        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, s2, li0, lo, hi, ne);
-        uint32_t tt;
-        const uint32_t before = block_excl_scan(c, S.w, tt);
-        if (c && off + before < a.cap) {
-            PosEmit pe;
-            pe.out = a.out;
-            pe.cap = a.cap;
-            pe.base = s2;
-            pe.idx = off + before;
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, s2, li0, lo, hi, pe);
+        const int hi_rel = (int)((a.n - a.m - s2) < (uint64_t)(Geometry<ALGO, L>::T - 1)
+                                     ? (a.n - a.m - s2) : (uint64_t)(Geometry<ALGO, L>::T - 1));
+        uint64_t run = off;
+        for (int sb = 0; sb <= hi_rel && run < a.cap; sb += EMIT_SUB) {  // uniform
+            const int lo = sb + SUB_LANE * (int)threadIdx.x;
+            const int hi = (lo + SUB_LANE - 1) < hi_rel ? (lo + SUB_LANE - 1) : hi_rel;
+            NoEmit ne;
+            const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, ne);
+            uint32_t ctot;
+            const uint32_t before = block_excl_scan(c, S.w, ctot);
+            if (ctot == 0) continue;  // uniform
+            ListEmit le;
+            le.dst = s_list;
+            le.idx = before;
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, le);
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK)
+                if (run + k < a.cap) a.out[run + k] = (int64_t)(s2 + s_list[k]);
+            __syncthreads();
+            run += ctot;
         }
     }
 }
 
-// Tile-count scan: one workgroup of 1024 threads, coalesced 4-count loads.
-// Writes exclusive offsets, the total and the ascending list of tiles with hits.
+// Tile-count scan, SCAN_CHUNK tiles per workgroup of 1024 threads and no waiting
+// between workgroups: workgroup w first sums all counts before its chunk itself
+// (coalesced 16-byte loads, eight in flight per thread), then scans its chunk.
+// Writes exclusive offsets and the ascending list of tiles with hits; the last
+// workgroup writes the total and the list length. With list == null only the
+// total is produced (count mode).
+__device__ __forceinline__ uint4 load_cnt4(const uint32_t *cnt, uint64_t i, uint64_t nt)
+{
+    if (i + 3 < nt) return *reinterpret_cast<const uint4 *>(cnt + i);
+    uint4 r = {0u, 0u, 0u, 0u};
+    if (i < nt) r.x = cnt[i];
+    if (i + 1 < nt) r.y = cnt[i + 1];
+    if (i + 2 < nt) r.z = cnt[i + 2];
+    return r;
+}
+
+// workgroup-wide sums of (a, b) over 1024 threads (16 waves)
+__device__ __forceinline__ void block_sum2_1024(uint64_t &a, uint32_t &b, uint64_t *s_a, uint32_t *s_b)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a += __shfl_xor(a, d, 64);
+        b += __shfl_xor(b, d, 64);
+    }
+    if (lane == 0) {
+        s_a[wv] = a;
+        s_b[wv] = b;
+    }
+    __syncthreads();
+    a = 0;
+    b = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        a += s_a[k];
+        b += s_b[k];
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint64_t nt,
                                                          uint64_t *off, uint64_t *total,
                                                          uint32_t *list, uint64_t *nlist)
 {
-    __shared__ uint64_t s_sum[16];
-    __shared__ uint32_t s_nz[16];
+    __shared__ uint64_t s_a[16];
+    __shared__ uint32_t s_b[16];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    uint64_t run = 0;     // occurrences before this chunk
-    uint64_t nrun = 0;    // listed tiles before this chunk
-    for (uint64_t base = 0; base < nt; base += 4096) {
-        uint32_t c[4];
-        const uint64_t i0 = base + 4 * (uint64_t)tid;
+    const uint64_t c0 = (uint64_t)blockIdx.x * SCAN_CHUNK;
+    // 1. occurrences and listed tiles before this chunk
+    uint64_t pre = 0;
+    uint32_t pnz = 0;
+    for (uint64_t i0 = 0; i0 < c0; i0 += 8 * 4 * 1024) {
+        uint4 v[8];
 #pragma unroll
-        for (int k = 0; k < 4; k++) c[k] = (i0 + k < nt) ? cnt[i0 + k] : 0u;
-        uint64_t my = (uint64_t)c[0] + c[1] + c[2] + c[3];
-        uint32_t nz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0) + (c[3] != 0);
-        // wave inclusive scans
-        uint64_t incl = my;
-        uint32_t nzi = nz;
+        for (int k = 0; k < 8; k++) {
+            const uint64_t i = i0 + 4 * (uint64_t)(tid + 1024 * k);
+            v[k] = i < c0 ? load_cnt4(cnt, i, c0) : uint4{0u, 0u, 0u, 0u};
+        }
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t o = __shfl_up(incl, d, 64);
-            const uint32_t p = __shfl_up(nzi, d, 64);
-            if (lane >= d) {
-                incl += o;
-                nzi += p;
-            }
+        for (int k = 0; k < 8; k++) {
+            pre += (uint64_t)v[k].x + v[k].y + v[k].z + v[k].w;
+            pnz += (v[k].x != 0) + (v[k].y != 0) + (v[k].z != 0) + (v[k].w != 0);
         }
-        if (lane == 63) {
-            s_sum[wv] = incl;
-            s_nz[wv] = nzi;
-        }
-        __syncthreads();
-        uint64_t wbefore = 0, ctot = 0;
-        uint32_t zbefore = 0, ztot = 0;
+    }
+    block_sum2_1024(pre, pnz, s_a, s_b);
+    // 2. this chunk: SCAN_CHUNK / 1024 = 4 consecutive counts per thread
+    const uint64_t i = c0 + 4 * (uint64_t)tid;
+    const uint4 v = load_cnt4(cnt, i, nt);
+    const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+    const uint64_t my = (uint64_t)c[0] + c[1] + c[2] + c[3];
+    const uint32_t mz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0) + (c[3] != 0);
+    uint64_t incl = my;
+    uint32_t zincl = mz;
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            const uint64_t x = s_sum[k];
-            const uint32_t z = s_nz[k];
-            wbefore += (k < wv) ? x : 0;
-            zbefore += (k < wv) ? z : 0;
-            ctot += x;
-            ztot += z;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(incl, d, 64);
+        const uint32_t p = __shfl_up(zincl, d, 64);
+        if (lane >= d) {
+            incl += o;
+            zincl += p;
         }
-        __syncthreads();
-        uint64_t o = run + wbefore + incl - my;
-        uint64_t zpos = nrun + zbefore + nzi - nz;
+    }
+    if (lane == 63) {
+        s_a[wv] = incl;
+        s_b[wv] = zincl;
+    }
+    __syncthreads();
+    uint64_t wb = 0, ctot = 0;
+    uint32_t zb = 0, ztot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        wb += (k < wv) ? s_a[k] : 0;
+        zb += (k < wv) ? s_b[k] : 0;
+        ctot += s_a[k];
+        ztot += s_b[k];
+    }
+    if (list) {
+        uint64_t o = pre + wb + incl - my;
+        uint64_t zp = pnz + zb + zincl - mz;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            if (i0 + k < nt) {
-                off[i0 + k] = o;
-                if (c[k]) list[zpos++] = (uint32_t)(i0 + k);
+            if (i + k < nt) {
+                off[i + k] = o;
+                if (c[k]) list[zp++] = (uint32_t)(i + k);
+                o += c[k];
             }
-            o += c[k];
         }
-        run += ctot;
-        nrun += ztot;
     }
-    if (tid == 0) {
-        *total = run;
-        *nlist = nrun;
+    if (tid == 0 && blockIdx.x == gridDim.x - 1) {
+        *total = pre + ctot;
+        if (nlist) *nlist = pnz + ztot;
     }
 }
 
@@ -651,19 +869,6 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
         for (uint32_t i = 0; i < m; i++)
             if (pp[m - 1 - i] == c) w |= 1ull << i;
         P->mask[c] = w;
-        if (tid == 0) {
-            // smallest period = m - (longest proper border of p)
-            int b = 0;  // border of p[0..k]
-            // prefix-function pass, O(m) with m <= 64
-            int pi[BP_MAX_M];
-            pi[0] = 0;
-            for (uint32_t k = 1; k < m; k++) {
-                while (b > 0 && pp[k] != pp[b]) b = pi[b - 1];
-                if (pp[k] == pp[b]) b++;
-                pi[k] = b;
-            }
-            P->period = m - (uint32_t)pi[m - 1];
-        }
     } else if (a.algo == ALGO_HASHQ) {
         const uint32_t q = a.q, hb = a.hbits, nb = 1u << hb;
         const uint32_t dflt = m - q + 1;
@@ -688,6 +893,39 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
             uint32_t v = (k == hl) ? 0u : s_tab[k];
             P->shift[k] = (uint8_t)(v > 255u ? 255u : v);
         }
+    }
+
+    // Smallest period of p among 1..PERIOD_MAX: d is a period iff p[i] == p[i+d]
+    // for all i < m - d. Four threads test each d. period = that d, or m when p
+    // has no proper period <= m-1 (only decided for m <= PERIOD_MAX + 1), else 0
+    // (unknown); period_lb is a lower bound on the smallest period.
+    __shared__ uint32_t s_bad[PERIOD_MAX + 1];
+    if (tid <= PERIOD_MAX) s_bad[tid] = 0;
+    __syncthreads();
+    {
+        const uint32_t d = 1 + (tid >> 2), part = tid & 3;
+        if (d <= PERIOD_MAX && d < m) {
+            const uint32_t len = m - d;
+            const uint32_t per = (len + 3) / 4;
+            const uint32_t b = part * per, e = b + per < len ? b + per : len;
+            for (uint32_t i = b; i < e; i++)
+                if (pp[i] != pp[i + d]) {
+                    s_bad[d] = 1;
+                    break;
+                }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t per = 0;
+        for (uint32_t d = 1; d <= PERIOD_MAX && d < m; d++)
+            if (!s_bad[d]) {
+                per = d;
+                break;
+            }
+        if (per == 0 && m <= PERIOD_MAX + 1) per = m;
+        P->period = per;
+        P->period_lb = per ? per : PERIOD_MAX + 1;
     }
 }
 
@@ -715,11 +953,14 @@ template <int ALGO, int L, int VAR, int KIND>
 hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
 {
     if (grid == 0) return hipSuccess;
-    if (KIND == K_COUNT)
-        hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false>), dim3(grid), dim3(BLOCK), 0, st, a);
-    else if (KIND == K_FIND_COUNT)
-        hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true>), dim3(grid), dim3(BLOCK), 0, st, a);
-    else
+    const bool pf = a.tiles_per_wg > 1;
+    if (KIND == K_COUNT) {
+        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    } else if (KIND == K_FIND_COUNT) {
+        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    } else
         hipLaunchKernelGGL((emit_kernel<ALGO, L, VAR>), dim3(grid), dim3(BLOCK), 0, st, a);
     return hipGetLastError();
 }
@@ -813,14 +1054,29 @@ hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_para
     return hipGetLastError();
 }
 
-hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                        const uint8_t *d_pat, uint64_t *d_total, uint64_t ntiles, hipStream_t stream)
+static hipError_t launch_tile_scan(const FindWs &w, uint64_t *d_total, bool find, hipStream_t stream)
 {
-    ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, ntiles);
-    a.total = d_total;
+    const uint64_t nb = (w.ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    hipLaunchKernelGGL(tile_scan_kernel, dim3((uint32_t)nb), dim3(1024), 0, stream, w.tile_cnt,
+                       w.ntiles, find ? w.tile_off : nullptr, d_total, find ? w.list : nullptr,
+                       find ? w.nlist : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
+                        const uint8_t *d_pat, const FindWs &w, uint64_t *d_total, hipStream_t stream,
+                        hipEvent_t after_count)
+{
+    if (w.ntiles == 0) return hipSuccess;
+    if (w.ntiles > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, w.ntiles);
+    a.tile_cnt = w.tile_cnt;
     const uint32_t g = count_grid(a);
-    if (ntiles && !g) return hipErrorInvalidValue;
-    return launch_any<K_COUNT>(plan, a, g, stream);
+    if (!g) return hipErrorInvalidValue;
+    hipError_t e = launch_any<K_COUNT>(plan, a, g, stream);
+    if (e != hipSuccess) return e;
+    if (after_count && (e = hipEventRecord(after_count, stream)) != hipSuccess) return e;
+    return launch_tile_scan(w, d_total, false, stream);
 }
 
 hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
@@ -845,10 +1101,7 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
         e = hipEventRecord(after_count, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, stream, w.tile_cnt, w.ntiles,
-                       w.tile_off, d_total, w.list, w.nlist);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = launch_tile_scan(w, d_total, true, stream)) != hipSuccess) return e;
     if (cap == 0) return hipSuccess;
     uint64_t eg = w.ntiles < EMIT_GRID ? w.ntiles : EMIT_GRID;
     return launch_any<K_EMIT>(plan, a, (uint32_t)eg, stream);

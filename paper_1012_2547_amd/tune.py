@@ -1,0 +1,135 @@
+"""Autotuner for the planner's (alphabet size, pattern length) -> kernel table.
+
+For each alphabet-size bucket (representative sigma in 2, 4, 16, 64, 256) and a
+grid of pattern lengths, every applicable configuration -- algorithm (Shift-And,
+BNDM, SBNDM, Hash-q with its gram length q), starts per lane and tiles per
+workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
+benchmark's seed 1) with substring patterns, as whole find_all calls. The
+fastest configuration of each cell becomes a table entry. The paper's own
+summary (Section 4) says the best algorithm depends on exactly these two
+quantities; this measures that map on MI355X.
+
+    python -m paper_1012_2547_amd.tune --out gpurun_out/tune      # on a GPU
+writes tune.json (entries + timings) and tune_table.inc (C initialisers for
+csrc/tune_table.inc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+SIGMAS = (2, 4, 16, 64, 256)
+SIGMA_RANGES = {2: (1, 2), 4: (3, 7), 16: (8, 31), 64: (32, 127), 256: (128, 256)}
+M_GRID = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 65, 96, 128, 192, 256, 384, 512, 768, 1024)
+QS = (2, 3, 4, 5, 6, 8, 10, 12, 16)
+
+
+def candidates(m: int, sigma: int):
+    out = []
+    if m <= 64:
+        for algo in (1, 2, 3):
+            for L in (32, 64, 128):
+                out.append(dict(algo=algo, lane_bytes=L, q=0, tiles_per_wg=1))
+            out.append(dict(algo=algo, lane_bytes=64, q=0, tiles_per_wg=2))
+    for q in QS:
+        if q > m or sigma ** q < m:  # too few distinct q-grams to skip anything
+            continue
+        for L in (64, 128):
+            out.append(dict(algo=4, lane_bytes=L, q=q, tiles_per_wg=1))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="gpurun_out/tune")
+    ap.add_argument("--n-log2", type=int, default=28)
+    ap.add_argument("--patterns", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=2)
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import numpy as np
+    import torch
+
+    import datagen as dg
+    import paper_1012_2547_amd as sm
+
+    os.makedirs(args.out, exist_ok=True)
+    dev = torch.device("cuda:0")
+    n = 1 << args.n_log2
+    stream = torch.cuda.current_stream()
+    work = torch.empty(sm.workspace_size(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
+                       device=dev)
+    dc = torch.zeros(1, dtype=torch.int64, device=dev)
+    results = []
+    t_start = time.time()
+    for sigma in SIGMAS:
+        h = dg.uniform_text(n, sigma, seed=2)
+        text = torch.from_numpy(h).to(dev)
+        for m in M_GRID:
+            pats = [dg.substring_pattern(h, m, seed=3, idx=j)[0] for j in range(args.patterns)]
+            counts = []
+            for p in pats:
+                sm.count_async(text, p, dc, work, None, stream)
+                counts.append(int(dc.item()))
+            out = torch.empty(max(max(counts), 1), dtype=torch.int64, device=dev)
+            best = None
+            cell = []
+            for cand in candidates(m, sigma):
+                o = sm.opts(algo=cand["algo"], lane_bytes=cand["lane_bytes"], q=cand["q"],
+                            tiles_per_wg=cand["tiles_per_wg"], sigma_hint=sigma)
+                for p in pats:  # warm-up
+                    sm.find_all_async(text, p, out, dc, work, o, stream)
+                torch.cuda.synchronize()
+                sm.prof_collect()
+                sm.prof_enable(True)
+                for _ in range(args.reps):
+                    for p in pats:
+                        sm.find_all_async(text, p, out, dc, work, o, stream)
+                torch.cuda.synchronize()
+                sm.prof_enable(False)
+                pr = sm.prof_collect()
+                us = pr["total_ms"] * 1e3 / max(pr["calls"], 1)
+                gbs = n / (us * 1e-6) / 1e9
+                rec = dict(cand, us=round(us, 2), gbs=round(gbs, 1),
+                           count_us=round(pr["count_ms"] * 1e3 / max(pr["calls"], 1), 2))
+                cell.append(rec)
+                if best is None or us < best["us"]:
+                    best = rec
+            results.append(dict(sigma=sigma, m=m, best=best, all=cell))
+            print("sigma=%3d m=%4d best %-9s L=%3d q=%2d tpw=%d  %.1f GB/s  (%.0fs)" % (
+                sigma, m, sm.ALGO_NAMES[best["algo"]], best["lane_bytes"], best["q"],
+                best["tiles_per_wg"], best["gbs"], time.time() - t_start), flush=True)
+        del text
+        torch.cuda.empty_cache()
+
+    entries = []
+    for r in results:
+        i = M_GRID.index(r["m"])
+        m_hi = M_GRID[i + 1] - 1 if i + 1 < len(M_GRID) else 0xFFFFFFFF
+        lo, hi = SIGMA_RANGES[r["sigma"]]
+        b = r["best"]
+        entries.append(dict(sigma_lo=lo, sigma_hi=hi, m_lo=r["m"], m_hi=m_hi, algo=b["algo"],
+                            lane_bytes=b["lane_bytes"], q=b["q"], tiles_per_wg=b["tiles_per_wg"],
+                            hbits=0, gbs=b["gbs"]))
+    with open(os.path.join(args.out, "tune.json"), "w") as f:
+        json.dump({"n": n, "device": torch.cuda.get_device_name(0), "entries": entries,
+                   "cells": results}, f, indent=1)
+    with open(os.path.join(args.out, "tune_table.inc"), "w") as f:
+        f.write("// generated by paper_1012_2547_amd/tune.py on %s, n = 2^%d, tuning seed 2\n"
+                % (torch.cuda.get_device_name(0), args.n_log2))
+        f.write("// {sigma_lo, sigma_hi, m_lo, m_hi, algo, lane_bytes, q, tiles_per_wg, hbits, 0}"
+                "  measured GB/s\n")
+        for e in entries:
+            f.write("    {%d, %d, %du, %du, %d, %d, %d, %d, %d, 0},  // %.1f\n" % (
+                e["sigma_lo"], e["sigma_hi"], e["m_lo"], e["m_hi"], e["algo"], e["lane_bytes"],
+                e["q"], e["tiles_per_wg"], e["hbits"], e["gbs"]))
+    print("wrote %s (%d entries) in %.0fs" % (args.out, len(entries), time.time() - t_start))
+
+
+if __name__ == "__main__":
+    main()

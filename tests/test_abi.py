@@ -117,3 +117,36 @@ def test_workspace_size_monotone(L):
     b = sm.workspace_size(1 << 30, 8)
     assert 0 < a < b
     assert sm.workspace_size(10, 20) > 0
+
+
+def test_tuning_table_roundtrip(L):
+    import paper_1012_2547_amd as sm
+    base = sm.tune_get()
+    assert len(base) > 50
+    assert all(1 <= e["algo"] <= 4 and e["m_lo"] <= e["m_hi"] for e in base)
+    # every (sigma, m) of the sweep grid is covered by some entry
+    for s in (2, 4, 16, 64, 256):
+        for m in (1, 2, 3, 5, 8, 63, 64, 65, 100, 1000, 5000):
+            assert any(e["sigma_lo"] <= s <= e["sigma_hi"] and e["m_lo"] <= m <= e["m_hi"]
+                       for e in base), (s, m)
+    custom = [dict(sigma_lo=1, sigma_hi=256, m_lo=1, m_hi=64, algo=3, lane_bytes=32)]
+    sm.tune_set(custom)
+    try:
+        assert sm.plan_query(b"abcdefgh")["algo"] == "sbndm"
+        assert sm.plan_query(b"abcdefgh")["lane_bytes"] == 32
+        assert sm.plan_query(b"x" * 100)["algo"] == "hashq"  # no entry: heuristic
+    finally:
+        sm.tune_set([])
+    assert sm.tune_get() == base
+    with pytest.raises(sm.SmError):
+        sm.tune_set([dict(sigma_lo=1, sigma_hi=2, m_lo=5, m_hi=1, algo=1)])
+    with pytest.raises(sm.SmError):
+        sm.tune_set([dict(sigma_lo=1, sigma_hi=2, m_lo=1, m_hi=5, algo=7)])
+
+
+def test_sigma_estimate_from_pattern_steers_plan(L):
+    import paper_1012_2547_amd as sm
+    # a 1000-byte pattern over 2 symbols plans long q-grams, over 256 symbols short ones
+    lo = sm.plan_query(bytes([0, 1]) * 500)
+    hi = sm.plan_query(bytes(range(256)) * 4)
+    assert lo["algo"] == hi["algo"] == "hashq" and lo["q"] > hi["q"]

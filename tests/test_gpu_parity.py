@@ -216,9 +216,11 @@ def test_config1_exact(sm):
 def test_host_and_corpus_paths(sm):
     t_np = dg.zipf_text(200_000, 64, 1.0, seed=1)
     c = sm.Corpus(t_np)
-    hist, sigma = c.stats()
-    assert np.array_equal(hist, np.bincount(t_np, minlength=256).astype(np.uint64))
-    assert sigma == int((np.bincount(t_np, minlength=256) > 0).sum())
+    hist, sigma, sigma_eff = c.stats()
+    bc = np.bincount(t_np, minlength=256)
+    assert np.array_equal(hist, bc.astype(np.uint64))
+    assert sigma == int((bc > 0).sum())
+    assert abs(sigma_eff - 1.0 / np.sum((bc / bc.sum()) ** 2)) < 1e-6 * sigma_eff
     for m in (4, 16, 64, 256):
         p, _ = dg.substring_pattern(t_np, m, seed=2, idx=m)
         want = oracle.find_all(t_np, p)
@@ -268,3 +270,23 @@ def test_workspace_reuse_across_calls(sm):
         sm.find_all_async(base[:n], p, out[:want.size], dc, work, o)
         assert int(dc.item()) == want.size, (i, n, m, algo)
         assert np.array_equal(out[:want.size].cpu().numpy(), want), (i, n, m, algo)
+
+
+def test_corpus_async_paths(sm):
+    """Corpus queries planned with the measured sigma_eff (zipf and uniform texts)."""
+    for t_np in (dg.zipf_text(300_000, 64, 1.0, seed=3), dg.uniform_text(300_000, 2, seed=3)):
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        c = sm.Corpus(t_dev)
+        work = torch.empty(sm.workspace_size(t_np.size, 1024, sm.opts(lane_bytes=16)),
+                           dtype=torch.uint8, device=DEV)
+        dc = torch.zeros(1, dtype=torch.int64, device=DEV)
+        for m in (1, 3, 8, 20, 64, 65, 300, 1024):
+            p, _ = dg.substring_pattern(t_np, m, seed=4, idx=m)
+            want = oracle.find_all(t_np, p)
+            c.count_async(p, dc, work)
+            assert int(dc.item()) == want.size
+            out = torch.empty(max(want.size, 1), dtype=torch.int64, device=DEV)
+            c.find_all_async(p, out[:want.size], dc, work)
+            assert int(dc.item()) == want.size
+            assert np.array_equal(out[:want.size].cpu().numpy(), want), m
+        c.close()
