@@ -68,6 +68,12 @@ def main():
     ap.add_argument("--per-cell", type=int, default=PER_CELL)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--sigmas", type=str, default="",
+                    help="comma-separated subset of the sweep's alphabet sizes (profiling runs)")
+    ap.add_argument("--ms", type=str, default="",
+                    help="comma-separated subset of the sweep's pattern lengths (profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,6 +91,19 @@ def main():
     torch.cuda.set_device(dev)
     n = 1 << args.n_log2
     stream = torch.cuda.current_stream()
+    global SIGMAS, MS
+    if args.sigmas:
+        SIGMAS = tuple(int(x) for x in args.sigmas.split(","))
+    if args.ms:
+        MS = tuple(int(x) for x in args.ms.split(","))
+    if args.calibrate_copy:
+        a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of 2^30 bytes done")
 
     # ---- inputs: texts resident in HBM, patterns, exact output sizes -------
     t0 = time.time()
