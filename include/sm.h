@@ -48,6 +48,9 @@ enum sm_status {
     SM_EBUSY = -4       /* the resource is in use (server queue full, closing) */
 };
 
+/* A device-resident text (see sm_corpus_open). */
+typedef struct sm_corpus sm_corpus;
+
 /* Scan algorithms (paper, Figs. 1 and 3). SM_ALGO_AUTO lets the planner choose. */
 enum sm_algo {
     SM_ALGO_AUTO = 0,
@@ -130,6 +133,36 @@ int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64
                    void *stream);
 
 /*
+ * Batched search: P patterns against one corpus, the text streamed once per
+ * group of patterns instead of once per pattern (kernels and grouping in the
+ * package's csrc/sm_batch.*). Patterns are concatenated in pats; pattern i is
+ * pats[pat_off[i] .. pat_off[i+1]) (pat_off has P + 1 entries, non-decreasing,
+ * no empty pattern: SM_EINVAL). Results are exactly the single-pattern results.
+ *
+ * sm_batch_count: counts[i] = number of occurrences of pattern i (host array).
+ * sm_batch_find_all: CSR output. out_off[i] = sum of the counts of patterns
+ *   < i (P + 1 entries, always complete); pattern i's positions, ascending, go
+ *   to out[out_off[i] .. out_off[i+1]) for the entries below cap. Returns
+ *   SM_TRUNCATED when out_off[P] > cap.
+ * *_async: device outputs (d_counts / d_out, d_out_off), caller workspace of
+ *   sm_batch_workspace_size bytes (256-byte aligned), enqueued on `stream`; the
+ *   pattern bytes are copied from the host during the call. The asynchronous
+ *   find_all takes patterns up to 2048 bytes; the synchronous forms take any m.
+ */
+uint64_t sm_batch_workspace_size(const sm_corpus *corpus, const uint8_t *pats,
+                                 const uint64_t *pat_off, uint32_t P);
+int sm_batch_count(sm_corpus *corpus, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+                   uint64_t *counts);
+int sm_batch_find_all(sm_corpus *corpus, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+                      int64_t *out, uint64_t cap, uint64_t *out_off);
+int sm_batch_count_async(sm_corpus *corpus, const uint8_t *pats, const uint64_t *pat_off,
+                         uint32_t P, uint64_t *d_counts, void *d_work, uint64_t work_bytes,
+                         void *stream);
+int sm_batch_find_all_async(sm_corpus *corpus, const uint8_t *pats, const uint64_t *pat_off,
+                            uint32_t P, int64_t *d_out, uint64_t cap, uint64_t *d_out_off,
+                            void *d_work, uint64_t work_bytes, void *stream);
+
+/*
  * Planner tuning table. The planner picks the first entry whose alphabet-size
  * range and pattern-length range contain (sigma, m); sigma is the corpus's
  * sigma_eff, opts->sigma_hint, or an estimate from the pattern's byte counts.
@@ -157,7 +190,6 @@ int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_i
  * planner then uses the measured alphabet size. A corpus is immutable after
  * open; concurrent queries on it are allowed.
  */
-typedef struct sm_corpus sm_corpus;
 int sm_corpus_open(const uint8_t *text, uint64_t n, int text_on_device, sm_corpus **corpus);
 int sm_corpus_close(sm_corpus *corpus);
 /* host output, synchronous */

@@ -18,7 +18,7 @@ from ._native import (ALGO_AUTO, ALGO_BNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
                       ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError,
                       TuneEntry, check, last_error, load)
 
-__all__ = ["find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
+__all__ = ["pack_patterns", "find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
            "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version"]
 
@@ -153,6 +153,20 @@ def find_all(text, pat, cap: int | None = None, o: Opts | None = None, stream=No
     return out[:min(int(c.value), cap)]
 
 
+def pack_patterns(patterns) -> tuple[np.ndarray, np.ndarray]:
+    """Concatenate patterns: (bytes as uint8 array, offsets as uint64 array of P + 1)."""
+    bs = [bytes(p) if not isinstance(p, np.ndarray) else p.astype(np.uint8).tobytes()
+          for p in patterns]
+    off = np.zeros(len(bs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(b) for b in bs])
+    buf = np.frombuffer(b"".join(bs) + b"\0", dtype=np.uint8)
+    return buf, off
+
+
+def _vp(a):
+    return ctypes.c_void_p(a.ctypes.data if isinstance(a, np.ndarray) else a.data_ptr())
+
+
 class Corpus:
     """A device-resident text reused across queries (sm_corpus_*)."""
 
@@ -209,6 +223,44 @@ class Corpus:
             self._h, _pat_ptr(b), m, ctypes.c_void_p(d_count.data_ptr()),
             ctypes.c_void_p(work.data_ptr()), work.numel(),
             ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+
+    # ---- batched search (sm_batch_*) --------------------------------------
+    def batch_workspace_size(self, patterns) -> int:
+        buf, off = pack_patterns(patterns)
+        return int(load().sm_batch_workspace_size(self._h, _vp(buf), _vp(off), len(off) - 1))
+
+    def batch_count(self, patterns) -> np.ndarray:
+        """Occurrence counts of every pattern (uint64 array, host)."""
+        buf, off = pack_patterns(patterns)
+        out = np.zeros(max(len(off) - 1, 1), dtype=np.uint64)
+        check(load().sm_batch_count(self._h, _vp(buf), _vp(off), len(off) - 1, _vp(out)))
+        return out[:len(off) - 1]
+
+    def batch_find_all(self, patterns, cap: int | None = None):
+        """(positions int64, offsets uint64 of P + 1): pattern i's occurrences are
+        positions[offsets[i]:offsets[i+1]] (entries past cap are not written)."""
+        buf, off = pack_patterns(patterns)
+        P = len(off) - 1
+        if cap is None:
+            cap = int(self.batch_count(patterns).sum())
+        out = np.empty(max(cap, 1), dtype=np.int64)
+        oo = np.zeros(P + 1, dtype=np.uint64)
+        check(load().sm_batch_find_all(self._h, _vp(buf), _vp(off), P, _vp(out), cap, _vp(oo)))
+        return out[:min(cap, int(oo[P]))], oo
+
+    def batch_count_async(self, patterns, d_counts, work, stream=None) -> int:
+        buf, off = pack_patterns(patterns)
+        return check(load().sm_batch_count_async(self._h, _vp(buf), _vp(off), len(off) - 1,
+                                                 _vp(d_counts), _vp(work), work.numel(),
+                                                 _stream_ptr(stream)))
+
+    def batch_find_all_async(self, patterns, d_out, d_out_off, work, stream=None) -> int:
+        buf, off = pack_patterns(patterns)
+        return check(load().sm_batch_find_all_async(
+            self._h, _vp(buf), _vp(off), len(off) - 1,
+            ctypes.c_void_p(d_out.data_ptr() if d_out is not None and d_out.numel() else 0),
+            d_out.numel() if d_out is not None else 0, _vp(d_out_off), _vp(work), work.numel(),
+            _stream_ptr(stream)))
 
     def count(self, pat) -> int:
         b, m = _pat(pat)

@@ -75,6 +75,11 @@ PROTOTYPES = {
     "sm_tune_set": (_i32, [ctypes.POINTER(TuneEntry), _u32]),
     "sm_tune_get": (_i32, [ctypes.POINTER(TuneEntry), _u32, ctypes.POINTER(ctypes.c_uint32)]),
     "sm_corpus_text": (_i32, [_vp, ctypes.POINTER(_vp), _pu64]),
+    "sm_batch_workspace_size": (_u64, [_vp, _vp, _vp, _u32]),
+    "sm_batch_count": (_i32, [_vp, _vp, _vp, _u32, _vp]),
+    "sm_batch_find_all": (_i32, [_vp, _vp, _vp, _u32, _vp, _u64, _vp]),
+    "sm_batch_count_async": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _u64, _vp]),
+    "sm_batch_find_all_async": (_i32, [_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _u64, _vp]),
     "sm_prof_enable": (_i32, [_i32]),
     "sm_prof_collect": (_i32, [ctypes.POINTER(Prof)]),
 }

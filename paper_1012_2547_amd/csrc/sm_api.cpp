@@ -41,6 +41,12 @@ static int fail(int status, const char *fmt, ...)
                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);                 \
     } while (0)
 
+const char *sm::sm_set_error(int status, const char *msg)
+{
+    fail(status, "%s", msg);
+    return g_err.c_str();
+}
+
 extern "C" const char *sm_version(void) { return "sm 0.1 (gfx950)"; }
 extern "C" const char *sm_last_error(void) { return g_err.c_str(); }
 
@@ -229,6 +235,11 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     p.lane_bytes = o->lane_bytes ? o->lane_bytes : (use_entry && te.lane_bytes ? te.lane_bytes : 64);
     p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (use_entry && te.tiles_per_wg ? te.tiles_per_wg : 1);
     return SM_OK;
+}
+
+int sm::plan_pattern(const uint8_t *pat, uint64_t m, int sigma, Plan &p)
+{
+    return make_plan(pat, m, nullptr, sigma, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,15 +549,6 @@ extern "C" int sm_count(const uint8_t *text, uint64_t n, const uint8_t *pat, uin
 // ---------------------------------------------------------------------------
 // corpora
 // ---------------------------------------------------------------------------
-struct sm_corpus {
-    const uint8_t *d_text = nullptr;
-    uint64_t n = 0;
-    bool owned = false;
-    uint64_t hist[256];
-    int32_t sigma = 0;        // distinct bytes
-    double sigma_eff = 0;     // 1 / sum_c p_c^2: alphabet size with the same collision rate
-    int dev = 0;
-};
 
 extern "C" int sm_corpus_open(const uint8_t *text, uint64_t n, int text_on_device, sm_corpus **corpus)
 {
@@ -620,7 +622,7 @@ extern "C" int sm_corpus_stats(const sm_corpus *c, uint64_t *histogram, int32_t 
     return SM_OK;
 }
 
-static int corpus_sigma(const sm_corpus *c)
+int sm::corpus_sigma(const sm_corpus *c)
 {
     int s = (int)std::lround(c->sigma_eff);
     return s < 1 ? 1 : (s > 256 ? 256 : s);

@@ -1,0 +1,392 @@
+// Batched multi-pattern search: P patterns against one resident text.
+//
+// The paper's experiments search one pattern at a time (Section 3); serving many
+// patterns over the same text on a GPU wants the text read once for many
+// patterns instead. Patterns are sorted by kernel variant (algorithm, state width
+// or q-gram words) and length, and cut into groups whose tables fit a fixed LDS
+// budget. A work item is (text chunk, group): one workgroup loads the group's
+// tables into LDS once, then streams the chunk's tiles through LDS and runs every
+// pattern of the group over each staged tile with the same per-lane scanners as
+// the single-pattern path. Items are ordered chunk-major, so the groups of a
+// chunk run close together and the chunk is served from L2 / Infinity Cache
+// after its first read.
+//
+// Counting writes one count per (pattern, chunk); a segmented scan gives each
+// pattern its total and per-chunk offsets; the write pass re-runs the items that
+// have hits and writes each pattern's positions into its CSR slice in order.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "sm_internal.h"
+#include "sm_device.h"
+
+namespace sm {
+namespace {
+using namespace dev;
+
+constexpr int BL = BATCH_LANE;                 // starts per lane
+constexpr int BT = BLOCK * BATCH_LANE;         // starts per tile
+// staged bytes: tile + halo of the group's longest pattern + misalignment + word reads
+constexpr int B_CHUNKS = (((BT + BATCH_MAX_M + 48 + 15) / 16 + 1) + 7) & ~7;
+constexpr int B_PER = (B_CHUNKS + BLOCK - 1) / BLOCK;
+
+struct PatInfo {
+    uint32_t m, q, hbits, sh1, period, period_lb;
+    uint64_t pat_off;
+};
+
+struct BatchArgs {
+    const uint8_t *text;
+    uint64_t n;
+    const BatchPat *pats;      // sorted order
+    const BatchGroup *groups;
+    const Params *params;      // per sorted pattern
+    const uint8_t *patbytes;
+    uint32_t group_lo, ngroups;  // groups handled by this launch
+    uint32_t chunk_tiles;
+    uint64_t nchunks, ntiles;
+    uint32_t *cnt;             // [sorted pattern][chunk]
+    const uint64_t *chunk_off; // [sorted pattern][chunk] (write)
+    const uint64_t *csr;       // [original index] (write)
+    int64_t *out;
+    uint64_t cap;
+};
+
+template <int ALGO, int VAR>
+struct BatchShared {
+    uint4 text[B_CHUNKS];
+    uint64_t tab[BATCH_TABLE_BYTES / 8];
+    PatInfo info[BATCH_GROUP_MAX];
+    uint32_t acc[BATCH_GROUP_MAX];
+    uint64_t run[BATCH_GROUP_MAX];
+    uint32_t w[BLOCK / 64];
+};
+
+// bytes of one pattern's table in LDS
+template <int ALGO, int VAR>
+__host__ __device__ __forceinline__ constexpr int tab_bytes()
+{
+    return ALGO == ALGO_HASHQ ? (1 << BATCH_HBITS_MAX) : ((ALGO == ALGO_SHIFT_AND && VAR == 0) ? 1024 : 2048);
+}
+
+template <int ALGO, int VAR>
+__device__ __forceinline__ void load_group_tables(BatchShared<ALGO, VAR> &S, const BatchArgs &a,
+                                                  const BatchGroup &g)
+{
+    constexpr int TB = tab_bytes<ALGO, VAR>();
+    const int tid = threadIdx.x;
+    for (uint32_t j = 0; j < g.count; j++) {
+        const Params *P = a.params + g.first + j;
+        uint8_t *dst = reinterpret_cast<uint8_t *>(S.tab) + j * TB;
+        if (ALGO == ALGO_HASHQ) {
+            const uint32_t nb = 1u << a.pats[g.first + j].hbits;
+            for (uint32_t k = tid; k < nb / 16; k += BLOCK)
+                reinterpret_cast<uint4 *>(dst)[k] = reinterpret_cast<const uint4 *>(P->shift)[k];
+        } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
+            reinterpret_cast<uint32_t *>(dst)[tid] = (uint32_t)P->mask[tid];
+        } else {
+            reinterpret_cast<uint64_t *>(dst)[tid] = P->mask[tid];
+        }
+    }
+    if (tid < (int)g.count) {
+        const BatchPat &bp = a.pats[g.first + tid];
+        const Params *P = a.params + g.first + tid;
+        PatInfo in;
+        in.m = bp.m;
+        in.q = bp.q;
+        in.hbits = bp.hbits;
+        in.sh1 = P->sh1;
+        in.period = P->period;
+        in.period_lb = P->period_lb;
+        in.pat_off = bp.pat_off;
+        S.info[tid] = in;
+        S.acc[tid] = 0;
+    }
+}
+
+// Scan pattern j of the group over the staged tile (all threads call it).
+template <int ALGO, int VAR, bool WRITE, class E>
+__device__ __forceinline__ uint32_t batch_lane(BatchShared<ALGO, VAR> &S, const BatchArgs &a, int j,
+                                               uint64_t s, int boff, int lo, int hi, E &o)
+{
+    constexpr int TB = tab_bytes<ALGO, VAR>();
+    const PatInfo in = S.info[j];
+    const int m = (int)in.m;
+    const uint8_t *tab = reinterpret_cast<const uint8_t *>(S.tab) + j * TB;
+    if (ALGO == ALGO_SHIFT_AND) {
+        if (lo > hi) return 0u;
+        if (VAR == 0)
+            return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(tab), m,
+                                                       boff, lo, hi, o);
+        if (VAR == 1)
+            return lane_shift_and<uint64_t, 16, WRITE>(S.text, reinterpret_cast<const uint64_t *>(tab), m,
+                                                       boff, lo, hi, o);
+        if (VAR == 2)
+            return lane_shift_and<uint64_t, 4, WRITE>(S.text, reinterpret_cast<const uint64_t *>(tab), m,
+                                                      boff, lo, hi, o);
+        return lane_shift_and<uint64_t, 1, WRITE>(S.text, reinterpret_cast<const uint64_t *>(tab), m,
+                                                  boff, lo, hi, o);
+    } else if (ALGO == ALGO_BNDM) {
+        if (lo > hi) return 0u;
+        return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text),
+                                reinterpret_cast<const uint64_t *>(tab), m, boff, lo, hi, o);
+    } else if (ALGO == ALGO_SBNDM) {
+        if (lo > hi) return 0u;
+        return lane_sbndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text),
+                                 reinterpret_cast<const uint64_t *>(tab), m, (int)in.period, boff, lo,
+                                 hi, o);
+    } else {
+        // wave-cooperative: every lane takes part, lanes without starts have lo > hi
+        return lane_hashq<VAR, WRITE>(reinterpret_cast<const uint32_t *>(S.text), tab, m, (int)in.q,
+                                      (int)in.hbits, (int)in.sh1, (int)in.period, (int)in.period_lb,
+                                      boff, lo, hi, a.text, s, a.patbytes + in.pat_off, o);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Stage tile t: text positions [s, s + BT + max_m - 1) clipped to n.
+template <int ALGO, int VAR>
+__device__ __forceinline__ int batch_stage(BatchShared<ALGO, VAR> &S, const BatchArgs &a, uint64_t s,
+                                           uint32_t max_m)
+{
+    uint64_t x1 = s + (uint64_t)BT + max_m - 1;
+    if (x1 > a.n) x1 = a.n;
+    Staged<B_PER> st;
+    stage_issue(st, a.text, s, x1);
+    stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+    return st.boff;
+}
+
+template <int ALGO, int VAR, bool WRITE>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a)
+{
+    __shared__ BatchShared<ALGO, VAR> S;
+    const uint64_t item = blockIdx.x;
+    const uint64_t chunk = item / a.ngroups;
+    const BatchGroup g = a.groups[a.group_lo + item % a.ngroups];
+    const int tid = threadIdx.x;
+
+    if (WRITE) {  // skip items without hits (uniform: every thread reads the same counts)
+        bool any = false;
+        for (uint32_t j = 0; j < g.count; j++) any |= a.cnt[(uint64_t)(g.first + j) * a.nchunks + chunk] != 0;
+        if (!any) return;
+    }
+    load_group_tables<ALGO, VAR>(S, a, g);
+    if (WRITE && tid < (int)g.count) {
+        const uint64_t sp = g.first + tid;
+        S.acc[tid] = a.cnt[sp * a.nchunks + chunk];
+        S.run[tid] = a.csr[a.pats[sp].index] + a.chunk_off[sp * a.nchunks + chunk];
+    }
+    const uint64_t t0 = chunk * a.chunk_tiles;
+    uint64_t t1 = t0 + a.chunk_tiles;
+    if (t1 > a.ntiles) t1 = a.ntiles;
+    for (uint64_t t = t0; t < t1; t++) {
+        const uint64_t s = t * (uint64_t)BT;
+        __syncthreads();  // previous tile's readers are done; tables and info visible
+        const int boff = batch_stage<ALGO, VAR>(S, a, s, g.max_m);
+        __syncthreads();
+        for (uint32_t j = 0; j < g.count; j++) {
+            const uint64_t m = S.info[j].m;
+            if (m > a.n || s > a.n - m) continue;  // no start of this pattern in the tile
+            if (WRITE && S.acc[j] == 0) continue;  // no hit of this pattern in the chunk
+            const uint64_t lim = a.n - m - s;
+            const int hi_rel = lim >= (uint64_t)(BT - 1) ? BT - 1 : (int)lim;
+            const int lo = tid * BL;
+            const int hi = (lo + BL - 1) < hi_rel ? (lo + BL - 1) : hi_rel;
+            NoEmit ne;
+            const uint32_t c = batch_lane<ALGO, VAR, false>(S, a, (int)j, s, boff, lo, hi, ne);
+            if (!WRITE) {
+                const uint32_t wsum = wave_sum(c);
+                if ((tid & 63) == 0 && wsum) atomicAdd(&S.acc[j], wsum);
+            } else {
+                uint32_t tot;
+                const uint32_t before = block_excl_scan(c, S.w, tot);
+                if (tot) {  // uniform
+                    PosEmit pe;
+                    pe.out = a.out;
+                    pe.cap = a.cap;
+                    pe.base = s;
+                    pe.idx = S.run[j] + before;
+                    batch_lane<ALGO, VAR, true>(S, a, (int)j, s, boff, lo, hi, pe);
+                    __syncthreads();
+                    if (tid == 0) S.run[j] += tot;
+                }
+            }
+        }
+    }
+    if (!WRITE) {
+        __syncthreads();
+        if (tid < (int)g.count) a.cnt[(uint64_t)(g.first + tid) * a.nchunks + chunk] = S.acc[tid];
+    }
+}
+
+// One workgroup per pattern: tables into params[j].
+__global__ __launch_bounds__(BLOCK) void batch_prep_kernel(const BatchPat *pats, const uint8_t *patbytes,
+                                                           Params *params)
+{
+    __shared__ uint32_t s_tab[1 << H_MAX];
+    __shared__ uint32_t s_bad[PERIOD_MAX + 1];
+    const BatchPat bp = pats[blockIdx.x];
+    Params *P = params + blockIdx.x;
+    if (threadIdx.x == 0) {
+        P->m = bp.m;
+        P->algo = bp.algo;
+        P->q = bp.q;
+        P->hbits = bp.hbits;
+    }
+    build_tables(patbytes + bp.pat_off, bp.m, bp.algo, bp.q, bp.hbits, P, s_tab, s_bad);
+}
+
+// One workgroup per sorted pattern: per-chunk counts -> exclusive offsets and the
+// pattern's total (stored at totals[original index]).
+__global__ __launch_bounds__(BLOCK) void batch_seg_scan_kernel(const BatchPat *pats, const uint32_t *cnt,
+                                                               uint64_t nchunks, uint64_t *chunk_off,
+                                                               uint64_t *totals)
+{
+    __shared__ uint32_t s_w[BLOCK / 64];
+    __shared__ uint64_t s_carry;
+    const uint64_t j = blockIdx.x;
+    const uint32_t *c = cnt + j * nchunks;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint64_t b = 0; b < nchunks; b += BLOCK) {
+        const uint64_t i = b + threadIdx.x;
+        const uint32_t v = i < nchunks ? c[i] : 0u;
+        uint32_t tot;
+        const uint32_t before = block_excl_scan(v, s_w, tot);
+        const uint64_t carry = s_carry;
+        if (chunk_off && i < nchunks) chunk_off[j * nchunks + i] = carry + before;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[pats[j].index] = s_carry;
+}
+
+// Exclusive scan of P totals (original order) -> csr[0..P], one workgroup of 1024.
+__global__ __launch_bounds__(1024) void csr_scan_kernel(const uint64_t *totals, uint64_t P, uint64_t *csr)
+{
+    __shared__ uint64_t s_part[1024];
+    const uint64_t per = (P + 1023) / 1024;
+    const uint64_t b = threadIdx.x * per;
+    const uint64_t e = b + per < P ? b + per : P;
+    uint64_t sum = 0;
+    for (uint64_t k = b; k < e; k++) sum += totals[k];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint64_t v = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t run = s_part[threadIdx.x] - sum;
+    for (uint64_t k = b; k < e; k++) {
+        csr[k] = run;
+        run += totals[k];
+    }
+    if (threadIdx.x == 1023) csr[P] = s_part[1023];
+}
+
+template <int ALGO, int VAR>
+hipError_t launch_batch_v(const BatchArgs &a, bool write, hipStream_t st)
+{
+    const uint64_t grid = a.nchunks * a.ngroups;
+    if (grid == 0) return hipSuccess;
+    if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    if (write)
+        hipLaunchKernelGGL((batch_kernel<ALGO, VAR, true>), dim3((uint32_t)grid), dim3(BLOCK), 0, st, a);
+    else
+        hipLaunchKernelGGL((batch_kernel<ALGO, VAR, false>), dim3((uint32_t)grid), dim3(BLOCK), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_class(uint32_t algo, uint32_t var, const BatchArgs &a, bool write, hipStream_t st)
+{
+    switch (algo) {
+    case ALGO_SHIFT_AND:
+        switch (var) {
+        case 0: return launch_batch_v<ALGO_SHIFT_AND, 0>(a, write, st);
+        case 1: return launch_batch_v<ALGO_SHIFT_AND, 1>(a, write, st);
+        case 2: return launch_batch_v<ALGO_SHIFT_AND, 2>(a, write, st);
+        default: return launch_batch_v<ALGO_SHIFT_AND, 3>(a, write, st);
+        }
+    case ALGO_BNDM: return launch_batch_v<ALGO_BNDM, 0>(a, write, st);
+    case ALGO_SBNDM: return launch_batch_v<ALGO_SBNDM, 0>(a, write, st);
+    case ALGO_HASHQ:
+        switch (var) {
+        case 1: return launch_batch_v<ALGO_HASHQ, 1>(a, write, st);
+        case 2: return launch_batch_v<ALGO_HASHQ, 2>(a, write, st);
+        case 3: return launch_batch_v<ALGO_HASHQ, 3>(a, write, st);
+        default: return launch_batch_v<ALGO_HASHQ, 4>(a, write, st);
+        }
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_csr_scan(const uint64_t *totals, uint64_t P, uint64_t *csr, hipStream_t st)
+{
+    hipLaunchKernelGGL(csr_scan_kernel, dim3(1), dim3(1024), 0, st, totals, P, csr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof a);
+    a.text = L.text;
+    a.n = L.n;
+    a.pats = L.pats;
+    a.groups = L.groups;
+    a.params = L.params;
+    a.patbytes = L.patbytes;
+    a.chunk_tiles = L.chunk_tiles;
+    a.nchunks = L.nchunks;
+    a.ntiles = L.ntiles;
+    a.cnt = L.cnt;
+    a.chunk_off = L.chunk_off;
+    a.csr = L.csr;
+    a.out = L.out;
+    a.cap = L.cap;
+    hipError_t e;
+    if (L.prep) {
+        hipLaunchKernelGGL(batch_prep_kernel, dim3(L.npats), dim3(BLOCK), 0, st, L.pats, L.patbytes,
+                           const_cast<Params *>(L.params));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // one launch per run of groups that share a kernel variant
+    uint32_t g = 0;
+    while (g < L.ngroups) {
+        uint32_t h = g + 1;
+        while (h < L.ngroups && L.host_groups[h].algo == L.host_groups[g].algo &&
+               L.host_groups[h].var == L.host_groups[g].var)
+            h++;
+        a.group_lo = g;
+        a.ngroups = h - g;
+        if ((e = launch_batch_class(L.host_groups[g].algo, L.host_groups[g].var, a, L.write, st)) != hipSuccess)
+            return e;
+        g = h;
+    }
+    if (!L.write) {
+        hipLaunchKernelGGL(batch_seg_scan_kernel, dim3(L.npats), dim3(BLOCK), 0, st, L.pats, L.cnt,
+                           L.nchunks, L.chunk_off_out, L.totals);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (L.csr_out) {
+            hipLaunchKernelGGL(csr_scan_kernel, dim3(1), dim3(1024), 0, st, L.totals,
+                               (uint64_t)L.npats_total, L.csr_out);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace sm

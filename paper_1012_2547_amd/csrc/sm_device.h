@@ -1,0 +1,490 @@
+// Device building blocks shared by the single-pattern and the batched kernels:
+// tile staging, the per-lane scanners (Shift-And, BNDM, SBNDM, Hash-q), hit
+// emitters, verification and per-pattern table construction.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sm_internal.h"
+
+namespace sm {
+namespace dev {
+
+__device__ __forceinline__ uint32_t swz(uint32_t u) { return u ^ ((u >> 3) & 7u); }
+
+__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s)
+{
+    return __builtin_amdgcn_alignbyte(hi, lo, s);
+}
+
+// Workgroup -> tile-group remap so that consecutive tile groups run on the same
+// XCD (workgroups are dealt round-robin over the 8 XCDs); neighbouring tiles share
+// their halo bytes through that XCD's L2.
+__device__ __forceinline__ uint64_t xcd_remap(uint64_t bid, uint64_t nblk)
+{
+    const uint64_t X = 8;
+    uint64_t x = bid % X, k = bid / X;
+    uint64_t per = nblk / X, rem = nblk % X;
+    return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// ---------------------------------------------------------------------------
+// q-gram hash: the q bytes, packed little-endian into up to four words (unused
+// bytes zero), multiplicatively hashed. Used identically by the prep kernel and
+// the scan; any hash is correct because candidates are verified byte-exactly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t qhash(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                          uint32_t hbits)
+{
+    uint32_t h = w0 * 0x9E3779B1u;
+    h ^= w1 * 0x85EBCA77u;
+    h ^= w2 * 0xC2B2AE3Du;
+    h ^= w3 * 0x27D4EB2Fu;
+    return h >> (32 - hbits);
+}
+
+__device__ __forceinline__ uint32_t byte_mask(int nbytes)  // nbytes in [0, 4]
+{
+    return nbytes >= 4 ? 0xFFFFFFFFu : ((1u << (8 * nbytes)) - 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup reductions (BLOCK = 256 threads = 4 wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// exclusive scan of v over the workgroup; returns the prefix, sets total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; k++) {
+        uint32_t x = s_w[k];
+        before += (k < wv) ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// Tile staging: text positions [x0, x1) (0 <= x0 < x1 <= n) into LDS chunks.
+// Returns the byte offset in LDS of position x0 (its offset inside the first
+// aligned 16-byte block). SWZ selects the XOR-swizzled chunk layout used by the
+// per-lane sequential readers (conflict-free 16-byte LDS reads at any segment
+// stride that is a power of two >= 16).
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Text bytes in flight from HBM to LDS: positions [x0, x1) (0 <= x0 < x1 <= n)
+// as aligned 16-byte chunks, PER chunk loads per thread.
+template <int PER>
+struct Staged {
+    u32x4 v[PER];
+    uint32_t nch;
+    int boff;  // byte offset in LDS of position x0 (inside the first aligned chunk)
+};
+
+template <int PER>
+__device__ __forceinline__ void stage_issue(Staged<PER> &st, const uint8_t *text, uint64_t x0,
+                                            uint64_t x1)
+{
+    const uintptr_t a0 = (uintptr_t)(text + x0);
+    const uintptr_t c0 = a0 & ~(uintptr_t)15;
+    const uintptr_t c1 = ((uintptr_t)(text + x1 - 1)) & ~(uintptr_t)15;
+    st.nch = (uint32_t)((c1 - c0) >> 4) + 1;
+    st.boff = (int)(a0 & 15);
+    typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
+    global_u32x4 *src = (global_u32x4 *)(c0);  // the text is in global memory
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const uint32_t u = threadIdx.x + BLOCK * k;
+        if (u < st.nch) st.v[k] = __builtin_nontemporal_load(src + u);
+    }
+}
+
+// SWZ selects the XOR-swizzled chunk layout used by the per-lane sequential
+// readers (conflict-free 16-byte LDS reads at any power-of-two segment stride).
+template <bool SWZ, int PER>
+__device__ __forceinline__ void stage_commit(const Staged<PER> &st, uint4 *lds)
+{
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const uint32_t u = threadIdx.x + BLOCK * k;
+        if (u < st.nch) {
+            uint4 w;
+            w.x = st.v[k].x;
+            w.y = st.v[k].y;
+            w.z = st.v[k].z;
+            w.w = st.v[k].w;
+            lds[SWZ ? swz(u) : u] = w;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Emitters: where a lane's hits go.
+// ---------------------------------------------------------------------------
+struct NoEmit {
+    __device__ __forceinline__ void put(int) {}
+};
+
+// int64 global positions, bounded by cap
+struct PosEmit {
+    int64_t *out;
+    uint64_t idx, cap;
+    uint64_t base;  // global position of relative position 0
+    __device__ __forceinline__ void put(int rel)
+    {
+        if (idx < cap) out[idx] = (int64_t)(base + (uint64_t)(int64_t)rel);
+        idx++;
+    }
+};
+
+// u16 offsets inside the tile (tile-local stash)
+struct StashEmit {
+    uint16_t *dst;
+    uint32_t idx;
+    __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+};
+
+// Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
+// hit checks (requires m - 1 + CHECK <= bits of W).
+template <typename W, int CHECK, bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *mask, int m, int li0,
+                                                  int lo, int hi, E &o)
+{
+    const int e_lo = lo + m - 1, e_hi = hi + m - 1;  // relative ends owned by this lane
+    const int u0 = (lo + li0) >> 4, u1 = (e_hi + li0) >> 4;
+    W D = ~(W)0;
+    uint32_t cnt = 0;
+    for (int u = u0; u <= u1; u++) {
+        const uint4 v = lds[swz((uint32_t)u)];
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int g = 0; g < 16 / CHECK; g++) {
+#pragma unroll
+            for (int b = 0; b < CHECK; b++) {
+                const int k = g * CHECK + b;
+                const uint32_t c = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                D = (D << 1) | mask[c];
+            }
+            // relative end of the last byte consumed
+            const int e_last = 16 * u + g * CHECK + CHECK - 1 - li0;
+            int jlo = e_last - e_hi, jhi = e_last - e_lo;
+            jlo = jlo < 0 ? 0 : jlo;
+            jhi = jhi > CHECK - 1 ? CHECK - 1 : jhi;
+            if (jlo <= jhi) {
+                uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
+                hits &= ((2u << jhi) - 1u) & ~((1u << jlo) - 1u);
+                if (hits) {
+                    if (WRITE) {
+                        // bit j <-> end e_last - j; ascending positions = descending j
+                        while (hits) {
+                            const int j = 31 - __builtin_clz(hits);
+                            hits &= ~(1u << j);
+                            o.put(e_last - j - m + 1);
+                        }
+                    } else {
+                        cnt += __builtin_popcount(hits);
+                    }
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+// BNDM: masks B[c] bit i set iff p[m-1-i] == c.
+template <bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_t *B, int m,
+                                             int li0, int lo, int hi, E &o)
+{
+    const uint64_t HB = 1ull << (m - 1);
+    const uint64_t ALL = ~0ull >> (64 - m);
+    uint32_t cnt = 0;
+    int pos = lo;
+    while (pos <= hi) {
+        int j = m, last = m;
+        uint64_t D = ALL;
+        const uint8_t *w = lds8 + li0 + pos;
+        do {
+            j--;
+            D &= B[w[j]];
+            if (D & HB) {
+                if (j > 0) {
+                    last = j;
+                } else {
+                    if (WRITE) o.put(pos); else cnt++;
+                    break;
+                }
+            }
+            D <<= 1;
+        } while (D != 0 && j > 0);
+        pos += last;
+    }
+    return cnt;
+}
+
+// SBNDM: same masks; no prefix tracking; shift m-k+1 when the k-byte suffix is
+// not a factor of p; after a hit, shift by the smallest period of p.
+template <bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_sbndm(const uint8_t *lds8, const uint64_t *B, int m,
+                                              int period, int li0, int lo, int hi, E &o)
+{
+    const uint64_t HB = 1ull << (m - 1);
+    uint32_t cnt = 0;
+    int pos = lo;
+    while (pos <= hi) {
+        const uint8_t *w = lds8 + li0 + pos;  // window bytes w[0 .. m-1]
+        uint64_t D = B[w[m - 1]];
+        int k = 1;
+        while (D != 0 && k < m) {
+            D = (D << 1) & B[w[m - 1 - k]];
+            k++;
+        }
+        if (D & HB) {  // the whole window was read and equals p
+            if (WRITE) o.put(pos); else cnt++;
+            pos += period;
+        } else {
+            pos += m - k + 1;
+        }
+    }
+    return cnt;
+}
+
+// 16 bytes starting at byte address p, assembled from aligned words. Only words
+// whose first byte is <= last (the last byte that may be read) are loaded; the
+// others read as zero.
+__device__ __forceinline__ uint4 load16(const uint8_t *p, const uint8_t *last)
+{
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *W = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3);
+    const uintptr_t wl = (uintptr_t)last & ~(uintptr_t)3;  // last loadable word
+    uint32_t w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = ((uintptr_t)(W + k) <= wl) ? W[k] : 0u;
+    uint4 r;
+    r.x = alignbyte(w[1], w[0], sh);
+    r.y = alignbyte(w[2], w[1], sh);
+    r.z = alignbyte(w[3], w[2], sh);
+    r.w = alignbyte(w[4], w[3], sh);
+    return r;
+}
+
+// nonzero iff the first nb (<= 16) bytes of x and y differ
+__device__ __forceinline__ uint32_t diff16(uint4 x, uint4 y, uint32_t nb)
+{
+    uint32_t d = 0;
+    d |= (x.x ^ y.x) & byte_mask((int)nb);
+    d |= (x.y ^ y.y) & byte_mask((int)nb - 4 < 0 ? 0 : (int)nb - 4);
+    d |= (x.z ^ y.z) & byte_mask((int)nb - 8 < 0 ? 0 : (int)nb - 8);
+    d |= (x.w ^ y.w) & byte_mask((int)nb - 12 < 0 ? 0 : (int)nb - 12);
+    return d;
+}
+
+// Compare t[g + off, g + off + len) with p[off, off + len) for len <= 16, where
+// g is the window's global start and the window [g, g + m) lies inside the text.
+__device__ __forceinline__ bool verify_lane16(const uint8_t *text, uint64_t g, const uint8_t *pat,
+                                              uint32_t m, uint32_t off, uint32_t len)
+{
+    return diff16(load16(text + g + off, text + g + m - 1), load16(pat + off, pat + m + 15), len) == 0;
+}
+
+// The same comparison, any len, by a whole wave: lane k takes bytes [16k, 16k + 16) of
+// each 1024-byte block. Every lane of the wave must call it with the same
+// arguments; the result is the same on all lanes.
+__device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, const uint8_t *pat,
+                                            uint32_t m, uint32_t off, uint32_t len)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint8_t *tlast = text + g + m - 1;
+    const uint8_t *plast = pat + m + 15;
+    uint32_t d = 0;
+    for (uint32_t b = 0; b < len; b += 1024) {
+        const uint32_t o = b + 16 * lane;
+        if (o < len)
+            d |= diff16(load16(text + g + off + o, tlast), load16(pat + off + o, plast),
+                        len - o < 16 ? len - o : 16);
+        if (__ballot(d != 0)) return false;
+    }
+    return true;
+}
+
+// Hash-q over the lane's windows. The LDS holds text positions from m-q on;
+// li0 is the LDS index of relative position 0 (may be negative).
+// Wave-cooperative: all 64 lanes of the wave call it (lanes without starts have
+// lo > hi). A lane advances to its next candidate window (zero shift); a
+// candidate is settled by the pattern's period when possible (two occurrences are
+// at least the smallest period apart, period_lb bounds it from below; at distance
+// exactly `period` -- the smallest period when known, else 0 -- from a verified
+// occurrence only the last `period` bytes are new), by the lane itself when at most 64
+// bytes remain to compare, and otherwise by the whole wave.
+template <int NW, bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint8_t *shift, int m,
+                                              int q, int hbits, int sh1, int period, int period_lb,
+                                              int li0, int lo, int hi, const uint8_t *text,
+                                              uint64_t s, const uint8_t *pat, E &o)
+{
+    uint32_t cnt = 0;
+    int pos = lo;
+    bool active = lo <= hi;
+    bool have_prev = false;  // a verified occurrence of this lane at prev
+    int prev = 0;
+    for (;;) {
+        // 1. next candidate of this lane
+        bool cand = false;
+        while (active && !cand) {
+            const int gs = li0 + pos + m - q;  // LDS index of the q-gram's first byte
+            const int wi = gs >> 2, sb = gs & 3;
+            uint32_t d[NW + 1];
+#pragma unroll
+            for (int k = 0; k <= NW; k++) d[k] = lds32[wi + k];
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int k = 0; k < NW; k++)
+                w[k] = alignbyte(d[k + 1], d[k], (uint32_t)sb) & byte_mask(q - 4 * k);
+            const int sh = shift[qhash(w[0], w[1], w[2], w[3], (uint32_t)hbits)];
+            if (sh == 0) {
+                cand = true;
+            } else {
+                pos += sh;
+                active = pos <= hi;
+            }
+        }
+        // 2. settle it: period rule, lane check, or mark for the wave
+        bool hit = false, need_wave = false;
+        uint32_t voff = 0, vlen = (uint32_t)m;
+        if (cand) {
+            const int dist = pos - prev;
+            if (have_prev && dist < period_lb) {
+                hit = false;  // closer than the smallest period to an occurrence: impossible
+            } else {
+                if (have_prev && dist == period && period < m) {
+                    voff = (uint32_t)(m - period);
+                    vlen = (uint32_t)period;
+                }
+                if (vlen <= 16) hit = verify_lane16(text, s + (uint64_t)pos, pat, (uint32_t)m, voff, vlen);
+                else need_wave = true;
+            }
+        }
+        uint64_t pend = __ballot(need_wave);
+        while (pend) {
+            const int k = __builtin_ctzll(pend);
+            pend &= pend - 1;
+            const int kpos = __shfl(pos, k, 64);
+            const uint32_t koff = __shfl(voff, k, 64), klen = __shfl(vlen, k, 64);
+            const bool ok = verify_wave(text, s + (uint64_t)kpos, pat, (uint32_t)m, koff, klen);
+            if ((int)(threadIdx.x & 63) == k) hit = ok;
+        }
+        // 3. record and move on
+        if (cand) {
+            if (hit) {
+                if (WRITE) o.put(pos); else cnt++;
+                have_prev = true;
+                prev = pos;
+            }
+            pos += sh1;
+            active = pos <= hi;
+        }
+        if (!__ballot(active)) break;
+    }
+    return cnt;
+}
+
+// Tables of one pattern (masks, Hash-q shift table and sh1, period bounds) into
+// *P, by one whole workgroup of BLOCK threads. pp: the pattern (global or LDS);
+// s_tab: LDS scratch of 1 << H_MAX words; s_bad: LDS scratch of PERIOD_MAX + 1.
+__device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint32_t algo,
+                                             uint32_t q_, uint32_t hbits, Params *P,
+                                             uint32_t *s_tab, uint32_t *s_bad)
+{
+    const int tid = threadIdx.x;
+    if (algo == ALGO_SHIFT_AND) {
+        // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear
+        const uint32_t c = tid;
+        uint64_t w = 0;
+        for (uint32_t j = 0; j < m; j++)
+            if (pp[j] != c) w |= 1ull << j;
+        P->mask[c] = w;
+    } else if (algo == ALGO_BNDM || algo == ALGO_SBNDM) {
+        const uint32_t c = tid;
+        uint64_t w = 0;
+        for (uint32_t i = 0; i < m; i++)
+            if (pp[m - 1 - i] == c) w |= 1ull << i;
+        P->mask[c] = w;
+    } else if (algo == ALGO_HASHQ) {
+        const uint32_t q = q_, hb = hbits, nb = 1u << hb;
+        const uint32_t dflt = m - q + 1;
+        for (uint32_t k = tid; k < nb; k += BLOCK) s_tab[k] = dflt;
+        __syncthreads();
+        // q-grams ending at j = q-1 .. m-2 (all but the last)
+        for (uint32_t j = q - 1 + tid; j + 1 < m; j += BLOCK) {
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (uint32_t k = 0; k < q; k++) w[k >> 2] |= (uint32_t)pp[j + 1 - q + k] << (8 * (k & 3));
+            atomicMin(&s_tab[qhash(w[0], w[1], w[2], w[3], hb)], m - 1 - j);
+        }
+        __syncthreads();
+        uint32_t hl;
+        {
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (uint32_t k = 0; k < q; k++) w[k >> 2] |= (uint32_t)pp[m - q + k] << (8 * (k & 3));
+            hl = qhash(w[0], w[1], w[2], w[3], hb);
+        }
+        if (tid == 0) P->sh1 = s_tab[hl];
+        __syncthreads();
+        for (uint32_t k = tid; k < nb; k += BLOCK) {
+            uint32_t v = (k == hl) ? 0u : s_tab[k];
+            P->shift[k] = (uint8_t)(v > 255u ? 255u : v);
+        }
+    }
+
+    // Smallest period of p among 1..PERIOD_MAX: d is a period iff p[i] == p[i+d]
+    // for all i < m - d. Four threads test each d. period = that d, or m when p
+    // has no proper period <= m-1 (only decided for m <= PERIOD_MAX + 1), else 0
+    // (unknown); period_lb is a lower bound on the smallest period.
+    if (tid <= PERIOD_MAX) s_bad[tid] = 0;
+    __syncthreads();
+    {
+        const uint32_t d = 1 + (tid >> 2), part = tid & 3;
+        if (d <= PERIOD_MAX && d < m) {
+            const uint32_t len = m - d;
+            const uint32_t per = (len + 3) / 4;
+            const uint32_t b = part * per, e = b + per < len ? b + per : len;
+            for (uint32_t i = b; i < e; i++)
+                if (pp[i] != pp[i + d]) {
+                    s_bad[d] = 1;
+                    break;
+                }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t per = 0;
+        for (uint32_t d = 1; d <= PERIOD_MAX && d < m; d++)
+            if (!s_bad[d]) {
+                per = d;
+                break;
+            }
+        if (per == 0 && m <= PERIOD_MAX + 1) per = m;
+        P->period = per;
+        P->period_lb = per ? per : PERIOD_MAX + 1;
+    }
+}
+
+}  // namespace dev
+}  // namespace sm

@@ -107,6 +107,73 @@ struct FindWs {
     uint64_t ntiles;
 };
 
+// ---------------------------------------------------------------------------
+// Batched multi-pattern search (sm_batch.hip / sm_batch.cpp)
+// ---------------------------------------------------------------------------
+constexpr int BATCH_LANE = 64;           // starts per lane
+constexpr int BATCH_MAX_M = 2048;        // longest pattern handled inside a batch launch
+constexpr int BATCH_TABLE_BYTES = 32768; // LDS for a group's tables
+constexpr int BATCH_GROUP_MAX = 32;      // patterns per group
+constexpr int BATCH_HBITS_MAX = 10;      // Hash-q table bits inside a batch (1 KB per pattern)
+
+struct BatchPat {      // one pattern, in the batch's sorted order
+    uint64_t pat_off;  // offset of its bytes in the device pattern buffer (16-byte aligned)
+    uint32_t m, algo, var, q, hbits;
+    uint32_t index;    // position in the caller's list
+};
+
+struct BatchGroup {    // consecutive sorted patterns that share a kernel variant
+    uint32_t first, count, algo, var, max_m, pad;
+};
+
+struct BatchLaunch {
+    const uint8_t *text;
+    uint64_t n;
+    const BatchPat *pats;
+    const BatchGroup *groups;
+    const BatchGroup *host_groups;
+    const Params *params;
+    const uint8_t *patbytes;
+    uint32_t npats;        // patterns in this launch set (sorted)
+    uint32_t npats_total;  // entries of totals / csr (caller's P)
+    uint32_t ngroups;
+    uint32_t chunk_tiles;
+    uint64_t nchunks, ntiles;
+    uint32_t *cnt;
+    const uint64_t *chunk_off;  // write: per (pattern, chunk) offsets
+    uint64_t *chunk_off_out;    // count: where the segmented scan writes them (may be null)
+    uint64_t *totals;           // count: per original index
+    uint64_t *csr_out;          // count: exclusive scan of totals, P + 1 entries (may be null)
+    const uint64_t *csr;        // write: CSR offsets by original index
+    int64_t *out;
+    uint64_t cap;
+    bool write, prep;
+};
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream);
+// csr[0..P] = exclusive scan of totals[0..P)
+hipError_t launch_csr_scan(const uint64_t *totals, uint64_t P, uint64_t *csr, hipStream_t stream);
+
+}  // namespace sm
+
+// A device-resident text (see sm_corpus_open).
+struct sm_corpus {
+    const uint8_t *d_text = nullptr;
+    uint64_t n = 0;
+    bool owned = false;
+    uint64_t hist[256];
+    int32_t sigma = 0;        // distinct bytes
+    double sigma_eff = 0;     // 1 / sum_c p_c^2: alphabet size with the same collision rate
+    int dev = 0;
+};
+
+namespace sm {
+// The corpus's sigma_eff rounded to [1, 256] (planner input).
+int corpus_sigma(const sm_corpus *c);
+
+// Plan one pattern as the single-pattern path would (sigma from the corpus).
+int plan_pattern(const uint8_t *pat, uint64_t m, int sigma, Plan &p);
+const char *sm_set_error(int status, const char *msg);
+
 // Kernel launchers (sm_kernels.hip). All are asynchronous on `stream` and
 // return the HIP error of the launch.
 // Builds the pattern's tables in d_params; zeroes *d_zero when not null.

@@ -1,0 +1,130 @@
+"""GPU parity of the batched multi-pattern search against the CPU oracle.
+
+Each pattern's slice of the batch output must equal the oracle's list for that
+pattern alone (exact), whatever else is in the batch and in whatever order.
+"""
+import numpy as np
+import pytest
+
+import datagen as dg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1012_2547_amd as sm
+    sm.version()
+    return sm
+
+
+def mixed_patterns(text, count, seed, long_ones=True):
+    ms = dg.log_uniform_lengths(count, 1, 1024, seed=seed)
+    pats = []
+    for i, m in enumerate(ms):
+        m = int(m)
+        if i % 2 == 0:
+            pats.append(dg.substring_pattern(text, m, seed=seed, idx=i)[0])
+        else:
+            pats.append(dg.random_pattern(m, int(text.max()) + 1, seed=seed, idx=i))
+    if long_ones:
+        pats.append(dg.substring_pattern(text, 2500, seed=seed, idx=10_000)[0])  # beyond the batch limit
+        pats.append(bytes(text[:3000]))
+        pats.append(bytes(len(text) + 5))        # longer than the text
+    pats.append(pats[0])                          # duplicate
+    return pats
+
+
+def check_csr(sm, t_np, pats, pos, off, cap=None):
+    P = len(pats)
+    assert off[0] == 0 and np.all(np.diff(off.astype(np.int64)) >= 0)
+    want_all = [oracle.find_all(t_np, p) for p in pats]
+    assert [int(off[i + 1] - off[i]) for i in range(P)] == [w.size for w in want_all]
+    flat = np.concatenate(want_all) if want_all else np.empty(0, np.int64)
+    lim = flat.size if cap is None else min(cap, flat.size)
+    assert pos.size == lim
+    assert np.array_equal(pos, flat[:lim])
+
+
+@pytest.mark.parametrize("sigma", [2, 4, 64])
+def test_batch_count_and_find_all(sm, sigma):
+    t_np = dg.uniform_text(300_001, sigma, seed=21 + sigma)
+    pats = mixed_patterns(t_np, 160, seed=sigma)
+    c = sm.Corpus(t_np)
+    counts = c.batch_count(pats)
+    want = np.array([oracle.count(t_np, p) for p in pats], dtype=np.uint64)
+    assert np.array_equal(counts, want)
+    pos, off = c.batch_find_all(pats)
+    check_csr(sm, t_np, pats, pos, off)
+    c.close()
+
+
+def test_batch_order_invariance_and_truncation(sm):
+    t_np = dg.zipf_text(200_000, 64, 1.0, seed=5)
+    pats = mixed_patterns(t_np, 120, seed=9)
+    c = sm.Corpus(t_np)
+    pos, off = c.batch_find_all(pats)
+    perm = np.random.default_rng(1).permutation(len(pats))
+    pos2, off2 = c.batch_find_all([pats[i] for i in perm])
+    for k, i in enumerate(perm):
+        a = pos[off[i]:off[i + 1]]
+        b = pos2[off2[k]:off2[k + 1]]
+        assert np.array_equal(a, b), i
+    total = int(off[-1])
+    for cap in (0, 1, total // 3, total - 1):
+        pc, oc = c.batch_find_all(pats, cap=cap)
+        assert np.array_equal(oc, off)
+        assert np.array_equal(pc, pos[:cap])
+    c.close()
+
+
+def test_batch_dense_and_periodic(sm):
+    n = 200_003
+    t_np = np.full(n, ord("a"), dtype=np.uint8)
+    t_np[4095::4096] = ord("b")
+    pats = [b"a" * m for m in (1, 2, 3, 4, 16, 64, 65, 200, 1024)] + \
+           [b"a" * (m - 1) + b"b" for m in (2, 4, 16, 64, 256, 1024)] + [b"b", b"ab", b"ba"]
+    c = sm.Corpus(t_np)
+    pos, off = c.batch_find_all(pats)
+    check_csr(sm, t_np, pats, pos, off)
+    c.close()
+
+
+def test_batch_async_forms(sm):
+    t_np = dg.uniform_text(500_000, 4, seed=77)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    pats = mixed_patterns(t_np, 100, seed=3, long_ones=False)
+    c = sm.Corpus(t_dev)
+    work = torch.empty(c.batch_workspace_size(pats), dtype=torch.uint8, device=DEV)
+    d_counts = torch.zeros(len(pats), dtype=torch.int64, device=DEV)
+    c.batch_count_async(pats, d_counts, work)
+    counts = d_counts.cpu().numpy().astype(np.uint64)
+    want = np.array([oracle.count(t_np, p) for p in pats], dtype=np.uint64)
+    assert np.array_equal(counts, want)
+    total = int(want.sum())
+    d_out = torch.full((total + 7,), -1, dtype=torch.int64, device=DEV)
+    d_off = torch.zeros(len(pats) + 1, dtype=torch.int64, device=DEV)
+    c.batch_find_all_async(pats, d_out[:total], d_off, work)
+    off = d_off.cpu().numpy().astype(np.uint64)
+    pos = d_out[:total].cpu().numpy()
+    assert np.all(d_out[total:].cpu().numpy() == -1)
+    check_csr(sm, t_np, pats, pos, off)
+    c.close()
+
+
+def test_batch_matches_single_path(sm):
+    t_np = dg.uniform_text(1 << 20, 16, seed=31)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    pats = mixed_patterns(t_np, 64, seed=12, long_ones=False)
+    c = sm.Corpus(t_dev)
+    pos, off = c.batch_find_all(pats)
+    for i, p in enumerate(pats):
+        single = sm.find_all(t_dev, p).cpu().numpy()
+        assert np.array_equal(pos[off[i]:off[i + 1]], single), i
+    c.close()
