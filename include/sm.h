@@ -163,6 +163,99 @@ int sm_batch_find_all_async(sm_corpus *corpus, const uint8_t *pats, const uint64
                             void *d_work, uint64_t work_bytes, void *stream);
 
 /*
+ * Batch handle: the count step of a batched find_all, kept so that the output
+ * can be written in windows (waves) of any size. sm_batch_open plans the
+ * patterns (as sm_batch_find_all), allocates the batch's workspace, counts
+ * every pattern and keeps the CSR offsets (synchronous). sm_batch_offsets
+ * copies them (P + 1 entries) to the host. sm_batch_write_async writes the CSR
+ * entries [lo, hi) (0 <= lo <= hi <= total) to the device buffer d_out[0 ..
+ * hi - lo), enqueued on `stream`: pattern i's positions are entries out_off[i]
+ * .. out_off[i+1], ascending. Writes on one batch share its workspace and must
+ * not overlap in time (one stream, or waits between them). The library copies
+ * the patterns at open; sm_batch_close waits for the device and frees the batch.
+ *
+ * sm_batch_find_all writes through the same windows, in waves of at most the
+ * budget set by sm_batch_set_wave_bytes (default 16 GiB, 0 restores it; it is
+ * also kept below half of the free device memory), so the device never holds
+ * the whole output.
+ */
+typedef struct sm_batch sm_batch;
+int sm_batch_open(sm_corpus *corpus, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+                  sm_batch **batch);
+int sm_batch_offsets(const sm_batch *batch, uint64_t *out_off);
+int sm_batch_write_async(sm_batch *batch, uint64_t lo, uint64_t hi, int64_t *d_out, void *stream);
+int sm_batch_close(sm_batch *batch);
+int sm_batch_set_wave_bytes(uint64_t bytes);
+
+/*
+ * Server: continuous batching of single-pattern queries over resident corpora
+ * (the paper's workload, Section 3, one pattern per query, served many at a
+ * time). Queries are queued per corpus; a scheduler thread batches the queued
+ * queries of one corpus (oldest first, at most max_batch) through the batched
+ * search on one of `slots` pipeline slots (own HIP stream, workspace and
+ * pool_bytes / slots of device output staging), so the count pass of one batch
+ * overlaps the writes and copies of the previous one. The exact output size
+ * from the count step admits each batch: host result space comes from a pinned
+ * arena of host_bytes (a dedicated pinned buffer when it does not fit) and the
+ * positions are written in waves of at most the slot's staging size.
+ *
+ * sm_server_create: zero fields take defaults (pool 16 GiB, host arena 2 GiB,
+ *   max_batch 256, 2 slots, max_pending 2^20 queued queries); the server runs on
+ *   the current HIP device.
+ * sm_server_add_corpus: registers an open corpus (borrowed: keep it open until
+ *   sm_server_destroy); ids are 0, 1, ...
+ * sm_server_submit: copies the pattern and queues the query; arrival_ns is its
+ *   arrival time on sm_now_ns's clock (<= 0: now) and latency is measured from
+ *   it. SM_EBUSY when max_pending queries are queued. Thread-safe.
+ * sm_server_wait: waits up to timeout_us (< 0: forever) for the query; SM_OK
+ *   with *res filled, SM_EBUSY if it is still running, or the query's error.
+ *   res->positions (res->count entries, ascending) is library-owned host memory,
+ *   valid until sm_result_free(ticket). sm_server_poll = wait with timeout 0.
+ * sm_server_stats: latency percentiles (arrival to positions on the host) of
+ *   the queries completed since the last reset, and throughput.
+ * sm_server_destroy: drops queued queries, finishes dispatched ones, frees all.
+ */
+typedef struct sm_server sm_server;
+typedef struct sm_server_config {
+    uint64_t pool_bytes;   /* device output staging, split across the slots */
+    uint64_t host_bytes;   /* pinned host result arena */
+    uint32_t max_batch;    /* queries per batch */
+    uint32_t slots;        /* pipeline slots (streams), 1..8 */
+    uint32_t max_pending;  /* queued queries before submit returns SM_EBUSY */
+    uint32_t reserved[5];  /* must be zero */
+} sm_server_config;
+typedef struct sm_result {
+    int32_t status;
+    uint32_t corpus;
+    uint64_t count;             /* occurrences */
+    const int64_t *positions;   /* count ascending positions (host, library-owned) */
+    int64_t arrival_ns, start_ns, done_ns;  /* arrival, batch dispatch, results on host */
+    uint32_t batch_size;        /* queries in its batch */
+    uint32_t reserved;
+} sm_result;
+typedef struct sm_server_metrics {
+    uint64_t completed, pending, batches, batched_queries;
+    uint64_t text_bytes;        /* sum over completed batches of n x queries (pattern-bytes) */
+    uint64_t out_bytes;         /* positions written, bytes */
+    uint64_t write_waves, overflow_allocs;
+    int64_t p50_ns, p99_ns, p999_ns, max_ns;
+    double mean_ns;
+    int64_t span_ns;            /* first arrival to last completion */
+    double qps;                 /* completed / span */
+} sm_server_metrics;
+int64_t sm_now_ns(void);
+int sm_server_create(const sm_server_config *cfg, sm_server **server);
+int sm_server_add_corpus(sm_server *server, sm_corpus *corpus, uint32_t *corpus_id);
+int sm_server_submit(sm_server *server, uint32_t corpus_id, const uint8_t *pat, uint64_t m,
+                     int64_t arrival_ns, uint64_t *ticket);
+int sm_server_wait(sm_server *server, uint64_t ticket, int64_t timeout_us, sm_result *res);
+int sm_server_poll(sm_server *server, uint64_t ticket, sm_result *res);
+int sm_result_free(sm_server *server, uint64_t ticket);
+int sm_server_stats(sm_server *server, sm_server_metrics *stats);
+int sm_server_reset_stats(sm_server *server);
+int sm_server_destroy(sm_server *server);
+
+/*
  * Planner tuning table. The planner picks the first entry whose alphabet-size
  * range and pattern-length range contain (sigma, m); sigma is the corpus's
  * sigma_eff, opts->sigma_hint, or an estimate from the pattern's byte counts.

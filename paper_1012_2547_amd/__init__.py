@@ -20,7 +20,8 @@ from ._native import (ALGO_AUTO, ALGO_BNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
 
 __all__ = ["pack_patterns", "find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
-           "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version"]
+           "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version",
+           "Batch", "Server", "batch_set_wave_bytes", "now_ns"]
 
 
 def version() -> str:
@@ -262,6 +263,10 @@ class Corpus:
             d_out.numel() if d_out is not None else 0, _vp(d_out_off), _vp(work), work.numel(),
             _stream_ptr(stream)))
 
+    def batch_open(self, patterns) -> "Batch":
+        """Count step of a batched find_all, kept for windowed writes (sm_batch_open)."""
+        return Batch(self, patterns)
+
     def count(self, pat) -> int:
         b, m = _pat(pat)
         c = ctypes.c_uint64(0)
@@ -277,6 +282,120 @@ class Corpus:
         check(load().sm_corpus_find_all(self._h, _pat_ptr(b), m, ctypes.c_void_p(out.ctypes.data),
                                         cap, ctypes.byref(c)))
         return out[:min(int(c.value), cap)]
+
+
+class Batch:
+    """Counted batch whose CSR output is written in windows (sm_batch_*)."""
+
+    def __init__(self, corpus: Corpus, patterns):
+        buf, off = pack_patterns(patterns)
+        self.P = len(off) - 1
+        self._corpus = corpus  # the corpus must outlive the batch
+        self._h = ctypes.c_void_p(0)
+        check(load().sm_batch_open(corpus.handle, _vp(buf), _vp(off), self.P, ctypes.byref(self._h)))
+        self.offsets = np.zeros(self.P + 1, dtype=np.uint64)
+        check(load().sm_batch_offsets(self._h, _vp(self.offsets)))
+        self.total = int(self.offsets[-1])
+
+    def write_async(self, lo: int, hi: int, d_out, stream=None) -> int:
+        """CSR entries [lo, hi) -> d_out[0:hi-lo] (device tensor), enqueued on stream."""
+        return check(load().sm_batch_write_async(
+            self._h, lo, hi, ctypes.c_void_p(d_out.data_ptr() if hi > lo else 0), _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            check(load().sm_batch_close(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_set_wave_bytes(nbytes: int) -> None:
+    """Output-wave budget of the synchronous batched find_all (0 = default 16 GiB)."""
+    check(load().sm_batch_set_wave_bytes(nbytes))
+
+
+def now_ns() -> int:
+    """The server's clock (CLOCK_MONOTONIC, ns)."""
+    return int(load().sm_now_ns())
+
+
+class Server:
+    """Continuous-batching query server over resident corpora (sm_server_*).
+
+    submit() queues a query and returns a ticket; wait(ticket) returns
+    (count, positions as a numpy view of library memory, result fields); the view
+    is valid until free(ticket) (result() copies and frees in one call)."""
+
+    def __init__(self, pool_bytes: int = 0, host_bytes: int = 0, max_batch: int = 0, slots: int = 0,
+                 max_pending: int = 0):
+        from ._native import ServerConfig
+        cfg = ServerConfig()
+        cfg.pool_bytes, cfg.host_bytes, cfg.max_batch = pool_bytes, host_bytes, max_batch
+        cfg.slots, cfg.max_pending = slots, max_pending
+        self._h = ctypes.c_void_p(0)
+        self._corpora = []
+        check(load().sm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def add_corpus(self, corpus: Corpus) -> int:
+        cid = ctypes.c_uint32(0)
+        check(load().sm_server_add_corpus(self._h, corpus.handle, ctypes.byref(cid)))
+        self._corpora.append(corpus)  # kept open while the server runs
+        return int(cid.value)
+
+    def submit(self, corpus_id: int, pat, arrival_ns: int = 0) -> int:
+        b, m = _pat(pat)
+        t = ctypes.c_uint64(0)
+        check(load().sm_server_submit(self._h, corpus_id, _pat_ptr(b), m, arrival_ns, ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """(count, positions view or None if still running, fields dict)."""
+        from ._native import Result
+        r = Result()
+        st = load().sm_server_wait(self._h, ticket, timeout_us, ctypes.byref(r))
+        if st == -4 and r.done_ns == 0:  # SM_EBUSY: still running
+            return None
+        check(st)
+        pos = (np.ctypeslib.as_array(r.positions, shape=(r.count,)) if r.count
+               else np.empty(0, dtype=np.int64))
+        return int(r.count), pos, {"arrival_ns": r.arrival_ns, "start_ns": r.start_ns,
+                                   "done_ns": r.done_ns, "batch_size": r.batch_size,
+                                   "corpus": r.corpus}
+
+    def free(self, ticket: int) -> None:
+        check(load().sm_result_free(self._h, ticket))
+
+    def result(self, ticket: int) -> np.ndarray:
+        """Wait, copy the positions out and free the result."""
+        _, pos, _ = self.wait(ticket)
+        out = pos.copy()
+        self.free(ticket)
+        return out
+
+    def stats(self) -> dict:
+        from ._native import ServerMetrics
+        s = ServerMetrics()
+        check(load().sm_server_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerMetrics._fields_}
+
+    def reset_stats(self) -> None:
+        check(load().sm_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            check(load().sm_server_destroy(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_get() -> list[dict]:

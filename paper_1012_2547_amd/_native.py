@@ -48,6 +48,31 @@ class Prof(ctypes.Structure):
                 ("text_bytes", ctypes.c_uint64)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64),
+                ("max_batch", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("max_pending", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("corpus", ctypes.c_uint32),
+                ("count", ctypes.c_uint64), ("positions", ctypes.POINTER(ctypes.c_int64)),
+                ("arrival_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch_size", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ServerMetrics(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("batched_queries", ctypes.c_uint64),
+                ("text_bytes", ctypes.c_uint64), ("out_bytes", ctypes.c_uint64),
+                ("write_waves", ctypes.c_uint64), ("overflow_allocs", ctypes.c_uint64),
+                ("p50_ns", ctypes.c_int64), ("p99_ns", ctypes.c_int64),
+                ("p999_ns", ctypes.c_int64), ("max_ns", ctypes.c_int64),
+                ("mean_ns", ctypes.c_double), ("span_ns", ctypes.c_int64),
+                ("qps", ctypes.c_double)]
+
+
 # every exported symbol and its prototype: (restype, argtypes)
 _vp, _u64, _i32, _u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32
 _pu64 = ctypes.POINTER(ctypes.c_uint64)
@@ -80,6 +105,21 @@ PROTOTYPES = {
     "sm_batch_find_all": (_i32, [_vp, _vp, _vp, _u32, _vp, _u64, _vp]),
     "sm_batch_count_async": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _u64, _vp]),
     "sm_batch_find_all_async": (_i32, [_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _u64, _vp]),
+    "sm_batch_open": (_i32, [_vp, _vp, _vp, _u32, ctypes.POINTER(_vp)]),
+    "sm_batch_offsets": (_i32, [_vp, _vp]),
+    "sm_batch_write_async": (_i32, [_vp, _u64, _u64, _vp, _vp]),
+    "sm_batch_close": (_i32, [_vp]),
+    "sm_batch_set_wave_bytes": (_i32, [_u64]),
+    "sm_now_ns": (ctypes.c_int64, []),
+    "sm_server_create": (_i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    "sm_server_add_corpus": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "sm_server_submit": (_i32, [_vp, _u32, _vp, _u64, ctypes.c_int64, _pu64]),
+    "sm_server_wait": (_i32, [_vp, _u64, ctypes.c_int64, ctypes.POINTER(Result)]),
+    "sm_server_poll": (_i32, [_vp, _u64, ctypes.POINTER(Result)]),
+    "sm_result_free": (_i32, [_vp, _u64]),
+    "sm_server_stats": (_i32, [_vp, ctypes.POINTER(ServerMetrics)]),
+    "sm_server_reset_stats": (_i32, [_vp]),
+    "sm_server_destroy": (_i32, [_vp]),
     "sm_prof_enable": (_i32, [_i32]),
     "sm_prof_collect": (_i32, [ctypes.POINTER(Prof)]),
 }

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sm_kernels.hip", "sm_batch.hip", "sm_api.cpp", "sm_batch.cpp"]
+SOURCES = ["sm_kernels.hip", "sm_batch.hip", "sm_api.cpp", "sm_batch.cpp", "sm_server.cpp"]
 
 # Packed-FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

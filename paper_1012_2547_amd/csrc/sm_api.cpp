@@ -316,7 +316,7 @@ extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opt
 static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
                      int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
                      uint64_t work_bytes, const sm_opts *opts, hipStream_t st, bool write,
-                     int sigma_known)
+                     int sigma_known, uint64_t first = 0)
 {
     int r = validate_common(d_text, n, pat, m);
     if (r) return r;
@@ -363,7 +363,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, st));
     if (prof) HIP_TRY(hipEventRecord(rec.e1, st));
     if (write) {
-        HIP_TRY(launch_find(plan, d_text, n, prm, dpat, fw, d_out, cap, d_count, st,
+        HIP_TRY(launch_find(plan, d_text, n, prm, dpat, fw, d_out, first, cap, d_count, st,
                             prof ? rec.e2 : nullptr));
     } else {
         HIP_TRY(launch_count(plan, d_text, n, prm, dpat, fw, d_count, st, prof ? rec.e2 : nullptr));
@@ -635,6 +635,15 @@ extern "C" int sm_corpus_find_all_async(sm_corpus *c, const uint8_t *pat, uint64
     if (!c) return fail(SM_EINVAL, "corpus is NULL");
     return run_async(c->d_text, c->n, pat, m, d_out, cap, d_count, d_work, work_bytes, opts,
                      (hipStream_t)stream, true, corpus_sigma(c));
+}
+
+int sm::corpus_find_window_async(sm_corpus *c, const uint8_t *pat, uint64_t m, int64_t *d_out,
+                                 uint64_t first, uint64_t cap, uint64_t *d_count, void *d_work,
+                                 uint64_t work_bytes, hipStream_t stream)
+{
+    if (!c) return fail(SM_EINVAL, "corpus is NULL");
+    return run_async(c->d_text, c->n, pat, m, d_out, cap, d_count, d_work, work_bytes, nullptr,
+                     stream, true, corpus_sigma(c), first);
 }
 
 extern "C" int sm_corpus_count_async(sm_corpus *c, const uint8_t *pat, uint64_t m, uint64_t *d_count,

@@ -1,21 +1,22 @@
 // C ABI of the batched multi-pattern search: planning and grouping of the
-// patterns, workspace layout, launches (sm_batch.hip) and the synchronous forms.
+// patterns, workspace layout, the count and windowed write steps (kernels in
+// sm_batch.hip), the batch handle and the synchronous forms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <new>
 #include <vector>
 
 #include "../../include/sm.h"
-#include "sm_internal.h"
+#include "sm_batch_host.h"
 
 using namespace sm;
 
-namespace {
-
-int err(int status, const char *fmt, ...)
+int sm::batch_err(int status, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -26,6 +27,8 @@ int err(int status, const char *fmt, ...)
     return status;
 }
 
+#define err sm::batch_err
+
 #define HIP_OK(expr)                                                                        \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \
@@ -33,6 +36,8 @@ int err(int status, const char *fmt, ...)
             return err(e_ == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE, "%s: %s", #expr, \
                        hipGetErrorString(e_));                                              \
     } while (0)
+
+namespace {
 
 constexpr uint64_t BT = (uint64_t)BLOCK * BATCH_LANE;
 
@@ -51,121 +56,27 @@ int table_bytes(uint32_t algo, uint32_t var)
 
 uint64_t pat_region(uint64_t m) { return align_up(m, 16) + 16; }  // verify reads 16 bytes past m
 
-struct HostPlan {
-    std::vector<BatchPat> pats;     // batch patterns, sorted by (algo, var, m)
-    std::vector<BatchGroup> groups;
-    std::vector<uint32_t> longp;    // m > BATCH_MAX_M: searched one at a time
-    uint64_t patbytes = 0;
-    uint32_t chunk_tiles = 1;
-    uint64_t nchunks = 0, ntiles = 0;
-};
-
-int build_plan(const sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
-               HostPlan &hp)
+BatchLayout layout_of(const BatchJob &j, uint64_t single)
 {
-    if (!pats || !pat_off) return err(SM_EINVAL, "patterns or offsets are NULL");
-    const int sigma = corpus_sigma(c);
-    uint64_t min_m = UINT64_MAX;
-    for (uint32_t i = 0; i < P; i++) {
-        if (pat_off[i + 1] < pat_off[i]) return err(SM_EINVAL, "pattern offsets decrease at %u", i);
-        const uint64_t m = pat_off[i + 1] - pat_off[i];
-        if (m == 0) return err(SM_EINVAL, "pattern %u is empty", i);
-        if (m > 0xFFFFFFFFull) return err(SM_EINVAL, "pattern %u is longer than 2^32-1", i);
-        if (m > c->n) continue;  // no occurrence
-        if (m > (uint64_t)BATCH_MAX_M) {
-            hp.longp.push_back(i);
-            continue;
-        }
-        Plan p;
-        int r = plan_pattern(pats + pat_off[i], m, sigma, p);
-        if (r) return r;
-        BatchPat bp;
-        memset(&bp, 0, sizeof bp);
-        bp.m = (uint32_t)m;
-        bp.algo = (uint32_t)p.algo;
-        bp.q = (uint32_t)p.q;
-        bp.hbits = (uint32_t)std::min(p.hbits, BATCH_HBITS_MAX);
-        bp.var = (uint32_t)var_of(p);
-        bp.index = i;
-        hp.pats.push_back(bp);
-        min_m = std::min<uint64_t>(min_m, m);
-    }
-    std::stable_sort(hp.pats.begin(), hp.pats.end(), [](const BatchPat &x, const BatchPat &y) {
-        if (x.algo != y.algo) return x.algo < y.algo;
-        if (x.var != y.var) return x.var < y.var;
-        return x.m < y.m;
-    });
-    uint64_t off = 0;
-    for (auto &bp : hp.pats) {
-        bp.pat_off = off;
-        off += pat_region(bp.m);
-    }
-    hp.patbytes = off;
-    for (uint32_t k = 0; k < hp.pats.size();) {
-        const BatchPat &b = hp.pats[k];
-        const uint32_t cap =
-            (uint32_t)std::min<int>(BATCH_GROUP_MAX, BATCH_TABLE_BYTES / table_bytes(b.algo, b.var));
-        BatchGroup g;
-        memset(&g, 0, sizeof g);
-        g.first = k;
-        g.algo = b.algo;
-        g.var = b.var;
-        while (k < hp.pats.size() && g.count < cap && hp.pats[k].algo == b.algo && hp.pats[k].var == b.var) {
-            g.max_m = std::max(g.max_m, hp.pats[k].m);
-            g.count++;
-            k++;
-        }
-        hp.groups.push_back(g);
-    }
-    if (!hp.pats.empty()) {
-        hp.ntiles = (c->n - min_m + 1 + BT - 1) / BT;
-        // aim for a few thousand (chunk, group) items
-        uint64_t want = hp.ntiles * hp.groups.size() / 4096;
-        uint32_t ct = 1;
-        while ((uint64_t)ct * 2 <= want && ct < 256) ct *= 2;
-        hp.chunk_tiles = ct;
-        hp.nchunks = (hp.ntiles + ct - 1) / ct;
-    }
-    return SM_OK;
-}
-
-struct Layout {
-    uint64_t pats, groups, params, patbytes, cnt, chunk_off, totals, csr, single, need;
-};
-
-uint64_t single_ws_need(const sm_corpus *c, const HostPlan &hp, const uint8_t *pats,
-                        const uint64_t *pat_off)
-{
-    uint64_t need = 0;
-    for (uint32_t i : hp.longp) {
-        const uint64_t m = pat_off[i + 1] - pat_off[i];
-        need = std::max(need, sm_workspace_size(c->n, m, nullptr));
-    }
-    (void)pats;
-    return need;
-}
-
-Layout layout_of(const HostPlan &hp, uint32_t P, uint64_t single)
-{
-    Layout L;
-    const uint64_t np = hp.pats.size();
+    BatchLayout L;
+    const uint64_t np = j.bpats.size();
     uint64_t o = 0;
     L.pats = o;
     o = align_up(o + np * sizeof(BatchPat), 256);
     L.groups = o;
-    o = align_up(o + hp.groups.size() * sizeof(BatchGroup), 256);
+    o = align_up(o + j.groups.size() * sizeof(BatchGroup), 256);
     L.params = o;
     o = align_up(o + np * sizeof(Params), 256);
     L.patbytes = o;
-    o = align_up(o + hp.patbytes, 256);
+    o = align_up(o + j.patbytes, 256);
     L.cnt = o;
-    o = align_up(o + np * hp.nchunks * 4, 256);
+    o = align_up(o + np * j.nchunks * 4, 256);
     L.chunk_off = o;
-    o = align_up(o + np * hp.nchunks * 8, 256);
+    o = align_up(o + np * j.nchunks * 8, 256);
     L.totals = o;
-    o = align_up(o + (uint64_t)P * 8, 256);
+    o = align_up(o + (uint64_t)j.P * 8, 256);
     L.csr = o;
-    o = align_up(o + ((uint64_t)P + 1) * 8, 256);
+    o = align_up(o + ((uint64_t)j.P + 1) * 8, 256);
     L.single = o;
     o = align_up(o + single, 256);
     L.need = o;
@@ -187,86 +98,25 @@ hipError_t fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st)
     return hipGetLastError();
 }
 
-// Uploads plan + pattern bytes and runs the count pass; totals -> d_totals (by
-// original index, all P entries), CSR -> d_csr when not null.
-int run_count(sm_corpus *c, const HostPlan &hp, const Layout &L, const uint8_t *pats,
-              const uint64_t *pat_off, uint32_t P, uint8_t *ws, uint64_t *d_totals, uint64_t *d_csr,
-              bool keep_chunk_off, hipStream_t st)
+BatchLaunch launch_of(const BatchJob &j, uint8_t *ws)
 {
-    HIP_OK(fill_u64(d_totals, P, 0, st));
-    if (!hp.pats.empty()) {
-        // pattern table, groups and pattern bytes: one host image, one copy
-        const uint64_t img = L.cnt;  // [pats .. patbytes] precede the count array
-        std::vector<uint8_t> h(img, 0);
-        memcpy(h.data() + L.pats, hp.pats.data(), hp.pats.size() * sizeof(BatchPat));
-        memcpy(h.data() + L.groups, hp.groups.data(), hp.groups.size() * sizeof(BatchGroup));
-        for (const auto &bp : hp.pats)
-            memcpy(h.data() + L.patbytes + bp.pat_off, pats + pat_off[bp.index], bp.m);
-        // the params region is written by the prep kernel; copy around it
-        HIP_OK(hipMemcpyAsync(ws, h.data(), L.params, hipMemcpyHostToDevice, st));
-        HIP_OK(hipMemcpyAsync(ws + L.patbytes, h.data() + L.patbytes, img - L.patbytes,
-                              hipMemcpyHostToDevice, st));
-        BatchLaunch B;
-        memset(&B, 0, sizeof B);
-        B.text = c->d_text;
-        B.n = c->n;
-        B.pats = reinterpret_cast<const BatchPat *>(ws + L.pats);
-        B.groups = reinterpret_cast<const BatchGroup *>(ws + L.groups);
-        B.host_groups = hp.groups.data();
-        B.params = reinterpret_cast<const Params *>(ws + L.params);
-        B.patbytes = ws + L.patbytes;
-        B.npats = (uint32_t)hp.pats.size();
-        B.npats_total = P;
-        B.ngroups = (uint32_t)hp.groups.size();
-        B.chunk_tiles = hp.chunk_tiles;
-        B.nchunks = hp.nchunks;
-        B.ntiles = hp.ntiles;
-        B.cnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
-        B.chunk_off_out = keep_chunk_off ? reinterpret_cast<uint64_t *>(ws + L.chunk_off) : nullptr;
-        B.totals = d_totals;
-        B.csr_out = nullptr;  // long patterns first, the CSR below
-        B.write = false;
-        B.prep = true;
-        HIP_OK(launch_batch(B, st));
-    }
-    for (uint32_t i : hp.longp) {
-        const uint64_t m = pat_off[i + 1] - pat_off[i];
-        const uint64_t single = L.need - L.single;
-        int r = sm_corpus_count_async(c, pats + pat_off[i], m, d_totals + i, ws + L.single, single,
-                                      nullptr, st);
-        if (r) return r;
-    }
-    if (d_csr) HIP_OK(launch_csr_scan(d_totals, P, d_csr, st));
-    return SM_OK;
-}
-
-int run_write(sm_corpus *c, const HostPlan &hp, const Layout &L, uint32_t P, uint8_t *ws,
-              const uint64_t *d_csr, int64_t *d_out, uint64_t cap, hipStream_t st)
-{
-    if (hp.pats.empty() || cap == 0) return SM_OK;
     BatchLaunch B;
     memset(&B, 0, sizeof B);
-    B.text = c->d_text;
-    B.n = c->n;
-    B.pats = reinterpret_cast<const BatchPat *>(ws + L.pats);
-    B.groups = reinterpret_cast<const BatchGroup *>(ws + L.groups);
-    B.host_groups = hp.groups.data();
-    B.params = reinterpret_cast<const Params *>(ws + L.params);
-    B.patbytes = ws + L.patbytes;
-    B.npats = (uint32_t)hp.pats.size();
-    B.npats_total = P;
-    B.ngroups = (uint32_t)hp.groups.size();
-    B.chunk_tiles = hp.chunk_tiles;
-    B.nchunks = hp.nchunks;
-    B.ntiles = hp.ntiles;
-    B.cnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
-    B.chunk_off = reinterpret_cast<const uint64_t *>(ws + L.chunk_off);
-    B.csr = d_csr;
-    B.out = d_out;
-    B.cap = cap;
-    B.write = true;
-    HIP_OK(launch_batch(B, st));
-    return SM_OK;
+    B.text = j.c->d_text;
+    B.n = j.c->n;
+    B.pats = reinterpret_cast<const BatchPat *>(ws + j.L.pats);
+    B.groups = reinterpret_cast<const BatchGroup *>(ws + j.L.groups);
+    B.host_groups = j.groups.data();
+    B.params = reinterpret_cast<const Params *>(ws + j.L.params);
+    B.patbytes = ws + j.L.patbytes;
+    B.npats = (uint32_t)j.bpats.size();
+    B.npats_total = j.P;
+    B.ngroups = (uint32_t)j.groups.size();
+    B.chunk_tiles = j.chunk_tiles;
+    B.nchunks = j.nchunks;
+    B.ntiles = j.ntiles;
+    B.cnt = reinterpret_cast<uint32_t *>(ws + j.L.cnt);
+    return B;
 }
 
 int check_corpus(const sm_corpus *c)
@@ -276,15 +126,260 @@ int check_corpus(const sm_corpus *c)
     return SM_OK;
 }
 
+int check_ws(const BatchJob &j, const void *d_work, uint64_t work_bytes)
+{
+    if (!d_work || work_bytes < j.L.need)
+        return err(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)j.L.need);
+    if ((uintptr_t)d_work & 255) return err(SM_EINVAL, "workspace must be 256-byte aligned");
+    return SM_OK;
+}
+
+struct DevFree {
+    void *p = nullptr;
+    ~DevFree()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+                   bool long_ws, BatchJob &j)
+{
+    if (!pats || !pat_off) return err(SM_EINVAL, "patterns or offsets are NULL");
+    j.c = c;
+    j.P = P;
+    j.pats = pats;
+    j.pat_off = pat_off;
+    const int sigma = corpus_sigma(c);
+    uint64_t min_m = UINT64_MAX, single = 0;
+    for (uint32_t i = 0; i < P; i++) {
+        if (pat_off[i + 1] < pat_off[i]) return err(SM_EINVAL, "pattern offsets decrease at %u", i);
+        const uint64_t m = pat_off[i + 1] - pat_off[i];
+        if (m == 0) return err(SM_EINVAL, "pattern %u is empty", i);
+        if (m > 0xFFFFFFFFull) return err(SM_EINVAL, "pattern %u is longer than 2^32-1", i);
+        if (m > c->n) continue;  // no occurrence
+        if (m > (uint64_t)BATCH_MAX_M) {
+            j.longp.push_back(i);
+            single = std::max(single, sm_workspace_size(c->n, m, nullptr));
+            continue;
+        }
+        Plan p;
+        int r = plan_pattern(pats + pat_off[i], m, sigma, p);
+        if (r) return r;
+        BatchPat bp;
+        memset(&bp, 0, sizeof bp);
+        bp.m = (uint32_t)m;
+        bp.algo = (uint32_t)p.algo;
+        bp.q = (uint32_t)p.q;
+        bp.hbits = (uint32_t)std::min(p.hbits, BATCH_HBITS_MAX);
+        bp.var = (uint32_t)var_of(p);
+        bp.index = i;
+        j.bpats.push_back(bp);
+        min_m = std::min<uint64_t>(min_m, m);
+    }
+    std::stable_sort(j.bpats.begin(), j.bpats.end(), [](const BatchPat &x, const BatchPat &y) {
+        if (x.algo != y.algo) return x.algo < y.algo;
+        if (x.var != y.var) return x.var < y.var;
+        return x.m < y.m;
+    });
+    uint64_t off = 0;
+    for (auto &bp : j.bpats) {
+        bp.pat_off = off;
+        off += pat_region(bp.m);
+    }
+    j.patbytes = off;
+    for (uint32_t k = 0; k < j.bpats.size();) {
+        const BatchPat &b = j.bpats[k];
+        const uint32_t cap =
+            (uint32_t)std::min<int>(BATCH_GROUP_MAX, BATCH_TABLE_BYTES / table_bytes(b.algo, b.var));
+        BatchGroup g;
+        memset(&g, 0, sizeof g);
+        g.first = k;
+        g.algo = b.algo;
+        g.var = b.var;
+        while (k < j.bpats.size() && g.count < cap && j.bpats[k].algo == b.algo && j.bpats[k].var == b.var) {
+            g.max_m = std::max(g.max_m, j.bpats[k].m);
+            g.count++;
+            k++;
+        }
+        j.groups.push_back(g);
+    }
+    if (!j.bpats.empty()) {
+        j.ntiles = (c->n - min_m + 1 + BT - 1) / BT;
+        // aim for a few thousand (chunk, group) items
+        uint64_t want = j.ntiles * j.groups.size() / 4096;
+        uint32_t ct = 1;
+        while ((uint64_t)ct * 2 <= want && ct < 256) ct *= 2;
+        j.chunk_tiles = ct;
+        j.nchunks = (j.ntiles + ct - 1) / ct;
+    }
+    j.L = layout_of(j, long_ws ? single : 0);
+    return SM_OK;
+}
+
+uint64_t sm::batch_image_bytes(const BatchJob &j) { return j.L.cnt; }
+
+void sm::batch_fill_image(const BatchJob &j, uint8_t *h)
+{
+    memset(h, 0, j.L.cnt);
+    memcpy(h + j.L.pats, j.bpats.data(), j.bpats.size() * sizeof(BatchPat));
+    memcpy(h + j.L.groups, j.groups.data(), j.groups.size() * sizeof(BatchGroup));
+    for (const auto &bp : j.bpats) memcpy(h + j.L.patbytes + bp.pat_off, j.pats + j.pat_off[bp.index], bp.m);
+}
+
+// ---------------------------------------------------------------------------
+// count and write steps
+// ---------------------------------------------------------------------------
+int sm::batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, uint64_t *d_totals,
+                            uint64_t *d_csr, bool keep_chunk_off, hipStream_t st)
+{
+    HIP_OK(fill_u64(d_totals, j.P, 0, st));
+    if (!j.bpats.empty()) {
+        std::vector<uint8_t> own;
+        if (!h_image) {
+            own.resize(batch_image_bytes(j));
+            batch_fill_image(j, own.data());
+            h_image = own.data();
+        }
+        // the params region is written by the prep kernel; copy around it
+        HIP_OK(hipMemcpyAsync(ws, h_image, j.L.params, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(ws + j.L.patbytes, h_image + j.L.patbytes, j.L.cnt - j.L.patbytes,
+                              hipMemcpyHostToDevice, st));
+        BatchLaunch B = launch_of(j, ws);
+        B.chunk_off_out = keep_chunk_off ? reinterpret_cast<uint64_t *>(ws + j.L.chunk_off) : nullptr;
+        B.totals = d_totals;
+        B.csr_out = nullptr;  // long patterns first, the CSR below
+        B.write = false;
+        B.prep = true;
+        HIP_OK(launch_batch(B, st));
+    }
+    for (uint32_t i : j.longp) {
+        const uint64_t m = j.pat_off[i + 1] - j.pat_off[i];
+        int r = sm_corpus_count_async(j.c, j.pats + j.pat_off[i], m, d_totals + i, ws + j.L.single,
+                                      j.L.need - j.L.single, nullptr, st);
+        if (r) return r;
+    }
+    if (d_csr) HIP_OK(launch_csr_scan(d_totals, j.P, d_csr, st));
+    return SM_OK;
+}
+
+int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, const uint64_t *h_csr,
+                            uint64_t *d_totals, int64_t *d_out, uint64_t lo, uint64_t hi,
+                            hipStream_t st)
+{
+    if (hi <= lo) return SM_OK;
+    if (!j.bpats.empty()) {
+        BatchLaunch B = launch_of(j, ws);
+        B.chunk_off = reinterpret_cast<const uint64_t *>(ws + j.L.chunk_off);
+        B.csr = d_csr;
+        B.out = d_out;
+        B.lo = lo;
+        B.span = hi - lo;
+        B.write = true;
+        HIP_OK(launch_batch(B, st));
+    }
+    if (!j.longp.empty() && !h_csr) return err(SM_EINVAL, "long patterns need the host offsets");
+    for (uint32_t i : j.longp) {  // one search each, into the window's part of its slice
+        const uint64_t a = std::max(h_csr[i], lo), b = std::min(h_csr[i + 1], hi);
+        if (a >= b) continue;
+        const uint64_t m = j.pat_off[i + 1] - j.pat_off[i];
+        int r = corpus_find_window_async(j.c, j.pats + j.pat_off[i], m, d_out + (a - lo), a - h_csr[i],
+                                         b - a, d_totals + i, ws + j.L.single, j.L.need - j.L.single, st);
+        if (r) return r;
+    }
+    return SM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch handle: count once, write windows
+// ---------------------------------------------------------------------------
+struct sm_batch {
+    BatchJob j;
+    std::vector<uint8_t> pats;
+    std::vector<uint64_t> pat_off;
+    std::vector<uint64_t> csr;  // host copy, P + 1
+    uint8_t *ws = nullptr;
+    ~sm_batch()
+    {
+        if (ws) (void)hipFree(ws);
+    }
+};
+
+extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+                             sm_batch **out)
+{
+    if (!out) return err(SM_EINVAL, "batch is NULL");
+    *out = nullptr;
+    int r = check_corpus(c);
+    if (r) return r;
+    if (!pats || !pat_off) return err(SM_EINVAL, "patterns or offsets are NULL");
+    for (uint32_t i = 0; i < P; i++)
+        if (pat_off[i + 1] < pat_off[i]) return err(SM_EINVAL, "pattern offsets decrease at %u", i);
+    std::unique_ptr<sm_batch> b(new (std::nothrow) sm_batch);
+    if (!b) return err(SM_ENOMEM, "out of host memory");
+    // own copy of the patterns: long patterns are read again by every write
+    const uint64_t base = pat_off[0];
+    b->pat_off.resize((uint64_t)P + 1);
+    for (uint64_t i = 0; i <= P; i++) b->pat_off[i] = pat_off[i] - base;
+    b->pats.assign(pats + base, pats + pat_off[P]);
+    b->pats.resize(b->pats.size() + 16);
+    if ((r = batch_plan(c, b->pats.data(), b->pat_off.data(), P, true, b->j))) return r;
+    HIP_OK(hipMalloc((void **)&b->ws, b->j.L.need));
+    uint64_t *d_tot = (uint64_t *)(b->ws + b->j.L.totals), *d_csr = (uint64_t *)(b->ws + b->j.L.csr);
+    if ((r = batch_count_enqueue(b->j, b->ws, nullptr, d_tot, d_csr, true, nullptr))) return r;
+    b->csr.resize((uint64_t)P + 1);
+    HIP_OK(hipMemcpy(b->csr.data(), d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost));
+    *out = b.release();
+    return SM_OK;
+}
+
+extern "C" int sm_batch_offsets(const sm_batch *b, uint64_t *out_off)
+{
+    if (!b || !out_off) return err(SM_EINVAL, "batch or out_off is NULL");
+    memcpy(out_off, b->csr.data(), b->csr.size() * 8);
+    return SM_OK;
+}
+
+extern "C" int sm_batch_write_async(sm_batch *b, uint64_t lo, uint64_t hi, int64_t *d_out, void *stream)
+{
+    if (!b) return err(SM_EINVAL, "batch is NULL");
+    const uint64_t total = b->csr.back();
+    if (lo > hi || hi > total)
+        return err(SM_EINVAL, "window [%llu, %llu) outside [0, %llu)", (unsigned long long)lo,
+                   (unsigned long long)hi, (unsigned long long)total);
+    if (hi > lo && !d_out) return err(SM_EINVAL, "d_out is NULL");
+    int r = check_corpus(b->j.c);
+    if (r) return r;
+    return batch_write_enqueue(b->j, b->ws, (const uint64_t *)(b->ws + b->j.L.csr), b->csr.data(),
+                               (uint64_t *)(b->ws + b->j.L.totals), d_out, lo, hi, (hipStream_t)stream);
+}
+
+extern "C" int sm_batch_close(sm_batch *b)
+{
+    if (!b) return SM_OK;
+    if (b->ws) {  // writes still in flight read the workspace
+        (void)hipSetDevice(b->j.c->dev);
+        (void)hipDeviceSynchronize();
+    }
+    delete b;
+    return SM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one-call forms
+// ---------------------------------------------------------------------------
 extern "C" uint64_t sm_batch_workspace_size(const sm_corpus *c, const uint8_t *pats,
                                             const uint64_t *pat_off, uint32_t P)
 {
     if (!c) return 0;
-    HostPlan hp;
-    if (build_plan(c, pats, pat_off, P, hp)) return 0;
-    return layout_of(hp, P, single_ws_need(c, hp, pats, pat_off)).need;
+    BatchJob j;
+    if (batch_plan(const_cast<sm_corpus *>(c), pats, pat_off, P, true, j)) return 0;
+    return j.L.need;
 }
 
 extern "C" int sm_batch_count_async(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off,
@@ -295,13 +390,10 @@ extern "C" int sm_batch_count_async(sm_corpus *c, const uint8_t *pats, const uin
     if (r) return r;
     if (P == 0) return SM_OK;
     if (!d_counts) return err(SM_EINVAL, "d_counts is NULL");
-    HostPlan hp;
-    if ((r = build_plan(c, pats, pat_off, P, hp))) return r;
-    const Layout L = layout_of(hp, P, single_ws_need(c, hp, pats, pat_off));
-    if (!d_work || work_bytes < L.need) return err(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)L.need);
-    if ((uintptr_t)d_work & 255) return err(SM_EINVAL, "workspace must be 256-byte aligned");
-    return run_count(c, hp, L, pats, pat_off, P, (uint8_t *)d_work, d_counts, nullptr, false,
-                     (hipStream_t)stream);
+    BatchJob j;
+    if ((r = batch_plan(c, pats, pat_off, P, true, j))) return r;
+    if ((r = check_ws(j, d_work, work_bytes))) return r;
+    return batch_count_enqueue(j, (uint8_t *)d_work, nullptr, d_counts, nullptr, false, (hipStream_t)stream);
 }
 
 extern "C" int sm_batch_find_all_async(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off,
@@ -313,19 +405,18 @@ extern "C" int sm_batch_find_all_async(sm_corpus *c, const uint8_t *pats, const 
     if (P == 0) return SM_OK;
     if (!d_out_off) return err(SM_EINVAL, "d_out_off is NULL");
     if (!d_out && cap > 0) return err(SM_EINVAL, "d_out is NULL with cap > 0");
-    HostPlan hp;
-    if ((r = build_plan(c, pats, pat_off, P, hp))) return r;
-    if (!hp.longp.empty())
+    BatchJob j;
+    if ((r = batch_plan(c, pats, pat_off, P, false, j))) return r;
+    if (!j.longp.empty())
         return err(SM_EINVAL, "asynchronous batched find_all takes patterns up to %d bytes (use sm_batch_find_all)",
                    BATCH_MAX_M);
-    const Layout L = layout_of(hp, P, 0);
-    if (!d_work || work_bytes < L.need) return err(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)L.need);
-    if ((uintptr_t)d_work & 255) return err(SM_EINVAL, "workspace must be 256-byte aligned");
+    if ((r = check_ws(j, d_work, work_bytes))) return r;
     uint8_t *ws = (uint8_t *)d_work;
     hipStream_t st = (hipStream_t)stream;
-    if ((r = run_count(c, hp, L, pats, pat_off, P, ws, (uint64_t *)(ws + L.totals), d_out_off, true, st)))
-        return r;
-    return run_write(c, hp, L, P, ws, d_out_off, d_out, cap, st);
+    uint64_t *d_tot = (uint64_t *)(ws + j.L.totals);
+    if ((r = batch_count_enqueue(j, ws, nullptr, d_tot, d_out_off, true, st))) return r;
+    // entries at or past the total are never produced, so [0, cap) is the whole prefix
+    return batch_write_enqueue(j, ws, d_out_off, nullptr, d_tot, d_out, 0, cap, st);
 }
 
 extern "C" int sm_batch_count(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
@@ -335,18 +426,25 @@ extern "C" int sm_batch_count(sm_corpus *c, const uint8_t *pats, const uint64_t 
     if (r) return r;
     if (P == 0) return SM_OK;
     if (!counts) return err(SM_EINVAL, "counts is NULL");
-    HostPlan hp;
-    if ((r = build_plan(c, pats, pat_off, P, hp))) return r;
-    const Layout L = layout_of(hp, P, single_ws_need(c, hp, pats, pat_off));
-    void *ws = nullptr;
-    HIP_OK(hipMalloc(&ws, L.need));
-    r = run_count(c, hp, L, pats, pat_off, P, (uint8_t *)ws, (uint64_t *)((uint8_t *)ws + L.totals),
-                  nullptr, false, nullptr);
-    hipError_t e = hipSuccess;
-    if (!r) e = hipMemcpy(counts, (uint8_t *)ws + L.totals, (uint64_t)P * 8, hipMemcpyDeviceToHost);
-    (void)hipFree(ws);
-    if (r) return r;
-    if (e != hipSuccess) return err(SM_EDEVICE, "copy of the counts failed: %s", hipGetErrorString(e));
+    BatchJob j;
+    if ((r = batch_plan(c, pats, pat_off, P, true, j))) return r;
+    DevFree ws;
+    HIP_OK(hipMalloc(&ws.p, j.L.need));
+    uint64_t *d_tot = (uint64_t *)((uint8_t *)ws.p + j.L.totals);
+    if ((r = batch_count_enqueue(j, (uint8_t *)ws.p, nullptr, d_tot, nullptr, false, nullptr))) return r;
+    HIP_OK(hipMemcpy(counts, d_tot, (uint64_t)P * 8, hipMemcpyDeviceToHost));
+    return SM_OK;
+}
+
+namespace {
+constexpr uint64_t WAVE_DEFAULT = 16ull << 30;
+uint64_t g_wave_bytes = WAVE_DEFAULT;  // output-wave budget of sm_batch_find_all
+}
+
+extern "C" int sm_batch_set_wave_bytes(uint64_t bytes)
+{
+    if (bytes != 0 && bytes < 8) return err(SM_EINVAL, "wave budget below one position");
+    g_wave_bytes = bytes ? bytes : WAVE_DEFAULT;
     return SM_OK;
 }
 
@@ -361,34 +459,24 @@ extern "C" int sm_batch_find_all(sm_corpus *c, const uint8_t *pats, const uint64
         return SM_OK;
     }
     if (!out && cap > 0) return err(SM_EINVAL, "out is NULL with cap > 0");
-    HostPlan hp;
-    if ((r = build_plan(c, pats, pat_off, P, hp))) return r;
-    const Layout L = layout_of(hp, P, single_ws_need(c, hp, pats, pat_off));
-    uint8_t *ws = nullptr;
-    HIP_OK(hipMalloc((void **)&ws, L.need));
-    struct Free {
-        void *p;
-        ~Free() { (void)hipFree(p); }
-    } f1{ws};
-    uint64_t *d_tot = (uint64_t *)(ws + L.totals), *d_csr = (uint64_t *)(ws + L.csr);
-    if ((r = run_count(c, hp, L, pats, pat_off, P, ws, d_tot, d_csr, true, nullptr))) return r;
-    HIP_OK(hipMemcpy(out_off, d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost));
+    sm_batch *b = nullptr;
+    if ((r = sm_batch_open(c, pats, pat_off, P, &b))) return r;
+    std::unique_ptr<sm_batch, int (*)(sm_batch *)> hold(b, sm_batch_close);
+    memcpy(out_off, b->csr.data(), ((uint64_t)P + 1) * 8);
     const uint64_t total = out_off[P];
     const uint64_t dcap = std::min(cap, total);
-    int64_t *d_out = nullptr;
-    if (dcap) HIP_OK(hipMalloc((void **)&d_out, dcap * 8));
-    Free f2{d_out};
-    if ((r = run_write(c, hp, L, P, ws, d_csr, d_out, dcap, nullptr))) return r;
-    // long patterns: one search each, into their CSR slices
-    for (uint32_t i : hp.longp) {
-        const uint64_t m = pat_off[i + 1] - pat_off[i];
-        if (out_off[i] >= dcap) continue;
-        const uint64_t room = std::min(out_off[i + 1], dcap) - out_off[i];
-        r = sm_corpus_find_all_async(c, pats + pat_off[i], m, d_out + out_off[i], room, d_tot + i,
-                                     ws + L.single, L.need - L.single, nullptr, nullptr);
-        if (r) return r;
+    // output in waves: the device never holds more than the wave budget of positions
+    size_t free_b = 0, tot_b = 0;
+    HIP_OK(hipMemGetInfo(&free_b, &tot_b));
+    uint64_t wave = std::min<uint64_t>(g_wave_bytes / 8, std::max<uint64_t>(free_b / 16, 1ull << 20));
+    wave = std::max<uint64_t>(std::min(wave, dcap), 1);
+    DevFree dbuf;
+    if (dcap) HIP_OK(hipMalloc(&dbuf.p, wave * 8));
+    for (uint64_t lo = 0; lo < dcap; lo += wave) {
+        const uint64_t hi = std::min(dcap, lo + wave);
+        if ((r = sm_batch_write_async(b, lo, hi, (int64_t *)dbuf.p, nullptr))) return r;
+        HIP_OK(hipMemcpy(out + lo, dbuf.p, (hi - lo) * 8, hipMemcpyDeviceToHost));
     }
-    if (dcap) HIP_OK(hipMemcpy(out, d_out, dcap * 8, hipMemcpyDeviceToHost));
     HIP_OK(hipDeviceSynchronize());
     return total > cap ? SM_TRUNCATED : SM_OK;
 }

@@ -49,8 +49,8 @@ struct BatchArgs {
     uint32_t *cnt;             // [sorted pattern][chunk]
     const uint64_t *chunk_off; // [sorted pattern][chunk] (write)
     const uint64_t *csr;       // [original index] (write)
-    int64_t *out;
-    uint64_t cap;
+    int64_t *out;              // write: CSR entry k goes to out[k - lo]
+    uint64_t lo, span;         // write: window [lo, lo + span) of CSR entries
 };
 
 template <int ALGO, int VAR>
@@ -173,16 +173,25 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a)
     const BatchGroup g = a.groups[a.group_lo + item % a.ngroups];
     const int tid = threadIdx.x;
 
-    if (WRITE) {  // skip items without hits (uniform: every thread reads the same counts)
+    const uint64_t wend = a.lo + a.span;
+    if (WRITE) {  // skip items without hits in the window (uniform: all threads read the same)
         bool any = false;
-        for (uint32_t j = 0; j < g.count; j++) any |= a.cnt[(uint64_t)(g.first + j) * a.nchunks + chunk] != 0;
+        for (uint32_t j = 0; j < g.count; j++) {
+            const uint64_t sp = g.first + j;
+            const uint32_t c = a.cnt[sp * a.nchunks + chunk];
+            if (c == 0) continue;
+            const uint64_t r0 = a.csr[a.pats[sp].index] + a.chunk_off[sp * a.nchunks + chunk];
+            any |= r0 < wend && r0 + c > a.lo;
+        }
         if (!any) return;
     }
     load_group_tables<ALGO, VAR>(S, a, g);
     if (WRITE && tid < (int)g.count) {
         const uint64_t sp = g.first + tid;
-        S.acc[tid] = a.cnt[sp * a.nchunks + chunk];
-        S.run[tid] = a.csr[a.pats[sp].index] + a.chunk_off[sp * a.nchunks + chunk];
+        const uint32_t c = a.cnt[sp * a.nchunks + chunk];
+        const uint64_t r0 = a.csr[a.pats[sp].index] + a.chunk_off[sp * a.nchunks + chunk];
+        S.acc[tid] = (r0 < wend && r0 + c > a.lo) ? c : 0u;  // nonzero: hits in the window
+        S.run[tid] = r0;
     }
     const uint64_t t0 = chunk * a.chunk_tiles;
     uint64_t t1 = t0 + a.chunk_tiles;
@@ -209,14 +218,21 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a)
                 uint32_t tot;
                 const uint32_t before = block_excl_scan(c, S.w, tot);
                 if (tot) {  // uniform
-                    PosEmit pe;
-                    pe.out = a.out;
-                    pe.cap = a.cap;
-                    pe.base = s;
-                    pe.idx = S.run[j] + before;
-                    batch_lane<ALGO, VAR, true>(S, a, (int)j, s, boff, lo, hi, pe);
+                    const uint64_t r0 = S.run[j];
+                    if (r0 < wend && r0 + tot > a.lo) {
+                        PosEmit pe;
+                        pe.out = a.out;
+                        pe.lo = a.lo;
+                        pe.span = a.span;
+                        pe.base = s;
+                        pe.idx = r0 + before;
+                        batch_lane<ALGO, VAR, true>(S, a, (int)j, s, boff, lo, hi, pe);
+                    }
                     __syncthreads();
-                    if (tid == 0) S.run[j] += tot;
+                    if (tid == 0) {
+                        S.run[j] = r0 + tot;
+                        if (r0 + tot >= wend) S.acc[j] = 0;  // the rest of the chunk is past the window
+                    }
                 }
             }
         }
@@ -356,7 +372,8 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
     a.chunk_off = L.chunk_off;
     a.csr = L.csr;
     a.out = L.out;
-    a.cap = L.cap;
+    a.lo = L.lo;
+    a.span = L.span;
     hipError_t e;
     if (L.prep) {
         hipLaunchKernelGGL(batch_prep_kernel, dim3(L.npats), dim3(BLOCK), 0, st, L.pats, L.patbytes,

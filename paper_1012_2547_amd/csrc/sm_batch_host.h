@@ -1,0 +1,59 @@
+// Host side of the batched search, shared by the batch C ABI (sm_batch.cpp) and
+// the server (sm_server.cpp): the plan of a batch (sorted patterns, groups, text
+// chunking), its workspace layout, and the two enqueue steps (count, then
+// writes of any window of the CSR output).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "sm_internal.h"
+
+namespace sm {
+
+struct BatchLayout {  // byte offsets inside the batch workspace
+    uint64_t pats, groups, params, patbytes, cnt, chunk_off, totals, csr, single, need;
+};
+
+struct BatchJob {
+    sm_corpus *c = nullptr;
+    uint32_t P = 0;
+    const uint8_t *pats = nullptr;    // host pattern bytes, valid for the job's life
+    const uint64_t *pat_off = nullptr;
+    std::vector<BatchPat> bpats;      // patterns searched inside batch launches, sorted
+    std::vector<BatchGroup> groups;
+    std::vector<uint32_t> longp;      // m > BATCH_MAX_M: searched one pattern at a time
+    uint64_t patbytes = 0;
+    uint32_t chunk_tiles = 1;
+    uint64_t nchunks = 0, ntiles = 0;
+    BatchLayout L{};
+};
+
+// Validates and plans P patterns against the corpus (host only). The workspace
+// reserves single-pattern scratch for the long patterns when long_ws is set.
+int batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
+               bool long_ws, BatchJob &j);
+
+// Bytes of the host image uploaded by the count step (pattern table, groups and
+// pattern bytes), and its contents.
+uint64_t batch_image_bytes(const BatchJob &j);
+void batch_fill_image(const BatchJob &j, uint8_t *dst);
+
+// Count step: uploads the image (h_image: batch_fill_image's output, pinned or
+// pageable; null = built here), builds the tables, counts every pattern ->
+// d_totals[0..P) (caller order) and, when d_csr is not null, the exclusive scan
+// -> d_csr[0..P]. keep_chunk_off keeps what a later write step needs.
+int batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, uint64_t *d_totals,
+                        uint64_t *d_csr, bool keep_chunk_off, hipStream_t st);
+
+// Write step: CSR entries [lo, hi) -> d_out[0 .. hi - lo). Needs the count
+// step's workspace (keep_chunk_off) and d_csr; h_csr (host copy of d_csr) is
+// needed only when the job has long patterns.
+int batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, const uint64_t *h_csr,
+                        uint64_t *d_totals, int64_t *d_out, uint64_t lo, uint64_t hi,
+                        hipStream_t st);
+
+int batch_err(int status, const char *fmt, ...);
+
+}  // namespace sm

@@ -143,13 +143,16 @@ struct NoEmit {
 };
 
 // int64 global positions, bounded by cap
+// Positions into an output window: hit number idx goes to out[idx - lo] when
+// lo <= idx < lo + span (one unsigned compare covers both ends).
 struct PosEmit {
     int64_t *out;
-    uint64_t idx, cap;
+    uint64_t idx, lo, span;
     uint64_t base;  // global position of relative position 0
     __device__ __forceinline__ void put(int rel)
     {
-        if (idx < cap) out[idx] = (int64_t)(base + (uint64_t)(int64_t)rel);
+        const uint64_t r = idx - lo;
+        if (r < span) out[r] = (int64_t)(base + (uint64_t)(int64_t)rel);
         idx++;
     }
 };

@@ -145,8 +145,8 @@ struct BatchLaunch {
     uint64_t *totals;           // count: per original index
     uint64_t *csr_out;          // count: exclusive scan of totals, P + 1 entries (may be null)
     const uint64_t *csr;        // write: CSR offsets by original index
-    int64_t *out;
-    uint64_t cap;
+    int64_t *out;               // write: CSR entry k goes to out[k - lo]
+    uint64_t lo, span;          // write: window [lo, lo + span) of CSR entries
     bool write, prep;
 };
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream);
@@ -170,6 +170,12 @@ namespace sm {
 // The corpus's sigma_eff rounded to [1, 256] (planner input).
 int corpus_sigma(const sm_corpus *c);
 
+// Single-pattern find_all of hit numbers [first, first + cap) into d_out[0 ..)
+// (a window of the sorted list); total -> *d_count.
+int corpus_find_window_async(sm_corpus *c, const uint8_t *pat, uint64_t m, int64_t *d_out,
+                             uint64_t first, uint64_t cap, uint64_t *d_count, void *d_work,
+                             uint64_t work_bytes, hipStream_t stream);
+
 // Plan one pattern as the single-pattern path would (sigma from the corpus).
 int plan_pattern(const uint8_t *pat, uint64_t m, int sigma, Plan &p);
 const char *sm_set_error(int status, const char *msg);
@@ -184,11 +190,11 @@ hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_para
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n,
                         const Params *d_params, const uint8_t *d_pat, const FindWs &w,
                         uint64_t *d_total, hipStream_t stream, hipEvent_t after_count);
-// count -> scan -> emit: positions -> d_out[0 .. min(total, cap)), total -> *d_total.
+// count -> scan -> emit: hit numbers [first, first + cap) -> d_out[0 .. ), total -> *d_total.
 // `after_count` (may be null) is recorded after the count kernel.
 hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t cap,
-                       uint64_t *d_total, hipStream_t stream, hipEvent_t after_count);
+                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t first,
+                       uint64_t cap, uint64_t *d_total, hipStream_t stream, hipEvent_t after_count);
 hipError_t launch_set_u64(uint64_t *d_dst, uint64_t value, hipStream_t stream);
 hipError_t launch_histogram(const uint8_t *d_text, uint64_t n, uint64_t *d_hist256,
                             hipStream_t stream);

@@ -61,8 +61,8 @@ struct ScanArgs {
     const uint64_t *tile_off;  // emit: exclusive prefix of tile_cnt
     const uint32_t *list;      // emit: tiles with hits, ascending
     const uint64_t *nlist;     // emit: list length
-    int64_t *out;
-    uint64_t cap;
+    int64_t *out;         // emit: hit number k of the pattern goes to out[k - lo]
+    uint64_t lo, cap;     // emit: window [lo, lo + cap) of hit numbers
 };
 
 template <int ALGO, int L>
@@ -265,12 +265,14 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
         const uint64_t t = a.list[e];
         const uint32_t tot = a.tile_cnt[t];
         const uint64_t off = a.tile_off[t];
-        if (off >= a.cap) continue;  // uniform over the workgroup
+        if (off >= a.lo + a.cap || off + tot <= a.lo) continue;  // uniform over the workgroup
         const uint64_t s = t * (uint64_t)Geometry<ALGO, L>::T;
         if (tot <= STASH_K) {
             const uint16_t *src = a.stash + t * STASH_K;
-            for (uint32_t k = threadIdx.x; k < tot; k += BLOCK)
-                if (off + k < a.cap) a.out[off + k] = (int64_t)(s + src[k]);
+            for (uint32_t k = threadIdx.x; k < tot; k += BLOCK) {
+                const uint64_t r = off + k - a.lo;
+                if (r < a.cap) a.out[r] = (int64_t)(s + src[k]);
+            }
             continue;
         }
         if (!tables) {
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
         const int hi_rel = (int)((a.n - a.m - s2) < (uint64_t)(Geometry<ALGO, L>::T - 1)
                                      ? (a.n - a.m - s2) : (uint64_t)(Geometry<ALGO, L>::T - 1));
         uint64_t run = off;
-        for (int sb = 0; sb <= hi_rel && run < a.cap; sb += EMIT_SUB) {  // uniform
+        for (int sb = 0; sb <= hi_rel && run < a.lo + a.cap; sb += EMIT_SUB) {  // uniform
             const int lo = sb + SUB_LANE * (int)threadIdx.x;
             const int hi = (lo + SUB_LANE - 1) < hi_rel ? (lo + SUB_LANE - 1) : hi_rel;
             NoEmit ne;
@@ -294,13 +296,19 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
             uint32_t ctot;
             const uint32_t before = block_excl_scan(c, S.w, ctot);
             if (ctot == 0) continue;  // uniform
+            if (run + ctot <= a.lo) {  // sub-tile entirely before the window (uniform)
+                run += ctot;
+                continue;
+            }
             ListEmit le;
             le.dst = s_list;
             le.idx = before;
             run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, le);
             __syncthreads();
-            for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK)
-                if (run + k < a.cap) a.out[run + k] = (int64_t)(s2 + s_list[k]);
+            for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK) {
+                const uint64_t r = run + k - a.lo;
+                if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[k]);
+            }
             __syncthreads();
             run += ctot;
         }
@@ -616,8 +624,8 @@ hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, con
 }
 
 hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
-                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t cap,
-                       uint64_t *d_total, hipStream_t stream, hipEvent_t after_count)
+                       const uint8_t *d_pat, const FindWs &w, int64_t *d_out, uint64_t first,
+                       uint64_t cap, uint64_t *d_total, hipStream_t stream, hipEvent_t after_count)
 {
     if (w.ntiles == 0) return hipSuccess;
     if (w.ntiles > 0xFFFFFFFFull) return hipErrorInvalidValue;
@@ -628,6 +636,7 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     a.list = w.list;
     a.nlist = w.nlist;
     a.out = d_out;
+    a.lo = first;
     a.cap = cap;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;

@@ -1,0 +1,165 @@
+"""GPU tests of the windowed batch writes and the query server.
+
+Every result is compared with the CPU oracle for the pattern alone, so a query
+answered inside a mixed batch must equal its answer in isolation, exactly.
+"""
+import numpy as np
+import pytest
+
+import datagen as dg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def sm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1012_2547_amd as sm
+    sm.version()
+    return sm
+
+
+def corpora_small():
+    """Scaled-down versions of the three serving corpora: uniform sigma=4,
+    uniform sigma=20, Zipf(s=1.1) over 256 symbols."""
+    return [dg.uniform_text(300_001, 4, seed=11), dg.uniform_text(200_003, 20, seed=12),
+            dg.zipf_text(250_007, 256, 1.1, seed=13)]
+
+
+def query_mix(texts, count, seed):
+    """(corpus, pattern) pairs: corpus uniform, m log-uniform in [4, 256], half
+    substrings of the chosen corpus, half i.i.d. random over its alphabet."""
+    ms = dg.log_uniform_lengths(count, 4, 256, seed=seed)
+    cs = dg.choices(count, len(texts), seed=seed)
+    out = []
+    for i in range(count):
+        t = texts[int(cs[i])]
+        m = int(ms[i])
+        if i % 2 == 0:
+            p = dg.substring_pattern(t, m, seed=seed, idx=i)[0]
+        else:
+            p = dg.random_pattern(m, int(t.max()) + 1, seed=seed, idx=i)
+        out.append((int(cs[i]), p))
+    return out
+
+
+def test_batch_windows_match_whole_output(sm):
+    t_np = dg.uniform_text(400_000, 4, seed=3)
+    t_np[:50_000] = np.tile(t_np[:7], 50_000 // 7 + 1)[:50_000]  # period 7: long patterns recur
+    pats = [dg.substring_pattern(t_np, int(m), seed=4, idx=i)[0]
+            for i, m in enumerate(dg.log_uniform_lengths(60, 2, 1024, seed=4))]
+    pats += [dg.substring_pattern(t_np, 2600, seed=4, idx=99)[0], b"\x00\x01", bytes(t_np[:3000])]
+    c = sm.Corpus(t_np)
+    want = [oracle.find_all(t_np, p) for p in pats]
+    flat = np.concatenate(want)
+    b = c.batch_open(pats)
+    assert b.total == flat.size
+    assert np.array_equal(b.offsets[1:] - b.offsets[:-1], [w.size for w in want])
+    rng = np.random.default_rng(5)
+    assert want[62].size > 1000
+    cuts = np.unique(np.concatenate([[0, b.total], rng.integers(0, b.total, 9),
+                                     b.offsets[[10, 61, 62]].astype(np.int64) + 1,
+                                     b.offsets[[62]].astype(np.int64) + 777]))
+    d = torch.full((b.total + 8,), -1, dtype=torch.int64, device=DEV)
+    got = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        buf = d[: hi - lo]
+        b.write_async(int(lo), int(hi), buf)
+        got.append(buf.cpu().numpy().copy())
+    assert np.array_equal(np.concatenate(got), flat)
+    b.write_async(5, 5, d)  # empty window
+    with pytest.raises(sm.SmError):
+        b.write_async(0, b.total + 1, d)
+    b.close()
+    c.close()
+
+
+def test_batch_find_all_in_small_waves(sm):
+    t_np = np.full(100_000, ord("a"), dtype=np.uint8)
+    t_np[::97] = ord("b")
+    pats = [b"a", b"aa", b"ab", b"a" * 40, b"ba", bytes(t_np[:2500]), b"a" * 2500]
+    c = sm.Corpus(t_np)
+    want = [oracle.find_all(t_np, p) for p in pats]
+    try:
+        sm.batch_set_wave_bytes(8 * 4099)  # many waves
+        pos, off = c.batch_find_all(pats)
+        pos2, off2 = c.batch_find_all(pats, cap=12_345)
+    finally:
+        sm.batch_set_wave_bytes(0)
+    flat = np.concatenate(want)
+    assert np.array_equal(off[1:] - off[:-1], [w.size for w in want])
+    assert np.array_equal(pos, flat)
+    assert np.array_equal(off2, off) and np.array_equal(pos2, flat[:12_345])
+    c.close()
+
+
+@pytest.mark.parametrize("slots,max_batch,pool,host", [(2, 64, 0, 0), (1, 7, 1 << 16, 1 << 16),
+                                                       (3, 256, 8 * 5000 * 3, 1 << 20)])
+def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host):
+    texts = corpora_small()
+    srv = sm.Server(pool_bytes=pool, host_bytes=host, max_batch=max_batch, slots=slots)
+    cs = [sm.Corpus(t) for t in texts]
+    ids = [srv.add_corpus(c) for c in cs]
+    qs = query_mix(texts, 150, seed=14)
+    qs += [(0, b"\x00\x01"), (1, b"\x05"), (2, bytes(texts[2][:2100])), (0, bytes(texts[0][:300_001]))]
+    tickets = [srv.submit(ids[c], p) for c, p in qs]
+    for (c, p), tk in zip(qs, tickets):
+        cnt, pos, info = srv.wait(tk)
+        want = oracle.find_all(texts[c], p)
+        assert cnt == want.size, (c, len(p))
+        assert np.array_equal(pos, want), (c, len(p))
+        assert info["corpus"] == c and info["done_ns"] >= info["start_ns"] >= info["arrival_ns"] > 0
+        srv.free(tk)
+    st = srv.stats()
+    assert st["completed"] == len(qs) and st["pending"] == 0
+    assert st["batched_queries"] == len(qs)
+    assert 0 < st["p50_ns"] <= st["p99_ns"] <= st["p999_ns"] <= st["max_ns"]
+    if pool:
+        assert st["write_waves"] > st["batches"]  # outputs larger than a slot's pool share
+    srv.close()
+    for c in cs:
+        c.close()
+
+
+def test_server_matches_single_path_and_reuses_memory(sm):
+    t_np = dg.uniform_text(1 << 20, 4, seed=21)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    c = sm.Corpus(t_dev)
+    srv = sm.Server(max_batch=32, host_bytes=1 << 22)
+    cid = srv.add_corpus(c)
+    pats = [dg.substring_pattern(t_np, int(m), seed=22, idx=i)[0]
+            for i, m in enumerate(dg.log_uniform_lengths(96, 4, 256, seed=22))]
+    for rnd in range(3):  # results freed in and out of order; arena space is reused
+        tks = [srv.submit(cid, p) for p in pats]
+        order = list(range(len(tks)))
+        np.random.default_rng(rnd).shuffle(order)
+        for k in order:
+            got = srv.result(tks[k])
+            single = sm.find_all(t_dev, pats[k]).cpu().numpy()
+            assert np.array_equal(got, single), (rnd, k)
+    srv.close()
+    c.close()
+
+
+def test_server_errors(sm):
+    t_np = dg.uniform_text(10_000, 4, seed=1)
+    c = sm.Corpus(t_np)
+    srv = sm.Server(max_pending=4)
+    cid = srv.add_corpus(c)
+    with pytest.raises(sm.SmError):
+        srv.submit(cid + 1, b"ab")
+    with pytest.raises(sm.SmError):
+        srv.submit(cid, b"")
+    tk = srv.submit(cid, b"\x00\x01\x02")
+    assert srv.result(tk).size == oracle.find_all(t_np, b"\x00\x01\x02").size
+    with pytest.raises(sm.SmError):
+        srv.free(tk)  # already freed
+    with pytest.raises(sm.SmError):
+        srv.wait(12345)
+    srv.close()
+    c.close()
