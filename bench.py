@@ -75,6 +75,14 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--batched-n-log2", type=int, default=32)
     ap.add_argument("--batched-patterns", type=int, default=4096)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-shift", type=int, default=0,
+                    help="log2 scale of the serving corpora (0: 8, 2 and 4 GiB)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="trace length per arrival rate: min(20000, rate x seconds) queries")
+    ap.add_argument("--serve-rates", type=str, default="250,1000,4000,16000")
+    ap.add_argument("--plain-queries", type=int, default=1000,
+                    help="queries of each trace (its prefix) replayed through the plain path")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -234,6 +242,11 @@ def main():
         torch.cuda.empty_cache()
         batched = batched_section(args, dev, stream)
 
+    serving = None
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        serving = serving_section(args, dev)
+
     res = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -250,6 +263,7 @@ def main():
         "cells_median_gbs": cell_gbs,
         "sigma_eff": sigma_eff,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(res), flush=True)
 
@@ -317,6 +331,172 @@ def batched_section(args, dev, stream):
             "plain_pattern_GBps": round(P * n / t_plain / 1e9, 1),
             "speedup_vs_plain": round(t_plain / t_batch, 2),
             "occurrences": int(cb.sum()), "counts_agree_with_plain": agree}
+
+
+def _digest(pos) -> tuple:
+    """(count, first, last, sum of 64 evenly strided positions): cheap order-sensitive
+    summary used to compare the server's answer with the plain path's."""
+    k = int(pos.size)
+    if k == 0:
+        return (0, -1, -1, 0)
+    return (k, int(pos[0]), int(pos[-1]), int(pos[::max(1, k // 64)].sum()))
+
+
+def _pct(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), p, method="higher")) if len(v) else None
+
+
+def serving_section(args, dev):
+    """Open-loop serving: three resident corpora (uniform sigma=4 of 8 GiB seed 11,
+    uniform sigma=20 of 2 GiB seed 12 (protein-like), Zipf(s=1.1) over 256 symbols
+    of 4 GiB seed 13); per arrival rate a Poisson trace of min(20000, rate x T)
+    queries (seed 14 + rate index), corpus uniform, m log-uniform in [4, 256], even
+    queries substrings of their corpus and odd ones i.i.d. random over its
+    alphabet. Latency = arrival -> positions in host memory. The prefix of each
+    trace is replayed through the plain path (one synchronous find_all per query,
+    in arrival order) and both answers must agree exactly (digest of every query)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import datagen as dg
+    import paper_1012_2547_amd as sm
+
+    t0 = time.time()
+    sh = args.serve_shift
+    specs = [("uniform sigma=4", 33 + sh, 4, lambda n: dg.uniform_text(n, 4, seed=11)),
+             ("uniform sigma=20", 31 + sh, 20, lambda n: dg.uniform_text(n, 20, seed=12)),
+             ("zipf K=256 s=1.1", 32 + sh, 256, lambda n: dg.zipf_text(n, 256, 1.1, seed=13))]
+    hosts, corpora, names = [], [], []
+    for name, lg, _, gen in specs:
+        h = gen(1 << lg)
+        hosts.append(h)
+        corpora.append(sm.Corpus(torch.from_numpy(h).to(dev)))
+        names.append("%s n=2^%d" % (name, lg))
+    sig = [sp[2] for sp in specs]
+    rates = [float(x) for x in args.serve_rates.split(",") if x]
+    traces = []
+    for k, lam in enumerate(rates):
+        N = int(min(20000, max(1, round(lam * args.serve_seconds))))
+        seed = 14 + k
+        arr = dg.poisson_arrivals(N, lam, seed)
+        cs = dg.choices(N, len(corpora), seed)
+        ms = dg.log_uniform_lengths(N, 4, 256, seed)
+        qs = []
+        for i in range(N):
+            c, m = int(cs[i]), int(ms[i])
+            p = (dg.substring_pattern(hosts[c], m, seed, i)[0] if i % 2 == 0
+                 else dg.random_pattern(m, sig[c], seed, i))
+            qs.append((c, p))
+        traces.append((lam, arr, qs))
+    del hosts
+    log("serving: corpora and %d queries ready in %.1fs" % (sum(len(t[2]) for t in traces),
+                                                           time.time() - t0))
+
+    srv = sm.Server()
+    ids = [srv.add_corpus(c) for c in corpora]
+    out = {"workload": "3 resident corpora (%s); Poisson arrivals; m log-uniform [4,256]; half "
+                       "substrings, half random; latency = arrival -> positions on host"
+                       % "; ".join(names),
+           "server": {"slots": 2, "max_batch": 256, "pool_GiB": 16, "host_arena_GiB": 2},
+           "rates": []}
+
+    def replay_server(arr, qs):
+        N = len(qs)
+        tickets = [0] * N
+        digests = [None] * N
+        lat = np.zeros(N, dtype=np.int64)
+        bsz = np.zeros(N, dtype=np.int64)
+        sem = threading.Semaphore(0)
+        start = sm.now_ns() + 20_000_000
+        sched = start + (arr * 1e9).astype(np.int64)
+
+        def submitter():
+            for i in range(N):
+                t = int(sched[i])
+                while True:
+                    d = t - sm.now_ns()
+                    if d <= 0:
+                        break
+                    if d > 300_000:
+                        time.sleep((d - 200_000) / 1e9)
+                tickets[i] = srv.submit(ids[qs[i][0]], qs[i][1], t)
+                sem.release()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for i in range(N):
+            sem.acquire()
+            cnt, pos, info = srv.wait(tickets[i])
+            digests[i] = _digest(pos)
+            lat[i] = info["done_ns"] - info["arrival_ns"]
+            bsz[i] = info["batch_size"]
+            srv.free(tickets[i])
+        th.join()
+        return lat, digests, bsz
+
+    def replay_plain(arr, qs):
+        N = len(qs)
+        lat = np.zeros(N, dtype=np.int64)
+        digests = [None] * N
+        start = sm.now_ns() + 20_000_000
+        sched = start + (arr[:N] * 1e9).astype(np.int64)
+        for i in range(N):
+            t = int(sched[i])
+            while sm.now_ns() < t:
+                d = t - sm.now_ns()
+                if d > 300_000:
+                    time.sleep((d - 200_000) / 1e9)
+            c, p = qs[i]
+            pos = corpora[c].find_all(p)  # synchronous: count, then positions to the host
+            lat[i] = sm.now_ns() - t
+            digests[i] = _digest(pos)
+        return lat, digests
+
+    # warm-up: one query per corpus through both paths
+    for c in range(len(corpora)):
+        srv.result(srv.submit(ids[c], b"\x01\x02\x03\x00"))
+        corpora[c].find_all(b"\x01\x02\x03\x00")
+    for lam, arr, qs in traces:
+        srv.reset_stats()
+        t1 = time.time()
+        lat, dig, bsz = replay_server(arr, qs)
+        st = srv.stats()
+        wall = time.time() - t1
+        K = min(len(qs), args.plain_queries)
+        plat, pdig = replay_plain(arr, qs[:K])
+        agree = all(a == b for a, b in zip(dig[:K], pdig))
+        span_s = st["span_ns"] / 1e9 if st["span_ns"] else wall
+        row = {
+            "rate_qps": lam, "queries": len(qs),
+            "p50_ms": round(st["p50_ns"] / 1e6, 3), "p99_ms": round(st["p99_ns"] / 1e6, 3),
+            "p999_ms": round(st["p999_ns"] / 1e6, 3), "max_ms": round(st["max_ns"] / 1e6, 3),
+            "achieved_qps": round(st["qps"], 1),
+            "pattern_GBps": round(st["text_bytes"] / span_s / 1e9, 1),
+            "out_GBps": round(st["out_bytes"] / span_s / 1e9, 2),
+            "batches": st["batches"], "mean_batch": round(float(bsz.mean()), 1),
+            "write_waves": st["write_waves"], "overflow_allocs": st["overflow_allocs"],
+            "prefix": {"queries": K,
+                       "server_p50_ms": round(_pct(lat[:K], 50) / 1e6, 3),
+                       "server_p99_ms": round(_pct(lat[:K], 99) / 1e6, 3),
+                       "plain_p50_ms": round(_pct(plat, 50) / 1e6, 3),
+                       "plain_p99_ms": round(_pct(plat, 99) / 1e6, 3)},
+            "alone_vs_in_mix_agree": bool(agree),
+        }
+        log("serving %6.0f qps: %5d queries, p50 %.2f ms p99 %.2f ms p999 %.2f ms, achieved %.0f qps, "
+            "%.0f pattern-GB/s, mean batch %.1f; prefix %d: server p99 %.2f ms vs plain p99 %.2f ms; "
+            "agree %s" % (lam, len(qs), row["p50_ms"], row["p99_ms"], row["p999_ms"],
+                          row["achieved_qps"], row["pattern_GBps"], row["mean_batch"], K,
+                          row["prefix"]["server_p99_ms"], row["prefix"]["plain_p99_ms"], agree))
+        if not agree:
+            raise SystemExit("server and plain path disagree at rate %g" % lam)
+        out["rates"].append(row)
+    srv.close()
+    for c in corpora:
+        c.close()
+    return out
 
 
 if __name__ == "__main__":
