@@ -56,6 +56,81 @@ int table_bytes(uint32_t algo, uint32_t var)
 
 uint64_t pat_region(uint64_t m) { return align_up(m, 16) + 16; }  // verify reads 16 bytes past m
 
+// Table of one prefix-filter group (layout in sm_internal.h): the patterns
+// mem[0 .. count) (sorted indices) of q-class q.
+// Returns whether the group is flat (every pattern has m == q and every bucket
+// holds one slot).
+bool build_mq_table(const BatchJob &j, const uint32_t *mem, uint32_t count, uint32_t q, uint8_t *T)
+{
+    uint32_t *bits = reinterpret_cast<uint32_t *>(T + MQ_OFF_BITS);
+    uint16_t *rank = reinterpret_cast<uint16_t *>(T + MQ_OFF_RANK);
+    uint16_t *bstart = reinterpret_cast<uint16_t *>(T + MQ_OFF_BSTART);
+    uint32_t *spre = reinterpret_cast<uint32_t *>(T + MQ_OFF_SPRE);
+    uint16_t *sstart = reinterpret_cast<uint16_t *>(T + MQ_OFF_SSTART);
+    uint16_t *srep = reinterpret_cast<uint16_t *>(T + MQ_OFF_SREP);
+    uint16_t *pid = reinterpret_cast<uint16_t *>(T + MQ_OFF_PID);
+    uint16_t *m16 = reinterpret_cast<uint16_t *>(T + MQ_OFF_M);
+    uint32_t *pre2 = reinterpret_cast<uint32_t *>(T + MQ_OFF_PRE2);
+    uint32_t *spi = reinterpret_cast<uint32_t *>(T + MQ_OFF_SPI);
+    uint32_t *poff = reinterpret_cast<uint32_t *>(T + MQ_OFF_POFF);
+    uint16_t *cid = reinterpret_cast<uint16_t *>(T + MQ_OFF_CID);
+    struct Ent {
+        uint32_t h, lo, hi, l;
+    };
+    std::vector<Ent> ents(count);
+    for (uint32_t l = 0; l < count; l++) {
+        const BatchPat &bp = j.bpats[mem[l]];
+        const uint8_t *pp = j.pats + j.pat_off[bp.index];
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (uint32_t k = 0; k < q; k++) w[k >> 2] |= (uint32_t)pp[k] << (8 * (k & 3));
+        const uint32_t nb = std::min<uint32_t>(bp.m - q, 8);
+        for (uint32_t k = 0; k < nb; k++) w[2 + (k >> 2)] |= (uint32_t)pp[q + k] << (8 * (k & 3));
+        pre2[2 * l] = w[2];
+        pre2[2 * l + 1] = w[3];
+        m16[l] = (uint16_t)bp.m;
+        spi[l] = mem[l];
+        poff[l] = (uint32_t)bp.pat_off;
+        ents[l] = {mq_key(w[0], w[1], q), w[0], w[1], l};
+        bits[ents[l].h >> 5] |= 1u << (ents[l].h & 31);
+    }
+    // buckets by hash, slots by prefix inside a bucket, m == q patterns first in a slot
+    std::sort(ents.begin(), ents.end(), [&](const Ent &x, const Ent &y) {
+        if (x.h != y.h) return x.h < y.h;
+        if (x.lo != y.lo) return x.lo < y.lo;
+        if (x.hi != y.hi) return x.hi < y.hi;
+        return x.l < y.l;
+    });
+    uint32_t nb = 0, ns = 0, np = 0;
+    for (uint32_t e = 0; e < count; e++) {
+        const Ent &x = ents[e];
+        const bool new_bucket = e == 0 || x.h != ents[e - 1].h;
+        const bool new_slot = new_bucket || x.lo != ents[e - 1].lo || x.hi != ents[e - 1].hi;
+        if (new_bucket) bstart[nb++] = (uint16_t)ns;
+        if (new_slot) {
+            spre[2 * ns] = x.lo;
+            spre[2 * ns + 1] = x.hi;
+            srep[ns] = (uint16_t)MQ_NONE;
+            sstart[ns] = (uint16_t)np;
+            ns++;
+        }
+        if (m16[x.l] == q) {  // counted by the slot: its first such pattern holds the count
+            if (srep[ns - 1] == MQ_NONE) srep[ns - 1] = (uint16_t)x.l;
+            cid[x.l] = srep[ns - 1];
+        } else {
+            pid[np++] = (uint16_t)x.l;
+            cid[x.l] = (uint16_t)x.l;
+        }
+    }
+    bstart[nb] = (uint16_t)ns;
+    sstart[ns] = (uint16_t)np;
+    uint32_t acc = 0;
+    for (int w = 0; w < MQ_WORDS; w++) {
+        rank[w] = (uint16_t)acc;
+        acc += (uint32_t)__builtin_popcount(bits[w]);
+    }
+    return np == 0 && ns == nb;
+}
+
 BatchLayout layout_of(const BatchJob &j, uint64_t single)
 {
     BatchLayout L;
@@ -65,6 +140,12 @@ BatchLayout layout_of(const BatchJob &j, uint64_t single)
     o = align_up(o + np * sizeof(BatchPat), 256);
     L.groups = o;
     o = align_up(o + j.groups.size() * sizeof(BatchGroup), 256);
+    L.cgroups = o;
+    o = align_up(o + j.cgroups.size() * sizeof(BatchGroup), 256);
+    L.mqgroups = o;
+    o = align_up(o + j.mq.size() * sizeof(MqGroup), 256);
+    L.mqtabs = o;
+    o = align_up(o + j.mqtab.size(), 256);
     L.params = o;
     o = align_up(o + np * sizeof(Params), 256);
     L.patbytes = o;
@@ -107,6 +188,14 @@ BatchLaunch launch_of(const BatchJob &j, uint8_t *ws)
     B.pats = reinterpret_cast<const BatchPat *>(ws + j.L.pats);
     B.groups = reinterpret_cast<const BatchGroup *>(ws + j.L.groups);
     B.host_groups = j.groups.data();
+    B.cgroups = reinterpret_cast<const BatchGroup *>(ws + j.L.cgroups);
+    B.host_cgroups = j.cgroups.data();
+    B.ncgroups = (uint32_t)j.cgroups.size();
+    B.mqgroups = reinterpret_cast<const MqGroup *>(ws + j.L.mqgroups);
+    B.host_mq = j.mq.data();
+    B.mqtabs = ws + j.L.mqtabs;
+    B.nmq = (uint32_t)j.mq.size();
+    B.mq_max_m = j.mq_max_m;
     B.params = reinterpret_cast<const Params *>(ws + j.L.params);
     B.patbytes = ws + j.L.patbytes;
     B.npats = (uint32_t)j.bpats.size();
@@ -193,26 +282,66 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         off += pat_region(bp.m);
     }
     j.patbytes = off;
-    for (uint32_t k = 0; k < j.bpats.size();) {
-        const BatchPat &b = j.bpats[k];
-        const uint32_t cap =
-            (uint32_t)std::min<int>(BATCH_GROUP_MAX, BATCH_TABLE_BYTES / table_bytes(b.algo, b.var));
-        BatchGroup g;
-        memset(&g, 0, sizeof g);
-        g.first = k;
-        g.algo = b.algo;
-        g.var = b.var;
-        while (k < j.bpats.size() && g.count < cap && j.bpats[k].algo == b.algo && j.bpats[k].var == b.var) {
-            g.max_m = std::max(g.max_m, j.bpats[k].m);
-            g.count++;
-            k++;
+    // q-classes (q = min(m, MQ_QMAX)) with at least MQ_MIN patterns are counted by
+    // the prefix filter; the others by their own scanners
+    std::vector<uint32_t> qcount(MQ_QMAX + 1, 0);
+    for (const auto &bp : j.bpats) qcount[std::min<uint32_t>(bp.m, MQ_QMAX)]++;
+    auto in_mq = [&](const BatchPat &bp) { return qcount[std::min<uint32_t>(bp.m, MQ_QMAX)] >= (uint32_t)MQ_MIN; };
+    // groups: consecutive sorted patterns of one kernel variant, within the LDS
+    // table budget; the count groups also stop at filtered patterns
+    auto make_groups = [&](std::vector<BatchGroup> &out, bool skip_mq) {
+        for (uint32_t k = 0; k < j.bpats.size();) {
+            if (skip_mq && in_mq(j.bpats[k])) {
+                k++;
+                continue;
+            }
+            const BatchPat &b = j.bpats[k];
+            const uint32_t cap =
+                (uint32_t)std::min<int>(BATCH_GROUP_MAX, BATCH_TABLE_BYTES / table_bytes(b.algo, b.var));
+            BatchGroup g;
+            memset(&g, 0, sizeof g);
+            g.first = k;
+            g.algo = b.algo;
+            g.var = b.var;
+            while (k < j.bpats.size() && g.count < cap && j.bpats[k].algo == b.algo &&
+                   j.bpats[k].var == b.var && !(skip_mq && in_mq(j.bpats[k]))) {
+                g.max_m = std::max(g.max_m, j.bpats[k].m);
+                g.count++;
+                k++;
+            }
+            out.push_back(g);
         }
-        j.groups.push_back(g);
+    };
+    make_groups(j.groups, false);
+    make_groups(j.cgroups, true);
+    // filter groups: each q-class by length, cut into groups of MQ_G
+    for (uint32_t q = 1; q <= (uint32_t)MQ_QMAX; q++) {
+        if (qcount[q] < (uint32_t)MQ_MIN) continue;
+        std::vector<uint32_t> mem;
+        for (uint32_t k = 0; k < j.bpats.size(); k++)
+            if (std::min<uint32_t>(j.bpats[k].m, MQ_QMAX) == q) mem.push_back(k);
+        std::stable_sort(mem.begin(), mem.end(), [&](uint32_t x, uint32_t y) { return j.bpats[x].m < j.bpats[y].m; });
+        for (size_t b = 0; b < mem.size(); b += MQ_G) {
+            const size_t e = std::min(mem.size(), b + (size_t)MQ_G);
+            MqGroup g;
+            memset(&g, 0, sizeof g);
+            g.count = (uint32_t)(e - b);
+            g.q = q;
+            g.min_m = j.bpats[mem[b]].m;
+            g.max_m = j.bpats[mem[e - 1]].m;
+            g.tab_off = (uint64_t)j.mq.size() * MQ_TAB_BYTES;
+            j.mq_max_m = std::max(j.mq_max_m, g.max_m);
+            j.mq.push_back(g);
+            j.mqtab.resize(j.mqtab.size() + MQ_TAB_BYTES, 0);
+            j.mq.back().flat = build_mq_table(j, mem.data() + b, g.count, q, j.mqtab.data() + g.tab_off) ? 1u : 0u;
+        }
     }
+    if (j.patbytes >= (1ull << 32)) return err(SM_EINVAL, "batch patterns exceed 4 GiB");
     if (!j.bpats.empty()) {
         j.ntiles = (c->n - min_m + 1 + BT - 1) / BT;
-        // aim for a few thousand (chunk, group) items
-        uint64_t want = j.ntiles * j.groups.size() / 4096;
+        // aim for several thousand (chunk, group) items in the count pass
+        const uint64_t ng = std::max<uint64_t>(1, j.cgroups.size() + j.mq.size());
+        uint64_t want = j.ntiles * ng / 8192;
         uint32_t ct = 1;
         while ((uint64_t)ct * 2 <= want && ct < 256) ct *= 2;
         j.chunk_tiles = ct;
@@ -229,6 +358,9 @@ void sm::batch_fill_image(const BatchJob &j, uint8_t *h)
     memset(h, 0, j.L.cnt);
     memcpy(h + j.L.pats, j.bpats.data(), j.bpats.size() * sizeof(BatchPat));
     memcpy(h + j.L.groups, j.groups.data(), j.groups.size() * sizeof(BatchGroup));
+    memcpy(h + j.L.cgroups, j.cgroups.data(), j.cgroups.size() * sizeof(BatchGroup));
+    memcpy(h + j.L.mqgroups, j.mq.data(), j.mq.size() * sizeof(MqGroup));
+    memcpy(h + j.L.mqtabs, j.mqtab.data(), j.mqtab.size());
     for (const auto &bp : j.bpats) memcpy(h + j.L.patbytes + bp.pat_off, j.pats + j.pat_off[bp.index], bp.m);
 }
 

@@ -243,6 +243,196 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Prefix filter count pass: one work item = (text chunk, filter group).
+// ---------------------------------------------------------------------------
+struct MqArgs {
+    const uint8_t *text;
+    uint64_t n;
+    const MqGroup *groups;
+    const uint8_t *tabs;
+    const uint8_t *patbytes;
+    uint32_t ngroups, chunk_tiles;
+    uint64_t nchunks, ntiles;
+    uint32_t *cnt;             // [sorted pattern][chunk]
+};
+
+struct MqShared {
+    uint4 text[B_CHUNKS];
+    uint4 tab[MQ_LDS_BYTES / 16];
+    uint32_t acc[MQ_G];
+};
+
+// Word k (bytes [4k, 4k + 4)) of the swizzled LDS tile.
+__device__ __forceinline__ uint32_t tile_word(const uint4 *text, uint32_t k)
+{
+    return reinterpret_cast<const uint32_t *>(text)[4 * swz(k >> 2) + (k & 3)];
+}
+
+// A start whose q-gram hash bit is set: the slots of its bucket whose prefix
+// equals the key (lo, hi) are counted (m == q) or their patterns checked.
+// x: LDS byte index of the start; g: its global position.
+__device__ __forceinline__ void mq_candidate(MqShared &S, const MqArgs &a, const uint32_t *poff,
+                                             uint32_t h, uint32_t wbits, uint32_t lo, uint32_t hi,
+                                             uint32_t x, uint64_t g, uint32_t q)
+{
+    const uint8_t *T = reinterpret_cast<const uint8_t *>(S.tab);
+    const uint16_t *rank = reinterpret_cast<const uint16_t *>(T + MQ_OFF_RANK);
+    const uint16_t *bstart = reinterpret_cast<const uint16_t *>(T + MQ_OFF_BSTART);
+    const uint2 *spre = reinterpret_cast<const uint2 *>(T + MQ_OFF_SPRE);
+    const uint16_t *sstart = reinterpret_cast<const uint16_t *>(T + MQ_OFF_SSTART);
+    const uint16_t *srep = reinterpret_cast<const uint16_t *>(T + MQ_OFF_SREP);
+    const uint16_t *pid = reinterpret_cast<const uint16_t *>(T + MQ_OFF_PID);
+    const uint16_t *m16 = reinterpret_cast<const uint16_t *>(T + MQ_OFF_M);
+    const uint2 *pre2 = reinterpret_cast<const uint2 *>(T + MQ_OFF_PRE2);
+    const uint32_t k = (uint32_t)rank[h >> 5] + (uint32_t)__builtin_popcount(wbits & ((1u << (h & 31)) - 1u));
+    const uint32_t s1 = bstart[k + 1];
+    for (uint32_t sl = bstart[k]; sl < s1; sl++) {
+        const uint2 p = spre[sl];
+        if ((p.x ^ lo) | (p.y ^ hi)) continue;
+        const uint32_t rep = srep[sl];
+        if (rep != MQ_NONE) atomicAdd(&S.acc[rep], 1u);  // the slot's patterns with m == q
+        const uint32_t e1 = sstart[sl + 1];
+        if (sstart[sl] == e1) continue;
+        // bytes [q, q + 8) of the text at this start, from the tile
+        const uint32_t y = x + q, wi = y >> 2, sb = y & 3;
+        const uint32_t w0 = tile_word(S.text, wi), w1 = tile_word(S.text, wi + 1), w2 = tile_word(S.text, wi + 2);
+        const uint32_t t0 = alignbyte(w1, w0, sb), t1 = alignbyte(w2, w1, sb);
+        for (uint32_t e = sstart[sl]; e < e1; e++) {
+            const uint32_t j = pid[e];
+            const uint32_t m = m16[j];
+            if (g + m > a.n) continue;
+            const uint32_t nb = m - q < 8 ? m - q : 8;
+            const uint2 p2 = pre2[j];
+            if (((t0 ^ p2.x) & byte_mask(nb < 4 ? (int)nb : 4)) | ((t1 ^ p2.y) & byte_mask(nb > 4 ? (int)nb - 4 : 0)))
+                continue;
+            bool ok = true;
+            if (m > q + 8) {  // the rest of the pattern, 16 bytes at a time, from global memory
+                const uint8_t *pat = a.patbytes + poff[j];
+                const uint8_t *tl = a.text + g + m - 1, *pl = pat + m + 15;
+                for (uint32_t off = q + 8; off < m && ok; off += 16)
+                    ok = diff16(load16(a.text + g + off, tl), load16(pat + off, pl), m - off < 16 ? m - off : 16) == 0;
+            }
+            if (ok) atomicAdd(&S.acc[j], 1u);
+        }
+    }
+}
+
+// EXACT: q <= 2, the key itself indexes the bitmap.
+template <bool EXACT>
+__global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
+{
+    __shared__ MqShared S;
+    const uint64_t item = blockIdx.x;
+    const uint64_t chunk = item / a.ngroups;
+    const MqGroup g = a.groups[item % a.ngroups];
+    const int tid = threadIdx.x;
+    const uint8_t *tab = a.tabs + g.tab_off;
+    {   // the group's table (bitmap, ranks, buckets, slots, prefixes, lengths) and counters
+        const uint4 *src = reinterpret_cast<const uint4 *>(tab);
+        for (uint32_t k = tid; k < MQ_LDS_BYTES / 16; k += BLOCK) S.tab[k] = src[k];
+        for (uint32_t k = tid; k < g.count; k += BLOCK) S.acc[k] = 0;
+    }
+    const uint32_t *poff = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_POFF);
+    const uint32_t *bits = reinterpret_cast<const uint32_t *>(S.tab);
+    const uint32_t q = g.q;
+    const uint32_t mlo = byte_mask(q < 4 ? (int)q : 4), mhi = byte_mask(q > 4 ? (int)q - 4 : 0);
+    const uint64_t t0 = chunk * a.chunk_tiles;
+    uint64_t t1 = t0 + a.chunk_tiles;
+    if (t1 > a.ntiles) t1 = a.ntiles;
+    // tiles with a start of some pattern of the group: s + min_m <= n
+    const uint64_t tl = a.n >= g.min_m ? (a.n - g.min_m) / BT + 1 : 0;
+    if (t1 > tl) t1 = tl;
+    Staged<B_PER> st;
+    if (t0 < t1) {
+        uint64_t x1 = t0 * (uint64_t)BT + (uint64_t)BT + g.max_m - 1;
+        stage_issue(st, a.text, t0 * (uint64_t)BT, x1 < a.n ? x1 : a.n);
+    }
+    for (uint64_t t = t0; t < t1; t++) {
+        const uint64_t s = t * (uint64_t)BT;
+        __syncthreads();  // previous tile's readers are done; tables visible
+        stage_commit<true>(st, S.text);
+        const int boff = st.boff;
+        __syncthreads();
+        if (t + 1 < t1) {  // next tile's loads fly while this one is scanned
+            const uint64_t s2 = s + (uint64_t)BT;
+            const uint64_t x1 = s2 + (uint64_t)BT + g.max_m - 1;
+            stage_issue(st, a.text, s2, x1 < a.n ? x1 : a.n);
+        }
+        const uint64_t lim = a.n - g.min_m - s;  // largest relative start of the group
+        const int hi_rel = lim >= (uint64_t)(BT - 1) ? BT - 1 : (int)lim;
+        const int lo = tid * BL;
+        const int hi = (lo + BL - 1) < hi_rel ? (lo + BL - 1) : hi_rel;
+        if (lo > hi) continue;
+        const int u0 = (boff + lo) >> 4, u1 = (boff + hi) >> 4;
+        uint4 nx = S.text[swz((uint32_t)u0)];
+        for (int u = u0; u <= u1; u++) {
+            const uint4 cu = nx;
+            nx = S.text[swz((uint32_t)(u + 1))];
+            const uint32_t W[8] = {cu.x, cu.y, cu.z, cu.w, nx.x, nx.y, nx.z, nx.w};
+            uint32_t hh[16], wb[16];
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const int i = b >> 2, sh = b & 3;
+                const uint32_t klo = (sh ? alignbyte(W[i + 1], W[i], sh) : W[i]) & mlo;
+                const uint32_t khi = EXACT ? 0u : ((sh ? alignbyte(W[i + 2], W[i + 1], sh) : W[i + 1]) & mhi);
+                hh[b] = EXACT ? klo : mq_hash(klo, khi);
+                wb[b] = bits[hh[b] >> 5];
+            }
+            uint32_t cm = 0;
+#pragma unroll
+            for (int b = 0; b < 16; b++) cm |= __builtin_amdgcn_ubfe(wb[b], hh[b] & 31, 1) << b;
+            const int r0 = 16 * u - boff;  // relative start of byte 0 of this chunk
+            if (g.flat && __ballot(__builtin_popcount(cm) >= 4)) {
+                // dense candidates in a flat group: bucket = slot, all 16 starts'
+                // lookups at once; a start counts when its bit is set, it lies in the
+                // lane's range and its key equals the slot's prefix
+                const uint8_t *T = reinterpret_cast<const uint8_t *>(S.tab);
+                const uint16_t *rank = reinterpret_cast<const uint16_t *>(T + MQ_OFF_RANK);
+                const uint2 *spre = reinterpret_cast<const uint2 *>(T + MQ_OFF_SPRE);
+                const uint16_t *srep = reinterpret_cast<const uint16_t *>(T + MQ_OFF_SREP);
+                uint32_t kk[16];
+#pragma unroll
+                for (int b = 0; b < 16; b++) {
+                    const int r = r0 + b;
+                    if (r < lo || r > hi) cm &= ~(1u << b);
+                    const uint32_t below = wb[b] & ((1u << (hh[b] & 31)) - 1u);
+                    kk[b] = ((cm >> b) & 1u) ? (uint32_t)rank[hh[b] >> 5] + (uint32_t)__builtin_popcount(below) : 0u;
+                }
+#pragma unroll
+                for (int b = 0; b < 16; b++) {
+                    const int i = b >> 2, sh = b & 3;
+                    const uint32_t klo = (sh ? alignbyte(W[i + 1], W[i], sh) : W[i]) & mlo;
+                    const uint32_t khi = EXACT ? 0u : ((sh ? alignbyte(W[i + 2], W[i + 1], sh) : W[i + 1]) & mhi);
+                    const uint2 p = spre[kk[b]];
+                    const uint32_t rep = srep[kk[b]];
+                    if (((cm >> b) & 1u) && !((p.x ^ klo) | (p.y ^ khi))) atomicAdd(&S.acc[rep], 1u);
+                }
+                continue;
+            }
+            // this lane's candidates, one per iteration (a wave iterates as often as
+            // its busiest lane); the key is read again from the tile
+            while (cm) {
+                const int b = __builtin_ctz(cm);
+                cm &= cm - 1;
+                const int r = r0 + b;
+                if (r < lo || r > hi) continue;
+                const uint32_t x = (uint32_t)(16 * u + b), wi = x >> 2, sb = x & 3;
+                const uint32_t w0 = tile_word(S.text, wi), w1 = tile_word(S.text, wi + 1);
+                const uint32_t klo = alignbyte(w1, w0, sb) & mlo;
+                const uint32_t khi = EXACT ? 0u : (alignbyte(tile_word(S.text, wi + 2), w1, sb) & mhi);
+                const uint32_t h = EXACT ? klo : mq_hash(klo, khi);
+                mq_candidate(S, a, poff, h, bits[h >> 5], klo, khi, x, s + (uint64_t)r, q);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t *spi = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_SPI);
+    const uint16_t *cid = reinterpret_cast<const uint16_t *>(tab + MQ_OFF_CID);
+    for (uint32_t j = tid; j < g.count; j += BLOCK)
+        a.cnt[(uint64_t)spi[j] * a.nchunks + chunk] = S.acc[cid[j]];
+}
+
 // One workgroup per pattern: tables into params[j].
 __global__ __launch_bounds__(BLOCK) void batch_prep_kernel(const BatchPat *pats, const uint8_t *patbytes,
                                                            Params *params)
@@ -381,17 +571,48 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // one launch per run of groups that share a kernel variant
+    const BatchGroup *hg = L.write ? L.host_groups : L.host_cgroups;
+    const uint32_t ng = L.write ? L.ngroups : L.ncgroups;
+    a.groups = L.write ? L.groups : L.cgroups;
     uint32_t g = 0;
-    while (g < L.ngroups) {
+    while (g < ng) {
         uint32_t h = g + 1;
-        while (h < L.ngroups && L.host_groups[h].algo == L.host_groups[g].algo &&
-               L.host_groups[h].var == L.host_groups[g].var)
-            h++;
+        while (h < ng && hg[h].algo == hg[g].algo && hg[h].var == hg[g].var) h++;
         a.group_lo = g;
         a.ngroups = h - g;
-        if ((e = launch_batch_class(L.host_groups[g].algo, L.host_groups[g].var, a, L.write, st)) != hipSuccess)
-            return e;
+        if ((e = launch_batch_class(hg[g].algo, hg[g].var, a, L.write, st)) != hipSuccess) return e;
         g = h;
+    }
+    if (!L.write && L.nmq) {
+        MqArgs m;
+        memset(&m, 0, sizeof m);
+        m.text = L.text;
+        m.n = L.n;
+        m.groups = L.mqgroups;
+        m.tabs = L.mqtabs;
+        m.patbytes = L.patbytes;
+        m.ngroups = L.nmq;
+        m.chunk_tiles = L.chunk_tiles;
+        m.nchunks = L.nchunks;
+        m.ntiles = L.ntiles;
+        m.cnt = L.cnt;
+        // one launch for the exact-key groups (q <= 2), one for the hashed ones; the
+        // groups are ordered by q, so each launch takes a contiguous range
+        uint32_t nexact = 0;
+        while (nexact < L.nmq && L.host_mq[nexact].q <= 2) nexact++;
+        for (int pass = 0; pass < 2; pass++) {
+            const uint32_t g0 = pass ? nexact : 0, g1 = pass ? L.nmq : nexact;
+            if (g1 == g0) continue;
+            m.groups = L.mqgroups + g0;
+            m.ngroups = g1 - g0;
+            const uint64_t grid = L.nchunks * (g1 - g0);
+            if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+            if (pass == 0)
+                hipLaunchKernelGGL(mq_count_kernel<true>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, m);
+            else
+                hipLaunchKernelGGL(mq_count_kernel<false>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, m);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     if (!L.write) {
         hipLaunchKernelGGL(batch_seg_scan_kernel, dim3(L.npats), dim3(BLOCK), 0, st, L.pats, L.cnt,

@@ -13,7 +13,8 @@
 namespace sm {
 
 struct BatchLayout {  // byte offsets inside the batch workspace
-    uint64_t pats, groups, params, patbytes, cnt, chunk_off, totals, csr, single, need;
+    uint64_t pats, groups, cgroups, mqgroups, mqtabs, params, patbytes, cnt, chunk_off, totals, csr,
+        single, need;
 };
 
 struct BatchJob {
@@ -22,7 +23,11 @@ struct BatchJob {
     const uint8_t *pats = nullptr;    // host pattern bytes, valid for the job's life
     const uint64_t *pat_off = nullptr;
     std::vector<BatchPat> bpats;      // patterns searched inside batch launches, sorted
-    std::vector<BatchGroup> groups;
+    std::vector<BatchGroup> groups;   // write pass: all batch patterns
+    std::vector<BatchGroup> cgroups;  // count pass: patterns outside the prefix filter
+    std::vector<MqGroup> mq;          // count pass: prefix filter groups
+    std::vector<uint8_t> mqtab;       // their tables (MQ_TAB_BYTES each)
+    uint32_t mq_max_m = 0;
     std::vector<uint32_t> longp;      // m > BATCH_MAX_M: searched one pattern at a time
     uint64_t patbytes = 0;
     uint32_t chunk_tiles = 1;

@@ -116,6 +116,55 @@ constexpr int BATCH_TABLE_BYTES = 32768; // LDS for a group's tables
 constexpr int BATCH_GROUP_MAX = 32;      // patterns per group
 constexpr int BATCH_HBITS_MAX = 10;      // Hash-q table bits inside a batch (1 KB per pattern)
 
+// Multi-pattern prefix filter of the batched count pass. The patterns of one
+// q-class (q = min(m, MQ_QMAX)) are cut into groups of at most MQ_G. A group keeps
+// a bitmap over MQ_H-bit hashes of its patterns' first q bytes; a set bit leads
+// (through the bucket's rank) to the slots of the distinct q-byte prefixes with
+// that hash, and a slot to its patterns. Patterns with m == q are counted once
+// per slot; longer ones are checked on bytes [q, q + 8) from a per-pattern copy
+// and beyond that against the pattern itself.
+constexpr int MQ_H = 16;                    // hash bits (bitmap of 2^16 bits)
+constexpr int MQ_WORDS = 1 << (MQ_H - 5);   // bitmap words
+constexpr int MQ_G = 1024;                  // patterns per group
+constexpr int MQ_QMAX = 8;                  // longest prefix gram (two 32-bit words)
+constexpr int MQ_MIN = 3;                   // smallest q-class sent to the filter
+constexpr uint32_t MQ_NONE = 0xFFFF;
+
+// Table of one group (byte offsets; the part below MQ_LDS_BYTES is staged in LDS).
+constexpr uint32_t MQ_OFF_BITS = 0;                                // u32[MQ_WORDS]
+constexpr uint32_t MQ_OFF_RANK = MQ_OFF_BITS + 4 * MQ_WORDS;       // u16[MQ_WORDS]: set bits before the word
+constexpr uint32_t MQ_OFF_BSTART = MQ_OFF_RANK + 2 * MQ_WORDS;     // u16[MQ_G + 8]: bucket -> first slot
+constexpr uint32_t MQ_OFF_SPRE = MQ_OFF_BSTART + 2 * (MQ_G + 8);   // uint2[MQ_G]: slot prefix (q bytes)
+constexpr uint32_t MQ_OFF_SSTART = MQ_OFF_SPRE + 8 * MQ_G;         // u16[MQ_G + 8]: slot -> first long pattern
+constexpr uint32_t MQ_OFF_SREP = MQ_OFF_SSTART + 2 * (MQ_G + 8);   // u16[MQ_G]: slot's counter for m == q, or MQ_NONE
+constexpr uint32_t MQ_OFF_PID = MQ_OFF_SREP + 2 * MQ_G;            // u16[MQ_G]: patterns with m > q, by slot
+constexpr uint32_t MQ_OFF_M = MQ_OFF_PID + 2 * MQ_G;               // u16[MQ_G]: lengths
+constexpr uint32_t MQ_OFF_PRE2 = MQ_OFF_M + 2 * MQ_G;              // uint2[MQ_G]: bytes [q, q + 8) (masked)
+constexpr uint32_t MQ_LDS_BYTES = MQ_OFF_PRE2 + 8 * MQ_G;
+constexpr uint32_t MQ_OFF_SPI = MQ_LDS_BYTES;                      // u32[MQ_G]: sorted pattern index
+constexpr uint32_t MQ_OFF_POFF = MQ_OFF_SPI + 4 * MQ_G;            // u32[MQ_G]: byte offset of the pattern
+constexpr uint32_t MQ_OFF_CID = MQ_OFF_POFF + 4 * MQ_G;            // u16[MQ_G]: counter holding its count
+constexpr uint32_t MQ_TAB_BYTES = MQ_OFF_CID + 2 * MQ_G;
+
+struct MqGroup {
+    uint32_t count, q, min_m, max_m;
+    uint32_t flat;     // every pattern has m == q and every bucket holds one slot
+    uint32_t pad;
+    uint64_t tab_off;  // byte offset of the group's table
+};
+
+// Hash of a q-gram packed little-endian into (lo, hi) with the bytes past q
+// zero. q <= 2 keys are used directly (exact); longer ones are hashed. Host and
+// device use the same functions.
+__host__ __device__ inline uint32_t mq_hash(uint32_t lo, uint32_t hi)
+{
+    return ((lo * 0x9E3779B1u) ^ (hi * 0x85EBCA77u)) >> (32 - MQ_H);
+}
+__host__ __device__ inline uint32_t mq_key(uint32_t lo, uint32_t hi, uint32_t q)
+{
+    return q <= 2 ? lo : mq_hash(lo, hi);
+}
+
 struct BatchPat {      // one pattern, in the batch's sorted order
     uint64_t pat_off;  // offset of its bytes in the device pattern buffer (16-byte aligned)
     uint32_t m, algo, var, q, hbits;
@@ -130,8 +179,15 @@ struct BatchLaunch {
     const uint8_t *text;
     uint64_t n;
     const BatchPat *pats;
-    const BatchGroup *groups;
+    const BatchGroup *groups;       // write pass: every pattern
     const BatchGroup *host_groups;
+    const BatchGroup *cgroups;      // count pass, per-pattern scanners (patterns outside the filter)
+    const BatchGroup *host_cgroups;
+    uint32_t ncgroups;
+    const MqGroup *mqgroups;        // count pass, prefix filter (ordered by q)
+    const MqGroup *host_mq;
+    const uint8_t *mqtabs;
+    uint32_t nmq, mq_max_m;
     const Params *params;
     const uint8_t *patbytes;
     uint32_t npats;        // patterns in this launch set (sorted)

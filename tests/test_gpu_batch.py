@@ -128,3 +128,45 @@ def test_batch_matches_single_path(sm):
         single = sm.find_all(t_dev, p).cpu().numpy()
         assert np.array_equal(pos[off[i]:off[i + 1]], single), i
     c.close()
+
+
+def test_batch_prefix_filter_many_patterns(sm):
+    """Thousands of patterns per q-class: shared hash buckets, exact 1- and 2-byte
+    keys, duplicates, and a 1024-pattern group boundary."""
+    t_np = dg.zipf_text(150_001, 256, 1.1, seed=41)
+    pats = []
+    for i in range(1500):
+        pats.append(dg.random_pattern(3, 256, seed=42, idx=i))           # hashed q = 3
+    for i in range(1300):
+        pats.append(dg.substring_pattern(t_np, 8 + i % 40, seed=43, idx=i)[0])  # q = 8, two groups
+    for i in range(300):
+        pats.append(dg.substring_pattern(t_np, 2, seed=44, idx=i)[0])    # exact q = 2
+    pats += [b"\x00", b"\x01", b"\x00"]                                   # q = 1, duplicate
+    pats += pats[:50]                                                     # duplicates
+    c = sm.Corpus(t_np)
+    counts = c.batch_count(pats)
+    want = np.array([oracle.count(t_np, p) for p in pats], dtype=np.uint64)
+    assert np.array_equal(counts, want)
+    sub = pats[1500:1600] + pats[-60:]
+    pos, off = c.batch_find_all(sub)
+    check_csr(sm, t_np, sub, pos, off)
+    c.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 40])
+def test_batch_filter_threshold_and_dense_classes(sm, k):
+    """k patterns per length 4..7 and 8..12 on a 4-letter text (dense prefix
+    hits): classes below the filter threshold use the per-pattern scanners."""
+    t_np = dg.uniform_text(250_003, 4, seed=50 + k)
+    pats = []
+    for m in list(range(1, 13)) + [64, 65, 300]:
+        for i in range(k):
+            pats.append(dg.substring_pattern(t_np, m, seed=51, idx=m * 100 + i)[0] if i % 2 == 0
+                        else dg.random_pattern(m, 4, seed=51, idx=m * 100 + i))
+    c = sm.Corpus(t_np)
+    counts = c.batch_count(pats)
+    want = np.array([oracle.count(t_np, p) for p in pats], dtype=np.uint64)
+    assert np.array_equal(counts, want)
+    pos, off = c.batch_find_all(pats)
+    check_csr(sm, t_np, pats, pos, off)
+    c.close()
