@@ -395,12 +395,12 @@ def serving_section(args, dev):
     log("serving: corpora and %d queries ready in %.1fs" % (sum(len(t[2]) for t in traces),
                                                            time.time() - t0))
 
-    srv = sm.Server()
+    srv = sm.Server(host_bytes=8 << 30)
     ids = [srv.add_corpus(c) for c in corpora]
     out = {"workload": "3 resident corpora (%s); Poisson arrivals; m log-uniform [4,256]; half "
                        "substrings, half random; latency = arrival -> positions on host"
                        % "; ".join(names),
-           "server": {"slots": 2, "max_batch": 256, "pool_GiB": 16, "host_arena_GiB": 2},
+           "server": {"slots": 2, "max_batch": 256, "pool_GiB": 16, "host_arena_GiB": 8},
            "rates": []}
 
     def replay_server(arr, qs):

@@ -186,6 +186,14 @@ int sm_batch_offsets(const sm_batch *batch, uint64_t *out_off);
 int sm_batch_write_async(sm_batch *batch, uint64_t lo, uint64_t hi, int64_t *d_out, void *stream);
 int sm_batch_close(sm_batch *batch);
 int sm_batch_set_wave_bytes(uint64_t bytes);
+/* How the write pass of sm_batch_open, sm_batch_find_all and the server finds the
+ * positions of each pattern with occurrences (speed only, never results):
+ * 0 = automatic (from the counts: a shared prefix-filter pass for q-classes whose
+ * patterns would otherwise rescan most of the text), 1 = every pattern's own
+ * scanner, 2 = the shared pass for every pattern sparse enough for it (at most 16
+ * occurrences per 4096 text bytes) in q-classes of at least 3 such patterns.
+ * Process-wide; SM_EINVAL outside 0..2. */
+int sm_batch_set_write_policy(int policy);
 
 /*
  * Server: continuous batching of single-pattern queries over resident corpora

@@ -21,7 +21,7 @@ from ._native import (ALGO_AUTO, ALGO_BNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
 __all__ = ["pack_patterns", "find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
            "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_NAMES", "version",
-           "Batch", "Server", "batch_set_wave_bytes", "now_ns"]
+           "Batch", "Server", "batch_set_wave_bytes", "batch_set_write_policy", "now_ns"]
 
 
 def version() -> str:
@@ -317,6 +317,12 @@ class Batch:
 def batch_set_wave_bytes(nbytes: int) -> None:
     """Output-wave budget of the synchronous batched find_all (0 = default 16 GiB)."""
     check(load().sm_batch_set_wave_bytes(nbytes))
+
+
+def batch_set_write_policy(policy: int) -> None:
+    """Batched write pass: 0 automatic, 1 each pattern's own scanner, 2 shared filter
+    whenever the pattern is sparse enough (speed only; results are identical)."""
+    check(load().sm_batch_set_write_policy(policy))
 
 
 def now_ns() -> int:

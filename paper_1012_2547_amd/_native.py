@@ -110,6 +110,7 @@ PROTOTYPES = {
     "sm_batch_write_async": (_i32, [_vp, _u64, _u64, _vp, _vp]),
     "sm_batch_close": (_i32, [_vp]),
     "sm_batch_set_wave_bytes": (_i32, [_u64]),
+    "sm_batch_set_write_policy": (_i32, [_i32]),
     "sm_now_ns": (ctypes.c_int64, []),
     "sm_server_create": (_i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
     "sm_server_add_corpus": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -60,7 +62,8 @@ uint64_t pat_region(uint64_t m) { return align_up(m, 16) + 16; }  // verify read
 // mem[0 .. count) (sorted indices) of q-class q.
 // Returns whether the group is flat (every pattern has m == q and every bucket
 // holds one slot).
-bool build_mq_table(const BatchJob &j, const uint32_t *mem, uint32_t count, uint32_t q, uint8_t *T)
+bool build_mq_table(const BatchJob &j, const uint32_t *mem, uint32_t count, uint32_t q, uint8_t *T,
+                    bool slot_counts)
 {
     uint32_t *bits = reinterpret_cast<uint32_t *>(T + MQ_OFF_BITS);
     uint16_t *rank = reinterpret_cast<uint16_t *>(T + MQ_OFF_RANK);
@@ -113,7 +116,7 @@ bool build_mq_table(const BatchJob &j, const uint32_t *mem, uint32_t count, uint
             sstart[ns] = (uint16_t)np;
             ns++;
         }
-        if (m16[x.l] == q) {  // counted by the slot: its first such pattern holds the count
+        if (slot_counts && m16[x.l] == q) {  // counted by the slot: its first such pattern holds the count
             if (srep[ns - 1] == MQ_NONE) srep[ns - 1] = (uint16_t)x.l;
             cid[x.l] = srep[ns - 1];
         } else {
@@ -158,6 +161,12 @@ BatchLayout layout_of(const BatchJob &j, uint64_t single)
     o = align_up(o + (uint64_t)j.P * 8, 256);
     L.csr = o;
     o = align_up(o + ((uint64_t)j.P + 1) * 8, 256);
+    L.wgroups = o;
+    o = align_up(o + np * sizeof(BatchGroup), 256);
+    L.mqwgroups = o;
+    o = align_up(o + (uint64_t)j.max_mqw * sizeof(MqGroup), 256);
+    L.mqwtabs = o;
+    o = align_up(o + (uint64_t)j.max_mqw * MQ_TAB_BYTES, 256);
     L.single = o;
     o = align_up(o + single, 256);
     L.need = o;
@@ -333,10 +342,11 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
             j.mq_max_m = std::max(j.mq_max_m, g.max_m);
             j.mq.push_back(g);
             j.mqtab.resize(j.mqtab.size() + MQ_TAB_BYTES, 0);
-            j.mq.back().flat = build_mq_table(j, mem.data() + b, g.count, q, j.mqtab.data() + g.tab_off) ? 1u : 0u;
+            j.mq.back().flat = build_mq_table(j, mem.data() + b, g.count, q, j.mqtab.data() + g.tab_off, true) ? 1u : 0u;
         }
     }
     if (j.patbytes >= (1ull << 32)) return err(SM_EINVAL, "batch patterns exceed 4 GiB");
+    j.max_mqw = (uint32_t)(j.bpats.size() / MQ_G + MQ_QMAX);
     if (!j.bpats.empty()) {
         j.ntiles = (c->n - min_m + 1 + BT - 1) / BT;
         // aim for several thousand (chunk, group) items in the count pass
@@ -400,6 +410,113 @@ int sm::batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, ui
     return SM_OK;
 }
 
+namespace {
+std::atomic<int> g_write_policy{0};  // 0 automatic, 1 own scanners only, 2 shared filter when sparse
+}
+
+extern "C" int sm_batch_set_write_policy(int policy)
+{
+    if (policy < 0 || policy > 2) return err(SM_EINVAL, "write policy must be 0, 1 or 2");
+    g_write_policy = policy;
+    return SM_OK;
+}
+
+int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStream_t st)
+{
+    const int policy = g_write_policy;
+    j.wplan = true;
+    j.wgroups.clear();
+    j.mqw.clear();
+    j.mqwtab.clear();
+    if (j.bpats.empty()) return SM_OK;
+    // A pattern may share a filter write pass when its own scanner would rescan at
+    // least 1/16 of the text (the chunks holding its hits; estimated from its
+    // count) and its hits are sparse enough to be sorted in LDS (at most 16 per
+    // 4096 starts on average). A q-class shares a pass when the rescans it replaces
+    // exceed 2.5 texts: one shared pass runs at about 2/5 of a per-pattern rescan's
+    // rate.
+    const double n = (double)j.c->n, nch = (double)j.nchunks;
+    const double chunk_bytes = (double)j.chunk_tiles * BT;
+    std::vector<uint8_t> route(j.bpats.size(), 0);  // 0: none, 1: own scanner, 2: filter
+    std::vector<double> qcover(MQ_QMAX + 1, 0.0);
+    std::vector<uint32_t> qn(MQ_QMAX + 1, 0);
+    for (size_t k = 0; k < j.bpats.size(); k++) {
+        const uint32_t i = j.bpats[k].index;
+        const double c = (double)(h_csr[i + 1] - h_csr[i]);
+        if (c == 0) continue;
+        const double cover = nch * (1.0 - std::exp(-c / nch)) * chunk_bytes;
+        const bool sparse = c * 4096.0 / n <= 16.0;
+        const bool filt = policy == 2 ? sparse : (policy == 0 && sparse && cover * 16 >= n);
+        route[k] = filt ? 2 : 1;
+        if (filt) {
+            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
+            qcover[qc] += cover;
+            qn[qc]++;
+        }
+    }
+    for (size_t k = 0; k < j.bpats.size(); k++) {
+        const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
+        if (route[k] == 2 && (qn[qc] < (uint32_t)MQ_MIN || (policy == 0 && qcover[qc] < 2.5 * n))) route[k] = 1;
+    }
+    // per-pattern write groups: consecutive sorted patterns routed to their own scanner
+    for (uint32_t k = 0; k < j.bpats.size();) {
+        if (route[k] != 1) {
+            k++;
+            continue;
+        }
+        const BatchPat &b = j.bpats[k];
+        const uint32_t cap =
+            (uint32_t)std::min<int>(BATCH_GROUP_MAX, BATCH_TABLE_BYTES / table_bytes(b.algo, b.var));
+        BatchGroup g;
+        memset(&g, 0, sizeof g);
+        g.first = k;
+        g.algo = b.algo;
+        g.var = b.var;
+        while (k < j.bpats.size() && g.count < cap && route[k] == 1 && j.bpats[k].algo == b.algo &&
+               j.bpats[k].var == b.var) {
+            g.max_m = std::max(g.max_m, j.bpats[k].m);
+            g.count++;
+            k++;
+        }
+        if (g.count == 0) {
+            k++;
+            continue;
+        }
+        j.wgroups.push_back(g);
+    }
+    // filter write groups: each q-class by length, in groups of MQ_G
+    for (uint32_t q = 1; q <= (uint32_t)MQ_QMAX; q++) {
+        std::vector<uint32_t> mem;
+        for (uint32_t k = 0; k < j.bpats.size(); k++)
+            if (route[k] == 2 && std::min<uint32_t>(j.bpats[k].m, MQ_QMAX) == q) mem.push_back(k);
+        std::stable_sort(mem.begin(), mem.end(), [&](uint32_t x, uint32_t y) { return j.bpats[x].m < j.bpats[y].m; });
+        for (size_t b = 0; b < mem.size(); b += MQ_G) {
+            const size_t e = std::min(mem.size(), b + (size_t)MQ_G);
+            MqGroup g;
+            memset(&g, 0, sizeof g);
+            g.count = (uint32_t)(e - b);
+            g.q = q;
+            g.min_m = j.bpats[mem[b]].m;
+            g.max_m = j.bpats[mem[e - 1]].m;
+            g.tab_off = (uint64_t)j.mqw.size() * MQ_TAB_BYTES;
+            j.mqw.push_back(g);
+            j.mqwtab.resize(j.mqwtab.size() + MQ_TAB_BYTES, 0);
+            build_mq_table(j, mem.data() + b, g.count, q, j.mqwtab.data() + g.tab_off, false);
+        }
+    }
+    if (j.mqw.size() > j.max_mqw) return err(SM_EDEVICE, "internal: write plan larger than its workspace");
+    // the plan into the workspace (a pageable source is consumed before the call returns)
+    if (!j.wgroups.empty())
+        HIP_OK(hipMemcpyAsync(ws + j.L.wgroups, j.wgroups.data(), j.wgroups.size() * sizeof(BatchGroup),
+                              hipMemcpyHostToDevice, st));
+    if (!j.mqw.empty()) {
+        HIP_OK(hipMemcpyAsync(ws + j.L.mqwgroups, j.mqw.data(), j.mqw.size() * sizeof(MqGroup),
+                              hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(ws + j.L.mqwtabs, j.mqwtab.data(), j.mqwtab.size(), hipMemcpyHostToDevice, st));
+    }
+    return SM_OK;
+}
+
 int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, const uint64_t *h_csr,
                             uint64_t *d_totals, int64_t *d_out, uint64_t lo, uint64_t hi,
                             hipStream_t st)
@@ -407,6 +524,15 @@ int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, con
     if (hi <= lo) return SM_OK;
     if (!j.bpats.empty()) {
         BatchLaunch B = launch_of(j, ws);
+        if (j.wplan) {
+            B.groups = reinterpret_cast<const BatchGroup *>(ws + j.L.wgroups);
+            B.host_groups = j.wgroups.data();
+            B.ngroups = (uint32_t)j.wgroups.size();
+            B.mqwgroups = reinterpret_cast<const MqGroup *>(ws + j.L.mqwgroups);
+            B.host_mqw = j.mqw.data();
+            B.mqwtabs = ws + j.L.mqwtabs;
+            B.nmqw = (uint32_t)j.mqw.size();
+        }
         B.chunk_off = reinterpret_cast<const uint64_t *>(ws + j.L.chunk_off);
         B.csr = d_csr;
         B.out = d_out;
@@ -466,6 +592,8 @@ extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *
     if ((r = batch_count_enqueue(b->j, b->ws, nullptr, d_tot, d_csr, true, nullptr))) return r;
     b->csr.resize((uint64_t)P + 1);
     HIP_OK(hipMemcpy(b->csr.data(), d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost));
+    if ((r = batch_write_plan(b->j, b->ws, b->csr.data(), nullptr))) return r;
+    HIP_OK(hipStreamSynchronize(nullptr));
     *out = b.release();
     return SM_OK;
 }

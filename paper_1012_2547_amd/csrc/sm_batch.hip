@@ -270,13 +270,17 @@ __device__ __forceinline__ uint32_t tile_word(const uint4 *text, uint32_t k)
 }
 
 // A start whose q-gram hash bit is set: the slots of its bucket whose prefix
-// equals the key (lo, hi) are counted (m == q) or their patterns checked.
-// x: LDS byte index of the start; g: its global position.
-__device__ __forceinline__ void mq_candidate(MqShared &S, const MqArgs &a, const uint32_t *poff,
-                                             uint32_t h, uint32_t wbits, uint32_t lo, uint32_t hi,
-                                             uint32_t x, uint64_t g, uint32_t q)
+// equals the key (lo, hi) are taken. A slot's m == q patterns (when the table
+// keeps them apart) go to one counter, on_slot(rep); every other pattern j of the
+// slot is checked on bytes [q, q + 8) from its copy in the table and beyond that
+// against the pattern in global memory, then on_hit(j).
+// text/T: the LDS tile and table; x: LDS byte index of the start; g: its global position.
+template <class OnSlot, class OnHit>
+__device__ __forceinline__ void mq_slots(const uint4 *text, const uint8_t *T, const MqArgs &a,
+                                         const uint32_t *poff, uint32_t h, uint32_t wbits, uint32_t lo,
+                                         uint32_t hi, uint32_t x, uint64_t g, uint32_t q, OnSlot on_slot,
+                                         OnHit on_hit)
 {
-    const uint8_t *T = reinterpret_cast<const uint8_t *>(S.tab);
     const uint16_t *rank = reinterpret_cast<const uint16_t *>(T + MQ_OFF_RANK);
     const uint16_t *bstart = reinterpret_cast<const uint16_t *>(T + MQ_OFF_BSTART);
     const uint2 *spre = reinterpret_cast<const uint2 *>(T + MQ_OFF_SPRE);
@@ -291,12 +295,12 @@ __device__ __forceinline__ void mq_candidate(MqShared &S, const MqArgs &a, const
         const uint2 p = spre[sl];
         if ((p.x ^ lo) | (p.y ^ hi)) continue;
         const uint32_t rep = srep[sl];
-        if (rep != MQ_NONE) atomicAdd(&S.acc[rep], 1u);  // the slot's patterns with m == q
+        if (rep != MQ_NONE) on_slot(rep);  // the slot's patterns with m == q
         const uint32_t e1 = sstart[sl + 1];
         if (sstart[sl] == e1) continue;
         // bytes [q, q + 8) of the text at this start, from the tile
         const uint32_t y = x + q, wi = y >> 2, sb = y & 3;
-        const uint32_t w0 = tile_word(S.text, wi), w1 = tile_word(S.text, wi + 1), w2 = tile_word(S.text, wi + 2);
+        const uint32_t w0 = tile_word(text, wi), w1 = tile_word(text, wi + 1), w2 = tile_word(text, wi + 2);
         const uint32_t t0 = alignbyte(w1, w0, sb), t1 = alignbyte(w2, w1, sb);
         for (uint32_t e = sstart[sl]; e < e1; e++) {
             const uint32_t j = pid[e];
@@ -313,9 +317,42 @@ __device__ __forceinline__ void mq_candidate(MqShared &S, const MqArgs &a, const
                 for (uint32_t off = q + 8; off < m && ok; off += 16)
                     ok = diff16(load16(a.text + g + off, tl), load16(pat + off, pl), m - off < 16 ? m - off : 16) == 0;
             }
-            if (ok) atomicAdd(&S.acc[j], 1u);
+            if (ok) on_hit(j);
         }
     }
+}
+
+// The 16 starts of LDS chunk u: their q-gram hashes and bitmap words, and the
+// mask of starts whose hash bit is set.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t mq_filter16(const uint4 cu, const uint4 nx, const uint32_t *bits,
+                                                uint32_t mlo, uint32_t mhi, uint32_t *hh, uint32_t *wb)
+{
+    const uint32_t W[8] = {cu.x, cu.y, cu.z, cu.w, nx.x, nx.y, nx.z, nx.w};
+#pragma unroll
+    for (int b = 0; b < 16; b++) {
+        const int i = b >> 2, sh = b & 3;
+        const uint32_t klo = (sh ? alignbyte(W[i + 1], W[i], sh) : W[i]) & mlo;
+        const uint32_t khi = EXACT ? 0u : ((sh ? alignbyte(W[i + 2], W[i + 1], sh) : W[i + 1]) & mhi);
+        hh[b] = EXACT ? klo : mq_hash(klo, khi);
+        wb[b] = bits[hh[b] >> 5];
+    }
+    uint32_t cm = 0;
+#pragma unroll
+    for (int b = 0; b < 16; b++) cm |= __builtin_amdgcn_ubfe(wb[b], hh[b] & 31, 1) << b;
+    return cm;
+}
+
+// The key of the start at LDS byte index x, read again from the tile.
+template <bool EXACT>
+__device__ __forceinline__ void mq_key_at(const uint4 *text, uint32_t x, uint32_t mlo, uint32_t mhi,
+                                          uint32_t &klo, uint32_t &khi, uint32_t &h)
+{
+    const uint32_t wi = x >> 2, sb = x & 3;
+    const uint32_t w0 = tile_word(text, wi), w1 = tile_word(text, wi + 1);
+    klo = alignbyte(w1, w0, sb) & mlo;
+    khi = EXACT ? 0u : (alignbyte(tile_word(text, wi + 2), w1, sb) & mhi);
+    h = EXACT ? klo : mq_hash(klo, khi);
 }
 
 // EXACT: q <= 2, the key itself indexes the bitmap.
@@ -369,19 +406,8 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
         for (int u = u0; u <= u1; u++) {
             const uint4 cu = nx;
             nx = S.text[swz((uint32_t)(u + 1))];
-            const uint32_t W[8] = {cu.x, cu.y, cu.z, cu.w, nx.x, nx.y, nx.z, nx.w};
             uint32_t hh[16], wb[16];
-#pragma unroll
-            for (int b = 0; b < 16; b++) {
-                const int i = b >> 2, sh = b & 3;
-                const uint32_t klo = (sh ? alignbyte(W[i + 1], W[i], sh) : W[i]) & mlo;
-                const uint32_t khi = EXACT ? 0u : ((sh ? alignbyte(W[i + 2], W[i + 1], sh) : W[i + 1]) & mhi);
-                hh[b] = EXACT ? klo : mq_hash(klo, khi);
-                wb[b] = bits[hh[b] >> 5];
-            }
-            uint32_t cm = 0;
-#pragma unroll
-            for (int b = 0; b < 16; b++) cm |= __builtin_amdgcn_ubfe(wb[b], hh[b] & 31, 1) << b;
+            uint32_t cm = mq_filter16<EXACT>(cu, nx, bits, mlo, mhi, hh, wb);
             const int r0 = 16 * u - boff;  // relative start of byte 0 of this chunk
             if (g.flat && __ballot(__builtin_popcount(cm) >= 4)) {
                 // dense candidates in a flat group: bucket = slot, all 16 starts'
@@ -391,6 +417,7 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                 const uint16_t *rank = reinterpret_cast<const uint16_t *>(T + MQ_OFF_RANK);
                 const uint2 *spre = reinterpret_cast<const uint2 *>(T + MQ_OFF_SPRE);
                 const uint16_t *srep = reinterpret_cast<const uint16_t *>(T + MQ_OFF_SREP);
+                const uint32_t W[8] = {cu.x, cu.y, cu.z, cu.w, nx.x, nx.y, nx.z, nx.w};
                 uint32_t kk[16];
 #pragma unroll
                 for (int b = 0; b < 16; b++) {
@@ -417,12 +444,12 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                 cm &= cm - 1;
                 const int r = r0 + b;
                 if (r < lo || r > hi) continue;
-                const uint32_t x = (uint32_t)(16 * u + b), wi = x >> 2, sb = x & 3;
-                const uint32_t w0 = tile_word(S.text, wi), w1 = tile_word(S.text, wi + 1);
-                const uint32_t klo = alignbyte(w1, w0, sb) & mlo;
-                const uint32_t khi = EXACT ? 0u : (alignbyte(tile_word(S.text, wi + 2), w1, sb) & mhi);
-                const uint32_t h = EXACT ? klo : mq_hash(klo, khi);
-                mq_candidate(S, a, poff, h, bits[h >> 5], klo, khi, x, s + (uint64_t)r, q);
+                const uint32_t x = (uint32_t)(16 * u + b);
+                uint32_t klo, khi, h;
+                mq_key_at<EXACT>(S.text, x, mlo, mhi, klo, khi, h);
+                mq_slots(S.text, reinterpret_cast<const uint8_t *>(S.tab), a, poff, h, bits[h >> 5], klo, khi,
+                         x, s + (uint64_t)r, q, [&](uint32_t rep) { atomicAdd(&S.acc[rep], 1u); },
+                         [&](uint32_t j) { atomicAdd(&S.acc[j], 1u); });
             }
         }
     }
@@ -431,6 +458,185 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
     const uint16_t *cid = reinterpret_cast<const uint16_t *>(tab + MQ_OFF_CID);
     for (uint32_t j = tid; j < g.count; j += BLOCK)
         a.cnt[(uint64_t)spi[j] * a.nchunks + chunk] = S.acc[cid[j]];
+}
+
+// ---------------------------------------------------------------------------
+// Prefix filter write pass: one work item = (text chunk, filter group). Each
+// round of 4096 tile starts (one 16-byte LDS chunk per lane) gathers its hits
+// (local pattern j, tile position r) in an LDS list, sorts them by (j, r), and
+// writes hit k of pattern j in the round at CSR entry base_j + run_j + k, where
+// base_j is the pattern's offset at the chunk start and run_j counts its hits in
+// the chunk so far. A round whose list would overflow is run again on halves of
+// the pattern range (one pattern has at most one hit per start, so it fits).
+// ---------------------------------------------------------------------------
+constexpr int MQW_LIST = 4096;
+
+struct MqwArgs {
+    MqArgs f;
+    const BatchPat *pats;      // sorted
+    const uint64_t *chunk_off; // [sorted pattern][chunk]
+    const uint64_t *csr;       // [original index]
+    int64_t *out;              // CSR entry k goes to out[k - lo]
+    uint64_t lo, span;
+};
+
+struct MqwShared {
+    uint4 text[B_CHUNKS];
+    uint4 tab[MQ_LDS_BYTES / 16];
+    uint32_t list[MQW_LIST];
+    uint32_t run[MQ_G];
+    uint8_t act[MQ_G];
+    uint32_t nlist;
+    int flag;
+};
+
+template <bool EXACT>
+__global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
+{
+    __shared__ MqwShared S;
+    const MqArgs &a = w.f;
+    const uint64_t item = blockIdx.x;
+    const uint64_t chunk = item / a.ngroups;
+    const MqGroup g = a.groups[item % a.ngroups];
+    const int tid = threadIdx.x;
+    const uint8_t *tab = a.tabs + g.tab_off;
+    const uint32_t *spi = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_SPI);
+    const uint32_t *poff = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_POFF);
+    const uint64_t wend = w.lo + w.span;
+    // patterns with hits in this chunk that fall in the window
+    if (tid == 0) S.flag = 0;
+    __syncthreads();
+    for (uint32_t j = tid; j < g.count; j += BLOCK) {
+        const uint64_t sp = spi[j];
+        const uint32_t c = a.cnt[sp * a.nchunks + chunk];
+        const uint64_t r0 = c ? w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk] : 0;
+        const bool on = c && r0 < wend && r0 + c > w.lo;
+        S.act[j] = on ? 1 : 0;
+        S.run[j] = 0;
+        if (on) S.flag = 1;
+    }
+    __syncthreads();
+    if (!S.flag) return;  // uniform
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(tab);
+        for (uint32_t k = tid; k < MQ_LDS_BYTES / 16; k += BLOCK) S.tab[k] = src[k];
+        if (tid == 0) S.nlist = 0;
+    }
+    const uint32_t *bits = reinterpret_cast<const uint32_t *>(S.tab);
+    const uint8_t *T = reinterpret_cast<const uint8_t *>(S.tab);
+    const uint32_t q = g.q;
+    const uint32_t mlo = byte_mask(q < 4 ? (int)q : 4), mhi = byte_mask(q > 4 ? (int)q - 4 : 0);
+    const uint64_t t0 = chunk * a.chunk_tiles;
+    uint64_t t1 = t0 + a.chunk_tiles;
+    if (t1 > a.ntiles) t1 = a.ntiles;
+    const uint64_t tl = a.n >= g.min_m ? (a.n - g.min_m) / BT + 1 : 0;
+    if (t1 > tl) t1 = tl;
+    for (uint64_t t = t0; t < t1; t++) {
+        const uint64_t s = t * (uint64_t)BT;
+        __syncthreads();
+        uint64_t x1 = s + (uint64_t)BT + g.max_m - 1;
+        if (x1 > a.n) x1 = a.n;
+        Staged<B_PER> st;
+        stage_issue(st, a.text, s, x1);
+        stage_commit<true>(st, S.text);
+        const int boff = st.boff;
+        __syncthreads();
+        const uint64_t lim = a.n - g.min_m - s;
+        const int hi_rel = lim >= (uint64_t)(BT - 1) ? BT - 1 : (int)lim;
+        // round rd: LDS chunks [256 rd, 256 rd + 256), one per lane, i.e. the
+        // contiguous starts [4096 rd - boff, 4096 rd + 4096 - boff)
+        const int nrounds = ((boff + hi_rel) >> 4) / BLOCK + 1;
+        for (int rd = 0; rd < nrounds; rd++) {
+            const int u = BLOCK * rd + tid;
+            const int lo = 0, hi = hi_rel;
+            const bool mine = 16 * u - boff <= hi_rel;
+            uint32_t jlo = 0, jhi = g.count;  // pattern range of this attempt (uniform)
+            for (;;) {
+                // 1. this round's hits of patterns [jlo, jhi) into the list
+                if (mine) {
+                    const uint4 cu = S.text[swz((uint32_t)u)], nx = S.text[swz((uint32_t)(u + 1))];
+                    uint32_t hh[16], wb[16];
+                    uint32_t cm = mq_filter16<EXACT>(cu, nx, bits, mlo, mhi, hh, wb);
+                    const int r0 = 16 * u - boff;
+                    while (cm) {
+                        const int b = __builtin_ctz(cm);
+                        cm &= cm - 1;
+                        const int r = r0 + b;
+                        if (r < lo || r > hi) continue;
+                        const uint32_t x = (uint32_t)(16 * u + b);
+                        uint32_t klo, khi, h;
+                        mq_key_at<EXACT>(S.text, x, mlo, mhi, klo, khi, h);
+                        mq_slots(S.text, T, a, poff, h, bits[h >> 5], klo, khi, x, s + (uint64_t)r, q,
+                                 [&](uint32_t) {},
+                                 [&](uint32_t j) {
+                                     if (j >= jlo && j < jhi && S.act[j]) {
+                                         const uint32_t i = atomicAdd(&S.nlist, 1u);
+                                         if (i < (uint32_t)MQW_LIST) S.list[i] = (j << 14) | (uint32_t)r;
+                                     }
+                                 });
+                    }
+                }
+                __syncthreads();
+                const uint32_t nl = S.nlist;
+                if (nl > (uint32_t)MQW_LIST) {  // overflow: again with the lower half of the range
+                    __syncthreads();
+                    if (tid == 0) S.nlist = 0;
+                    jhi = jlo + (jhi - jlo) / 2;
+                    __syncthreads();
+                    continue;
+                }
+                if (nl) {
+                    // 2. bitonic sort of the list by (j, r), padded to a power of two
+                    uint32_t n2 = 2;
+                    while (n2 < nl) n2 <<= 1;
+                    for (uint32_t i = nl + tid; i < n2; i += BLOCK) S.list[i] = 0xFFFFFFFFu;
+                    __syncthreads();
+                    for (uint32_t k = 2; k <= n2; k <<= 1)
+                        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                            for (uint32_t i = tid; i < n2; i += BLOCK) {
+                                const uint32_t ixj = i ^ jj;
+                                if (ixj > i) {
+                                    const uint32_t x = S.list[i], y = S.list[ixj];
+                                    if ((x > y) == ((i & k) == 0)) {
+                                        S.list[i] = y;
+                                        S.list[ixj] = x;
+                                    }
+                                }
+                            }
+                            __syncthreads();
+                        }
+                    // 3. rank inside its pattern's run (entries before it with the same j), write
+                    auto rank_of = [&](uint32_t e, uint32_t j) {
+                        uint32_t b0 = 0, b1 = e;  // first entry of pattern j: lower bound of j << 14
+                        while (b0 < b1) {
+                            const uint32_t mid = (b0 + b1) >> 1;
+                            if (S.list[mid] < (j << 14)) b0 = mid + 1; else b1 = mid;
+                        }
+                        return e - b0;
+                    };
+                    for (uint32_t e = tid; e < nl; e += BLOCK) {
+                        const uint32_t key = S.list[e], j = key >> 14, r = key & 0x3FFFu;
+                        const uint64_t sp = spi[j];
+                        const uint64_t k = w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk] +
+                                           S.run[j] + rank_of(e, j);
+                        if (k - w.lo < w.span) w.out[k - w.lo] = (int64_t)(s + r);
+                    }
+                    __syncthreads();
+                    // 4. the last entry of each pattern advances its run counter
+                    for (uint32_t e = tid; e < nl; e += BLOCK) {
+                        const uint32_t j = S.list[e] >> 14;
+                        if (e + 1 == nl || (S.list[e + 1] >> 14) != j) S.run[j] += rank_of(e, j) + 1;
+                    }
+                    __syncthreads();
+                    if (tid == 0) S.nlist = 0;
+                }
+                __syncthreads();
+                if (jhi >= g.count) break;  // every pattern of the round is done
+                jlo = jhi;
+                jhi = g.count;
+            }
+        }
+    }
 }
 
 // One workgroup per pattern: tables into params[j].
@@ -573,7 +779,7 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
     // one launch per run of groups that share a kernel variant
     const BatchGroup *hg = L.write ? L.host_groups : L.host_cgroups;
     const uint32_t ng = L.write ? L.ngroups : L.ncgroups;
-    a.groups = L.write ? L.groups : L.cgroups;
+    a.groups = L.write ? L.groups : L.cgroups;  // write: the per-pattern write groups given
     uint32_t g = 0;
     while (g < ng) {
         uint32_t h = g + 1;
@@ -582,6 +788,39 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         a.ngroups = h - g;
         if ((e = launch_batch_class(hg[g].algo, hg[g].var, a, L.write, st)) != hipSuccess) return e;
         g = h;
+    }
+    if (L.write && L.nmqw) {
+        MqwArgs w;
+        memset(&w, 0, sizeof w);
+        w.f.text = L.text;
+        w.f.n = L.n;
+        w.f.tabs = L.mqwtabs;
+        w.f.patbytes = L.patbytes;
+        w.f.chunk_tiles = L.chunk_tiles;
+        w.f.nchunks = L.nchunks;
+        w.f.ntiles = L.ntiles;
+        w.f.cnt = L.cnt;
+        w.pats = L.pats;
+        w.chunk_off = L.chunk_off;
+        w.csr = L.csr;
+        w.out = L.out;
+        w.lo = L.lo;
+        w.span = L.span;
+        uint32_t nexact = 0;
+        while (nexact < L.nmqw && L.host_mqw[nexact].q <= 2) nexact++;
+        for (int pass = 0; pass < 2; pass++) {
+            const uint32_t g0 = pass ? nexact : 0, g1 = pass ? L.nmqw : nexact;
+            if (g1 == g0) continue;
+            w.f.groups = L.mqwgroups + g0;
+            w.f.ngroups = g1 - g0;
+            const uint64_t grid = L.nchunks * (g1 - g0);
+            if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+            if (pass == 0)
+                hipLaunchKernelGGL(mq_write_kernel<true>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
+            else
+                hipLaunchKernelGGL(mq_write_kernel<false>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     if (!L.write && L.nmq) {
         MqArgs m;

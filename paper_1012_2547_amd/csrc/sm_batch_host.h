@@ -14,7 +14,7 @@ namespace sm {
 
 struct BatchLayout {  // byte offsets inside the batch workspace
     uint64_t pats, groups, cgroups, mqgroups, mqtabs, params, patbytes, cnt, chunk_off, totals, csr,
-        single, need;
+        wgroups, mqwgroups, mqwtabs, single, need;
 };
 
 struct BatchJob {
@@ -28,6 +28,13 @@ struct BatchJob {
     std::vector<MqGroup> mq;          // count pass: prefix filter groups
     std::vector<uint8_t> mqtab;       // their tables (MQ_TAB_BYTES each)
     uint32_t mq_max_m = 0;
+    // write plan, built from the counts (batch_write_plan); without one the write
+    // pass runs every pattern's own scanner (groups)
+    bool wplan = false;
+    std::vector<BatchGroup> wgroups;  // per-pattern write groups
+    std::vector<MqGroup> mqw;         // prefix filter write groups
+    std::vector<uint8_t> mqwtab;
+    uint32_t max_mqw = 0;             // filter write groups the layout has room for
     std::vector<uint32_t> longp;      // m > BATCH_MAX_M: searched one pattern at a time
     uint64_t patbytes = 0;
     uint32_t chunk_tiles = 1;
@@ -51,6 +58,11 @@ void batch_fill_image(const BatchJob &j, uint8_t *dst);
 // -> d_csr[0..P]. keep_chunk_off keeps what a later write step needs.
 int batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, uint64_t *d_totals,
                         uint64_t *d_csr, bool keep_chunk_off, hipStream_t st);
+
+// Routes every pattern with occurrences to its own scanner or to a shared prefix
+// filter write group, from the host copy of the CSR offsets, and uploads the plan
+// into the workspace (enqueued on st). Later writes use it.
+int batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStream_t st);
 
 // Write step: CSR entries [lo, hi) -> d_out[0 .. hi - lo). Needs the count
 // step's workspace (keep_chunk_off) and d_csr; h_csr (host copy of d_csr) is

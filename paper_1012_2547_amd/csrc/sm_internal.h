@@ -186,6 +186,10 @@ struct BatchLaunch {
     uint32_t ncgroups;
     const MqGroup *mqgroups;        // count pass, prefix filter (ordered by q)
     const MqGroup *host_mq;
+    const MqGroup *mqwgroups;       // write pass, prefix filter (ordered by q)
+    const MqGroup *host_mqw;
+    const uint8_t *mqwtabs;
+    uint32_t nmqw;
     const uint8_t *mqtabs;
     uint32_t nmq, mq_max_m;
     const Params *params;

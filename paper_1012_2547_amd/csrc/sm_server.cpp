@@ -189,6 +189,7 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     HIP_OK(hipEventRecord(s.ev_count, s.st));
     HIP_OK(hipEventSynchronize(s.ev_count));
     const uint64_t total = s.h_csr[P];
+    if (total && (r = batch_write_plan(j, s.ws, s.h_csr, s.st))) return r;
     // admission: host space for exactly `total` positions
     s.region.reset();
     s.host_out = nullptr;

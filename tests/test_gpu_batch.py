@@ -52,8 +52,15 @@ def check_csr(sm, t_np, pats, pos, off, cap=None):
     assert np.array_equal(pos, flat[:lim])
 
 
+@pytest.fixture(params=[0, 1, 2], ids=["auto", "own", "shared"])
+def policy(sm, request):
+    sm.batch_set_write_policy(request.param)
+    yield request.param
+    sm.batch_set_write_policy(0)
+
+
 @pytest.mark.parametrize("sigma", [2, 4, 64])
-def test_batch_count_and_find_all(sm, sigma):
+def test_batch_count_and_find_all(sm, sigma, policy):
     t_np = dg.uniform_text(300_001, sigma, seed=21 + sigma)
     pats = mixed_patterns(t_np, 160, seed=sigma)
     c = sm.Corpus(t_np)
@@ -65,7 +72,7 @@ def test_batch_count_and_find_all(sm, sigma):
     c.close()
 
 
-def test_batch_order_invariance_and_truncation(sm):
+def test_batch_order_invariance_and_truncation(sm, policy):
     t_np = dg.zipf_text(200_000, 64, 1.0, seed=5)
     pats = mixed_patterns(t_np, 120, seed=9)
     c = sm.Corpus(t_np)
@@ -84,7 +91,7 @@ def test_batch_order_invariance_and_truncation(sm):
     c.close()
 
 
-def test_batch_dense_and_periodic(sm):
+def test_batch_dense_and_periodic(sm, policy):
     n = 200_003
     t_np = np.full(n, ord("a"), dtype=np.uint8)
     t_np[4095::4096] = ord("b")
@@ -169,4 +176,24 @@ def test_batch_filter_threshold_and_dense_classes(sm, k):
     assert np.array_equal(counts, want)
     pos, off = c.batch_find_all(pats)
     check_csr(sm, t_np, pats, pos, off)
+    c.close()
+
+
+def test_batch_filter_write_overflowing_rounds(sm, policy):
+    """1500 four-byte patterns on a 4-letter text: about 16 hits per pattern per
+    4096 starts, so a round of the shared write pass holds far more hits than its
+    LDS list and is split over pattern ranges."""
+    t_np = dg.uniform_text(120_001, 4, seed=61)
+    pats = [dg.random_pattern(4, 4, seed=62, idx=i) for i in range(1500)]
+    pats += [dg.substring_pattern(t_np, 9 + i % 7, seed=63, idx=i)[0] for i in range(40)]
+    c = sm.Corpus(t_np)
+    pos, off = c.batch_find_all(pats)
+    check_csr(sm, t_np, pats, pos, off)
+    b = c.batch_open(pats)
+    d = torch.empty(b.total, dtype=torch.int64, device=DEV)
+    half = b.total // 2 + 3
+    b.write_async(0, half, d[:half])
+    b.write_async(half, b.total, d[half:])
+    assert np.array_equal(d.cpu().numpy(), pos)
+    b.close()
     c.close()

@@ -101,6 +101,7 @@ def test_batch_find_all_in_small_waves(sm):
 @pytest.mark.parametrize("slots,max_batch,pool,host", [(2, 64, 0, 0), (1, 7, 1 << 16, 1 << 16),
                                                        (3, 256, 8 * 5000 * 3, 1 << 20)])
 def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host):
+    sm.batch_set_write_policy(2 if slots == 3 else 0)
     texts = corpora_small()
     srv = sm.Server(pool_bytes=pool, host_bytes=host, max_batch=max_batch, slots=slots)
     cs = [sm.Corpus(t) for t in texts]
@@ -122,6 +123,7 @@ def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host):
     if pool:
         assert st["write_waves"] > st["batches"]  # outputs larger than a slot's pool share
     srv.close()
+    sm.batch_set_write_policy(0)
     for c in cs:
         c.close()
 
