@@ -462,14 +462,17 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
 
 // ---------------------------------------------------------------------------
 // Prefix filter write pass: one work item = (text chunk, filter group). Each
-// round of 4096 tile starts (one 16-byte LDS chunk per lane) gathers its hits
-// (local pattern j, tile position r) in an LDS list, sorts them by (j, r), and
-// writes hit k of pattern j in the round at CSR entry base_j + run_j + k, where
-// base_j is the pattern's offset at the chunk start and run_j counts its hits in
-// the chunk so far. A round whose list would overflow is run again on halves of
-// the pattern range (one pattern has at most one hit per start, so it fits).
+// tile gathers its hits (local pattern j, tile position r) in an LDS list, sorts
+// them by (j, r), and writes hit k of pattern j in the tile at CSR entry
+// base_j + run_j + k, where base_j is the pattern's offset at the chunk start and
+// run_j counts its hits in the chunk so far. A tile whose list would overflow is
+// run again on halves of the pattern range, down to single patterns; a pattern
+// with more hits in one tile than the list holds is never routed here (the
+// router sends only patterns with at most 16 hits per 4096 starts on average, and
+// the tile is re-run per pattern range until each fits).
 // ---------------------------------------------------------------------------
 constexpr int MQW_LIST = 4096;
+static_assert(BT / 4 <= MQW_LIST, "a quarter tile of one pattern must fit the write list");
 
 struct MqwArgs {
     MqArgs f;
@@ -543,18 +546,19 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
         __syncthreads();
         const uint64_t lim = a.n - g.min_m - s;
         const int hi_rel = lim >= (uint64_t)(BT - 1) ? BT - 1 : (int)lim;
-        // round rd: LDS chunks [256 rd, 256 rd + 256), one per lane, i.e. the
-        // contiguous starts [4096 rd - boff, 4096 rd + 4096 - boff)
-        const int nrounds = ((boff + hi_rel) >> 4) / BLOCK + 1;
-        for (int rd = 0; rd < nrounds; rd++) {
-            const int u = BLOCK * rd + tid;
-            const int lo = 0, hi = hi_rel;
-            const bool mine = 16 * u - boff <= hi_rel;
-            uint32_t jlo = 0, jhi = g.count;  // pattern range of this attempt (uniform)
-            for (;;) {
-                // 1. this round's hits of patterns [jlo, jhi) into the list
-                if (mine) {
-                    const uint4 cu = S.text[swz((uint32_t)u)], nx = S.text[swz((uint32_t)(u + 1))];
+        const int lo = tid * BL;
+        const int hi = (lo + BL - 1) < hi_rel ? (lo + BL - 1) : hi_rel;
+        // One attempt: the hits of patterns [jlo, jhi) at tile starts [rlo, rhi) are
+        // listed, sorted, written, and counted into the run counters. Returns false
+        // (and changes nothing) when the list overflows. Uniform over the block.
+        auto attempt = [&](uint32_t jlo, uint32_t jhi, int rlo, int rhi) -> bool {
+            const int a0 = lo > rlo ? lo : rlo, a1 = hi < rhi - 1 ? hi : rhi - 1;
+            if (a0 <= a1) {
+                const int u0 = (boff + a0) >> 4, u1 = (boff + a1) >> 4;
+                uint4 nx = S.text[swz((uint32_t)u0)];
+                for (int u = u0; u <= u1; u++) {
+                    const uint4 cu = nx;
+                    nx = S.text[swz((uint32_t)(u + 1))];
                     uint32_t hh[16], wb[16];
                     uint32_t cm = mq_filter16<EXACT>(cu, nx, bits, mlo, mhi, hh, wb);
                     const int r0 = 16 * u - boff;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
                         const int b = __builtin_ctz(cm);
                         cm &= cm - 1;
                         const int r = r0 + b;
-                        if (r < lo || r > hi) continue;
+                        if (r < a0 || r > a1) continue;
                         const uint32_t x = (uint32_t)(16 * u + b);
                         uint32_t klo, khi, h;
                         mq_key_at<EXACT>(S.text, x, mlo, mhi, klo, khi, h);
@@ -576,65 +580,76 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
                                  });
                     }
                 }
+            }
+            __syncthreads();
+            const uint32_t nl = S.nlist;
+            __syncthreads();
+            if (tid == 0) S.nlist = 0;
+            if (nl > (uint32_t)MQW_LIST) {
                 __syncthreads();
-                const uint32_t nl = S.nlist;
-                if (nl > (uint32_t)MQW_LIST) {  // overflow: again with the lower half of the range
-                    __syncthreads();
-                    if (tid == 0) S.nlist = 0;
-                    jhi = jlo + (jhi - jlo) / 2;
-                    __syncthreads();
-                    continue;
-                }
-                if (nl) {
-                    // 2. bitonic sort of the list by (j, r), padded to a power of two
-                    uint32_t n2 = 2;
-                    while (n2 < nl) n2 <<= 1;
-                    for (uint32_t i = nl + tid; i < n2; i += BLOCK) S.list[i] = 0xFFFFFFFFu;
-                    __syncthreads();
-                    for (uint32_t k = 2; k <= n2; k <<= 1)
-                        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-                            for (uint32_t i = tid; i < n2; i += BLOCK) {
-                                const uint32_t ixj = i ^ jj;
-                                if (ixj > i) {
-                                    const uint32_t x = S.list[i], y = S.list[ixj];
-                                    if ((x > y) == ((i & k) == 0)) {
-                                        S.list[i] = y;
-                                        S.list[ixj] = x;
-                                    }
+                return false;
+            }
+            if (nl) {
+                // bitonic sort of the list by (j, r), padded to a power of two
+                uint32_t n2 = 2;
+                while (n2 < nl) n2 <<= 1;
+                for (uint32_t i = nl + tid; i < n2; i += BLOCK) S.list[i] = 0xFFFFFFFFu;
+                __syncthreads();
+                for (uint32_t k = 2; k <= n2; k <<= 1)
+                    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                        for (uint32_t i = tid; i < n2; i += BLOCK) {
+                            const uint32_t ixj = i ^ jj;
+                            if (ixj > i) {
+                                const uint32_t x = S.list[i], y = S.list[ixj];
+                                if ((x > y) == ((i & k) == 0)) {
+                                    S.list[i] = y;
+                                    S.list[ixj] = x;
                                 }
                             }
-                            __syncthreads();
                         }
-                    // 3. rank inside its pattern's run (entries before it with the same j), write
-                    auto rank_of = [&](uint32_t e, uint32_t j) {
-                        uint32_t b0 = 0, b1 = e;  // first entry of pattern j: lower bound of j << 14
-                        while (b0 < b1) {
-                            const uint32_t mid = (b0 + b1) >> 1;
-                            if (S.list[mid] < (j << 14)) b0 = mid + 1; else b1 = mid;
-                        }
-                        return e - b0;
-                    };
-                    for (uint32_t e = tid; e < nl; e += BLOCK) {
-                        const uint32_t key = S.list[e], j = key >> 14, r = key & 0x3FFFu;
-                        const uint64_t sp = spi[j];
-                        const uint64_t k = w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk] +
-                                           S.run[j] + rank_of(e, j);
-                        if (k - w.lo < w.span) w.out[k - w.lo] = (int64_t)(s + r);
+                        __syncthreads();
                     }
-                    __syncthreads();
-                    // 4. the last entry of each pattern advances its run counter
-                    for (uint32_t e = tid; e < nl; e += BLOCK) {
-                        const uint32_t j = S.list[e] >> 14;
-                        if (e + 1 == nl || (S.list[e + 1] >> 14) != j) S.run[j] += rank_of(e, j) + 1;
+                // rank inside its pattern's run (entries before it with the same j), write
+                auto rank_of = [&](uint32_t e, uint32_t j) {
+                    uint32_t b0 = 0, b1 = e;  // first entry of pattern j: lower bound of j << 14
+                    while (b0 < b1) {
+                        const uint32_t mid = (b0 + b1) >> 1;
+                        if (S.list[mid] < (j << 14)) b0 = mid + 1; else b1 = mid;
                     }
-                    __syncthreads();
-                    if (tid == 0) S.nlist = 0;
+                    return e - b0;
+                };
+                for (uint32_t e = tid; e < nl; e += BLOCK) {
+                    const uint32_t key = S.list[e], j = key >> 14, r = key & 0x3FFFu;
+                    const uint64_t sp = spi[j];
+                    const uint64_t k = w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk] +
+                                       S.run[j] + rank_of(e, j);
+                    if (k - w.lo < w.span) w.out[k - w.lo] = (int64_t)(s + r);
                 }
                 __syncthreads();
-                if (jhi >= g.count) break;  // every pattern of the round is done
-                jlo = jhi;
-                jhi = g.count;
+                // the last entry of each pattern advances its run counter
+                for (uint32_t e = tid; e < nl; e += BLOCK) {
+                    const uint32_t j = S.list[e] >> 14;
+                    if (e + 1 == nl || (S.list[e + 1] >> 14) != j) S.run[j] += rank_of(e, j) + 1;
+                }
             }
+            __syncthreads();
+            return true;
+        };
+        // pattern ranges: the whole group, halved on overflow; a single pattern that
+        // overflows is run over the tile's quarters (at most 4096 starts, so at
+        // most 4096 hits of one pattern: each fits)
+        uint32_t jlo = 0;
+        while (jlo < g.count) {
+            uint32_t jhi = g.count;
+            while (!attempt(jlo, jhi, 0, BT)) {
+                if (jhi - jlo > 1) {
+                    jhi = jlo + (jhi - jlo) / 2;
+                    continue;
+                }
+                for (int qt = 0; qt < 4; qt++) attempt(jlo, jhi, qt * (BT / 4), (qt + 1) * (BT / 4));
+                break;
+            }
+            jlo = jhi;
         }
     }
 }

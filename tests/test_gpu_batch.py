@@ -197,3 +197,21 @@ def test_batch_filter_write_overflowing_rounds(sm, policy):
     assert np.array_equal(d.cpu().numpy(), pos)
     b.close()
     c.close()
+
+
+def test_batch_shared_write_dense_tile_of_one_pattern(sm):
+    """A pattern sparse on average but with a hit at every start of one tile (a run
+    of zero bytes): its tile overflows the shared write pass's list even alone and
+    is written over the tile's quarters."""
+    t_np = (dg.uniform_text(8 << 20, 5, seed=71) + 1).astype(np.uint8)   # bytes 1..5
+    t_np[3 * 16384 + 100: 5 * 16384] = 0                                   # zero run over two tiles
+    pats = [b"\x00\x00\x00\x00", b"\x00\x00\x00\x01", b"\x01\x02\x03\x04", b"\x02\x03\x04\x05",
+            b"\x05\x04\x03\x02", b"\x00\x00\x00\x00\x00\x00\x00\x00\x00\x00"]
+    sm.batch_set_write_policy(2)
+    try:
+        c = sm.Corpus(t_np)
+        pos, off = c.batch_find_all(pats)
+        check_csr(sm, t_np, pats, pos, off)
+        c.close()
+    finally:
+        sm.batch_set_write_policy(0)
