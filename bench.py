@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--batched-n-log2", type=int, default=32)
     ap.add_argument("--batched-patterns", type=int, default=4096)
+    ap.add_argument("--batched-find-all", action="store_true",
+                    help="also list every position of the batched workload in 16 GiB output waves")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-shift", type=int, default=0,
                     help="log2 scale of the serving corpora (0: 8, 2 and 4 GiB)")
@@ -242,6 +244,11 @@ def main():
         torch.cuda.empty_cache()
         batched = batched_section(args, dev, stream)
 
+    batched_waves = None
+    if args.batched_find_all:
+        torch.cuda.empty_cache()
+        batched_waves = batched_find_all_section(args, dev)
+
     serving = None
     if not args.no_serving:
         torch.cuda.empty_cache()
@@ -265,6 +272,8 @@ def main():
         "batched": batched,
         "serving": serving,
     }
+    if batched_waves is not None:
+        res["batched_find_all"] = batched_waves
     print(json.dumps(res), flush=True)
 
 
@@ -331,6 +340,79 @@ def batched_section(args, dev, stream):
             "plain_pattern_GBps": round(P * n / t_plain / 1e9, 1),
             "speedup_vs_plain": round(t_plain / t_batch, 2),
             "occurrences": int(cb.sum()), "counts_agree_with_plain": agree}
+
+
+def batched_find_all_section(args, dev):
+    """Every position of the batched workload (n = 2^32 uniform sigma=4, 4096 patterns,
+    m log-uniform [2, 1024], half substrings): one count step (sm_batch_open), then
+    the CSR output written in windows of 2^31 positions (16 GiB of device staging per
+    wave). Pattern-bytes/s counts the count step and every wave. Sampled patterns'
+    slices are compared with the plain single-pattern path wherever a wave holds
+    them."""
+    import numpy as np
+    import torch
+
+    import datagen as dg
+    import paper_1012_2547_amd as sm
+
+    n = 1 << args.batched_n_log2
+    P = args.batched_patterns
+    h = dg.uniform_text(n, 4, seed=TEXT_SEED)
+    text = torch.from_numpy(h).to(dev)
+    ms = dg.log_uniform_lengths(P, 2, 1024, seed=3)
+    pats = [dg.substring_pattern(h, int(m), seed=3, idx=i)[0] if i < P // 2
+            else dg.random_pattern(int(m), 4, seed=3, idx=i) for i, m in enumerate(ms)]
+    del h
+    corpus = sm.Corpus(text)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = corpus.batch_open(pats)
+    torch.cuda.synchronize()
+    t_count = time.perf_counter() - t0
+    off = b.offsets.astype(np.int64)
+    total = b.total
+    W = 1 << 31
+    buf = torch.empty(min(W, max(total, 1)), dtype=torch.int64, device=dev)
+    # sampled patterns: every 128th, plus the largest output
+    sample = sorted(set(list(range(0, P, 128)) + [int(np.argmax(off[1:] - off[:-1]))]))
+    stream = torch.cuda.current_stream()
+    checked = mismatched = 0
+    t_waves = 0.0
+    nw = 0
+    for lo in range(0, total, W):
+        hi = min(total, lo + W)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b.write_async(lo, hi, buf[:hi - lo], stream)
+        torch.cuda.synchronize()
+        t_waves += time.perf_counter() - t1
+        nw += 1
+        for i in sample:
+            a0, a1 = max(off[i], lo), min(off[i + 1], hi)
+            if a0 >= a1:
+                continue
+            single = sm.find_all(text, pats[i])
+            got = buf[a0 - lo:a1 - lo]
+            ref = single[a0 - off[i]:a1 - off[i]]
+            checked += 1
+            if not torch.equal(got, ref):
+                mismatched += 1
+            del single
+    t_total = t_count + t_waves
+    log("batched find_all: %d positions (%.1f GiB) in %d waves; count %.3fs + waves %.3fs; "
+        "%.0f pattern-GB/s; %.0f GB/s of positions; sampled slices %d, mismatches %d" % (
+            total, total * 8 / 2**30, nw, t_count, t_waves, P * n / t_total / 1e9,
+            total * 8 / t_waves / 1e9 if t_waves else 0, checked, mismatched))
+    b.close()
+    corpus.close()
+    if mismatched:
+        raise SystemExit("batched find_all disagrees with the plain path on %d slices" % mismatched)
+    return {"workload": "n=2^%d uniform sigma=4, %d patterns m log-uniform [2,1024], find_all in "
+                        "waves of 2^31 positions" % (args.batched_n_log2, P),
+            "positions": total, "waves": nw, "count_s": round(t_count, 3), "waves_s": round(t_waves, 3),
+            "pattern_GBps": round(P * n / t_total / 1e9, 1),
+            "positions_GBps": round(total * 8 / t_waves / 1e9, 1) if t_waves else None,
+            "sampled_slices": checked, "mismatches": mismatched}
 
 
 def _digest(pos) -> tuple:

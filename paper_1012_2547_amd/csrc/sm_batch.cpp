@@ -421,7 +421,17 @@ extern "C" int sm_batch_set_write_policy(int policy)
     return SM_OK;
 }
 
-int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStream_t st)
+sm::PlanStaging::~PlanStaging()
+{
+    if (ev) {
+        (void)hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
+    }
+    if (host) (void)hipHostFree(host);
+}
+
+int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64_t lo, uint64_t hi,
+                         hipStream_t st, PlanStaging &stg)
 {
     const int policy = g_write_policy;
     j.wplan = true;
@@ -442,7 +452,9 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStr
     std::vector<uint32_t> qn(MQ_QMAX + 1, 0);
     for (size_t k = 0; k < j.bpats.size(); k++) {
         const uint32_t i = j.bpats[k].index;
-        const double c = (double)(h_csr[i + 1] - h_csr[i]);
+        // occurrences of this pattern inside the window [lo, hi)
+        const uint64_t a0 = std::max(h_csr[i], lo), a1 = std::min(h_csr[i + 1], hi);
+        const double c = a0 < a1 ? (double)(a1 - a0) : 0.0;
         if (c == 0) continue;
         const double cover = nch * (1.0 - std::exp(-c / nch)) * chunk_bytes;
         const bool sparse = c * 4096.0 / n <= 16.0;
@@ -505,15 +517,28 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStr
         }
     }
     if (j.mqw.size() > j.max_mqw) return err(SM_EDEVICE, "internal: write plan larger than its workspace");
-    // the plan into the workspace (a pageable source is consumed before the call returns)
-    if (!j.wgroups.empty())
-        HIP_OK(hipMemcpyAsync(ws + j.L.wgroups, j.wgroups.data(), j.wgroups.size() * sizeof(BatchGroup),
-                              hipMemcpyHostToDevice, st));
-    if (!j.mqw.empty()) {
-        HIP_OK(hipMemcpyAsync(ws + j.L.mqwgroups, j.mqw.data(), j.mqw.size() * sizeof(MqGroup),
-                              hipMemcpyHostToDevice, st));
-        HIP_OK(hipMemcpyAsync(ws + j.L.mqwtabs, j.mqwtab.data(), j.mqwtab.size(), hipMemcpyHostToDevice, st));
+    // the plan into the workspace region [L.wgroups, L.mqwtabs + tables), one copy
+    // from pinned staging that no earlier upload still reads
+    const uint64_t bytes = j.L.mqwtabs + j.mqwtab.size() - j.L.wgroups;
+    if (stg.pending) {
+        HIP_OK(hipEventSynchronize(stg.ev));
+        stg.pending = false;
     }
+    if (!stg.ev) HIP_OK(hipEventCreateWithFlags(&stg.ev, hipEventDisableTiming));
+    if (stg.cap < bytes) {
+        if (stg.host) HIP_OK(hipHostFree(stg.host));
+        stg.host = nullptr;
+        stg.cap = 0;
+        HIP_OK(hipHostMalloc((void **)&stg.host, bytes, hipHostMallocDefault));
+        stg.cap = bytes;
+    }
+    uint8_t *h = stg.host;
+    memcpy(h, j.wgroups.data(), j.wgroups.size() * sizeof(BatchGroup));
+    memcpy(h + (j.L.mqwgroups - j.L.wgroups), j.mqw.data(), j.mqw.size() * sizeof(MqGroup));
+    memcpy(h + (j.L.mqwtabs - j.L.wgroups), j.mqwtab.data(), j.mqwtab.size());
+    HIP_OK(hipMemcpyAsync(ws + j.L.wgroups, h, bytes, hipMemcpyHostToDevice, st));
+    HIP_OK(hipEventRecord(stg.ev, st));
+    stg.pending = true;
     return SM_OK;
 }
 
@@ -558,6 +583,7 @@ int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, con
 // ---------------------------------------------------------------------------
 struct sm_batch {
     BatchJob j;
+    PlanStaging stg;
     std::vector<uint8_t> pats;
     std::vector<uint64_t> pat_off;
     std::vector<uint64_t> csr;  // host copy, P + 1
@@ -592,8 +618,6 @@ extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *
     if ((r = batch_count_enqueue(b->j, b->ws, nullptr, d_tot, d_csr, true, nullptr))) return r;
     b->csr.resize((uint64_t)P + 1);
     HIP_OK(hipMemcpy(b->csr.data(), d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost));
-    if ((r = batch_write_plan(b->j, b->ws, b->csr.data(), nullptr))) return r;
-    HIP_OK(hipStreamSynchronize(nullptr));
     *out = b.release();
     return SM_OK;
 }
@@ -615,6 +639,9 @@ extern "C" int sm_batch_write_async(sm_batch *b, uint64_t lo, uint64_t hi, int64
     if (hi > lo && !d_out) return err(SM_EINVAL, "d_out is NULL");
     int r = check_corpus(b->j.c);
     if (r) return r;
+    if (hi == lo) return SM_OK;
+    // the write plan of this window: only the patterns whose slices meet it
+    if ((r = batch_write_plan(b->j, b->ws, b->csr.data(), lo, hi, (hipStream_t)stream, b->stg))) return r;
     return batch_write_enqueue(b->j, b->ws, (const uint64_t *)(b->ws + b->j.L.csr), b->csr.data(),
                                (uint64_t *)(b->ws + b->j.L.totals), d_out, lo, hi, (hipStream_t)stream);
 }

@@ -59,10 +59,22 @@ void batch_fill_image(const BatchJob &j, uint8_t *dst);
 int batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, uint64_t *d_totals,
                         uint64_t *d_csr, bool keep_chunk_off, hipStream_t st);
 
-// Routes every pattern with occurrences to its own scanner or to a shared prefix
-// filter write group, from the host copy of the CSR offsets, and uploads the plan
-// into the workspace (enqueued on st). Later writes use it.
-int batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, hipStream_t st);
+// Pinned staging for write-plan uploads: refilled only after the previous
+// upload from it has completed (its event).
+struct PlanStaging {
+    uint8_t *host = nullptr;
+    uint64_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    ~PlanStaging();
+};
+
+// Routes every pattern with occurrences in the CSR window [lo, hi) to its own
+// scanner or to a shared prefix filter write group, from the host copy of the
+// CSR offsets, and uploads the plan into the workspace through stg (enqueued on
+// st). The next write uses it.
+int batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64_t lo, uint64_t hi,
+                     hipStream_t st, PlanStaging &stg);
 
 // Write step: CSR entries [lo, hi) -> d_out[0 .. hi - lo). Needs the count
 // step's workspace (keep_chunk_off) and d_csr; h_csr (host copy of d_csr) is

@@ -157,6 +157,13 @@ struct PosEmit {
     }
 };
 
+// u16 offsets into an LDS list
+struct ListEmit {
+    uint16_t *dst;
+    uint32_t idx;
+    __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+};
+
 // u16 offsets inside the tile (tile-local stash)
 struct StashEmit {
     uint16_t *dst;

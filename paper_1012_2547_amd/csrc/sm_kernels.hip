@@ -237,13 +237,6 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
     }
 }
 
-// u16 offsets into an LDS list
-struct ListEmit {
-    uint16_t *dst;
-    uint32_t idx;
-    __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
-};
-
 // Emit kernel: positions of the listed tiles, at their offsets, bounded by cap.
 // Tiles with at most STASH_K hits copy their stash. Denser tiles are rescanned
 // from LDS in sub-tiles of EMIT_SUB starts (16 per lane): each sub-tile's hits

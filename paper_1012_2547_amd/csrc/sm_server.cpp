@@ -93,6 +93,7 @@ struct Slot {
     std::vector<uint8_t> pats;
     std::vector<uint64_t> pat_off;
     BatchJob job;
+    std::unique_ptr<PlanStaging> stg{new PlanStaging};
     std::shared_ptr<Region> region;
     int64_t *host_out = nullptr;
     int status = SM_OK;
@@ -189,7 +190,6 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     HIP_OK(hipEventRecord(s.ev_count, s.st));
     HIP_OK(hipEventSynchronize(s.ev_count));
     const uint64_t total = s.h_csr[P];
-    if (total && (r = batch_write_plan(j, s.ws, s.h_csr, s.st))) return r;
     // admission: host space for exactly `total` positions
     s.region.reset();
     s.host_out = nullptr;
@@ -218,6 +218,7 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     uint64_t nw = 0;
     for (uint64_t lo = 0; lo < total; lo += s.pool_pos, nw++) {
         const uint64_t hi = std::min(total, lo + s.pool_pos);
+        if ((r = batch_write_plan(j, s.ws, s.h_csr, lo, hi, s.st, *s.stg))) return r;
         if ((r = batch_write_enqueue(j, s.ws, d_csr, s.h_csr, d_tot, s.pool, lo, hi, s.st))) return r;
         HIP_OK(hipMemcpyAsync(s.host_out + lo, s.pool, (hi - lo) * 8, hipMemcpyDeviceToHost, s.st));
     }
