@@ -560,6 +560,7 @@ def serving_section(args, dev):
             "out_GBps": round(st["out_bytes"] / span_s / 1e9, 2),
             "batches": st["batches"], "mean_batch": round(float(bsz.mean()), 1),
             "write_waves": st["write_waves"], "overflow_allocs": st["overflow_allocs"],
+            "graph_launches": st["graph_launches"], "graph_builds": st["graph_builds"],
             "prefix": {"queries": K,
                        "server_p50_ms": round(_pct(lat[:K], 50) / 1e6, 3),
                        "server_p99_ms": round(_pct(lat[:K], 99) / 1e6, 3),
@@ -576,6 +577,19 @@ def serving_section(args, dev):
             raise SystemExit("server and plain path disagree at rate %g" % lam)
         out["rates"].append(row)
     srv.close()
+    # the lowest rate's trace again with direct launches instead of HIP graphs
+    lam, arr, qs = traces[0]
+    srv = sm.Server(host_bytes=8 << 30, graphs=False)
+    ids = [srv.add_corpus(c) for c in corpora]
+    srv.reset_stats()
+    lat, dig, _ = replay_server(arr, qs)
+    st = srv.stats()
+    srv.close()
+    out["graphs_ab"] = {"rate_qps": lam, "queries": len(qs),
+                        "graphs_p50_ms": out["rates"][0]["p50_ms"], "graphs_p99_ms": out["rates"][0]["p99_ms"],
+                        "direct_p50_ms": round(st["p50_ns"] / 1e6, 3), "direct_p99_ms": round(st["p99_ns"] / 1e6, 3)}
+    log("serving %g qps with direct launches: p50 %.2f ms p99 %.2f ms (graphs: %.2f / %.2f)" % (
+        lam, st["p50_ns"] / 1e6, st["p99_ns"] / 1e6, out["rates"][0]["p50_ms"], out["rates"][0]["p99_ms"]))
     for c in corpora:
         c.close()
     return out

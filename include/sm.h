@@ -208,8 +208,11 @@ int sm_batch_set_write_policy(int policy);
  * positions are written in waves of at most the slot's staging size.
  *
  * sm_server_create: zero fields take defaults (pool 16 GiB, host arena 2 GiB,
- *   max_batch 256, 2 slots, max_pending 2^20 queued queries); the server runs on
- *   the current HIP device.
+ *   max_batch 256, 2 slots, max_pending 2^20 queued queries, HIP graphs on); the
+ *   server runs on the current HIP device. With graphs on, each batch's count step
+ *   and write waves are captured as HIP graphs and replayed through per-slot
+ *   executables, updated in place while the launch sequence keeps its shape
+ *   (batches with patterns over 2048 bytes launch directly).
  * sm_server_add_corpus: registers an open corpus (borrowed: keep it open until
  *   sm_server_destroy); ids are 0, 1, ...
  * sm_server_submit: copies the pattern and queues the query; arrival_ns is its
@@ -230,7 +233,8 @@ typedef struct sm_server_config {
     uint32_t max_batch;    /* queries per batch */
     uint32_t slots;        /* pipeline slots (streams), 1..8 */
     uint32_t max_pending;  /* queued queries before submit returns SM_EBUSY */
-    uint32_t reserved[5];  /* must be zero */
+    uint32_t graphs_off;   /* nonzero: launch directly instead of through HIP graphs */
+    uint32_t reserved[4];  /* must be zero */
 } sm_server_config;
 typedef struct sm_result {
     int32_t status;
@@ -250,6 +254,8 @@ typedef struct sm_server_metrics {
     double mean_ns;
     int64_t span_ns;            /* first arrival to last completion */
     double qps;                 /* completed / span */
+    uint64_t graph_launches;    /* graph launches (count steps and write waves) */
+    uint64_t graph_builds;      /* of which needed a new executable (shape changed) */
 } sm_server_metrics;
 int64_t sm_now_ns(void);
 int sm_server_create(const sm_server_config *cfg, sm_server **server);

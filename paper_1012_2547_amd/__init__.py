@@ -338,11 +338,12 @@ class Server:
     is valid until free(ticket) (result() copies and frees in one call)."""
 
     def __init__(self, pool_bytes: int = 0, host_bytes: int = 0, max_batch: int = 0, slots: int = 0,
-                 max_pending: int = 0):
+                 max_pending: int = 0, graphs: bool = True):
         from ._native import ServerConfig
         cfg = ServerConfig()
         cfg.pool_bytes, cfg.host_bytes, cfg.max_batch = pool_bytes, host_bytes, max_batch
         cfg.slots, cfg.max_pending = slots, max_pending
+        cfg.graphs_off = 0 if graphs else 1
         self._h = ctypes.c_void_p(0)
         self._corpora = []
         check(load().sm_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))

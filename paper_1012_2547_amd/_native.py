@@ -51,7 +51,8 @@ class Prof(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64),
                 ("max_batch", ctypes.c_uint32), ("slots", ctypes.c_uint32),
-                ("max_pending", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("max_pending", ctypes.c_uint32), ("graphs_off", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class Result(ctypes.Structure):
@@ -70,7 +71,8 @@ class ServerMetrics(ctypes.Structure):
                 ("p50_ns", ctypes.c_int64), ("p99_ns", ctypes.c_int64),
                 ("p999_ns", ctypes.c_int64), ("max_ns", ctypes.c_int64),
                 ("mean_ns", ctypes.c_double), ("span_ns", ctypes.c_int64),
-                ("qps", ctypes.c_double)]
+                ("qps", ctypes.c_double), ("graph_launches", ctypes.c_uint64),
+                ("graph_builds", ctypes.c_uint64)]
 
 
 # every exported symbol and its prototype: (restype, argtypes)

@@ -15,7 +15,9 @@
 //
 // While the scheduler waits for batch j+1's counts on one slot, batch j's writes
 // and copies run on another, so the count pass of one batch overlaps the output
-// traffic of the previous one. A completion thread waits for each slot's done
+// traffic of the previous one. The count step and each write wave are captured
+// as HIP graphs and replayed through per-slot executables that are updated in
+// place while the launch sequence keeps its shape (steady state under load). A completion thread waits for each slot's done
 // event in dispatch order and publishes the results. Queries past the queue
 // limit are refused at submission (SM_EBUSY).
 #include <hip/hip_runtime.h>
@@ -98,6 +100,9 @@ struct Slot {
     int64_t *host_out = nullptr;
     int status = SM_OK;
     bool busy = false;
+    // graph executables of the count step and of a write wave, updated in place
+    // while the captured launch sequence keeps its shape
+    hipGraphExec_t count_exec = nullptr, write_exec = nullptr;
 };
 
 }  // namespace
@@ -120,7 +125,7 @@ struct sm_server {
     // statistics since the last reset
     std::vector<int64_t> lat_ns;
     uint64_t batches = 0, batched_queries = 0, text_bytes = 0, out_bytes = 0, overflow_allocs = 0;
-    uint64_t waves = 0;
+    uint64_t waves = 0, graph_launches = 0, graph_builds = 0;
     int64_t first_arrival = 0, last_done = 0;
     std::atomic<int> fatal{SM_OK};
 };
@@ -163,6 +168,54 @@ int grow_host(T **p, uint64_t *cap, uint64_t need_bytes)
     return SM_OK;
 }
 
+// Enqueues work(): captured as a graph and launched through `exec` (updated in
+// place when the captured sequence has the same shape as the one it was built
+// from, else rebuilt) when use is set, else directly. A capture that fails is
+// abandoned and the work is enqueued directly (nothing of it ran).
+template <class F>
+int enqueue_graph(sm_server *S, hipStream_t st, hipGraphExec_t &exec, bool use, F work)
+{
+    if (!use) return work();
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return work();
+    }
+    const int r = work();
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (r != SM_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return work();
+    }
+    bool updated = false;
+    if (exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(exec, graph, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            updated = true;
+        } else {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+        }
+    }
+    if (!exec) {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            exec = nullptr;
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "graph instantiation");
+        }
+    }
+    (void)hipGraphDestroy(graph);
+    HIP_OK(hipGraphLaunch(exec, st));
+    std::lock_guard<std::mutex> g(S->mu);
+    S->graph_launches++;
+    if (!updated) S->graph_builds++;
+    return SM_OK;
+}
+
 // Count, admission, windowed writes and copies of one batch on slot s. Runs on
 // the scheduler thread with the server lock released; returns after the writes
 // are enqueued (the completion thread waits for them).
@@ -185,8 +238,16 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     if ((r = grow_host(&s.h_csr, &s.h_csr_cap, ((uint64_t)P + 1) * 8))) return r;
     batch_fill_image(j, s.h_image);
     uint64_t *d_tot = (uint64_t *)(s.ws + j.L.totals), *d_csr = (uint64_t *)(s.ws + j.L.csr);
-    if ((r = batch_count_enqueue(j, s.ws, s.h_image, d_tot, d_csr, true, s.st))) return r;
-    HIP_OK(hipMemcpyAsync(s.h_csr, d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost, s.st));
+    // graphs for batches of patterns within the batch kernels' reach (longer ones
+    // take the single-pattern path, whose preparation may copy from pageable memory)
+    const bool graphs = !S->cfg.graphs_off && j.longp.empty();
+    r = enqueue_graph(S, s.st, s.count_exec, graphs, [&]() -> int {
+        int rr = batch_count_enqueue(j, s.ws, s.h_image, d_tot, d_csr, true, s.st);
+        if (rr) return rr;
+        HIP_OK(hipMemcpyAsync(s.h_csr, d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost, s.st));
+        return SM_OK;
+    });
+    if (r) return r;
     HIP_OK(hipEventRecord(s.ev_count, s.st));
     HIP_OK(hipEventSynchronize(s.ev_count));
     const uint64_t total = s.h_csr[P];
@@ -219,8 +280,13 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     for (uint64_t lo = 0; lo < total; lo += s.pool_pos, nw++) {
         const uint64_t hi = std::min(total, lo + s.pool_pos);
         if ((r = batch_write_plan(j, s.ws, s.h_csr, lo, hi, s.st, *s.stg))) return r;
-        if ((r = batch_write_enqueue(j, s.ws, d_csr, s.h_csr, d_tot, s.pool, lo, hi, s.st))) return r;
-        HIP_OK(hipMemcpyAsync(s.host_out + lo, s.pool, (hi - lo) * 8, hipMemcpyDeviceToHost, s.st));
+        r = enqueue_graph(S, s.st, s.write_exec, graphs, [&]() -> int {
+            int rr = batch_write_enqueue(j, s.ws, d_csr, s.h_csr, d_tot, s.pool, lo, hi, s.st);
+            if (rr) return rr;
+            HIP_OK(hipMemcpyAsync(s.host_out + lo, s.pool, (hi - lo) * 8, hipMemcpyDeviceToHost, s.st));
+            return SM_OK;
+        });
+        if (r) return r;
     }
     HIP_OK(hipEventRecord(s.ev_done, s.st));
     std::lock_guard<std::mutex> g(S->mu);
@@ -350,6 +416,8 @@ void destroy_resources(sm_server *S)
         if (s.h_csr) (void)hipHostFree(s.h_csr);
         if (s.ev_count) (void)hipEventDestroy(s.ev_count);
         if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+        if (s.count_exec) (void)hipGraphExecDestroy(s.count_exec);
+        if (s.write_exec) (void)hipGraphExecDestroy(s.write_exec);
         if (s.st) (void)hipStreamDestroy(s.st);
     }
     for (auto &kv : S->queries)
@@ -519,6 +587,8 @@ extern "C" int sm_server_stats(sm_server *S, sm_server_metrics *st)
         st->out_bytes = S->out_bytes;
         st->write_waves = S->waves;
         st->overflow_allocs = S->overflow_allocs;
+        st->graph_launches = S->graph_launches;
+        st->graph_builds = S->graph_builds;
         st->span_ns = S->last_done > S->first_arrival ? S->last_done - S->first_arrival : 0;
     }
     st->completed = lat.size();
@@ -546,6 +616,7 @@ extern "C" int sm_server_reset_stats(sm_server *S)
     std::lock_guard<std::mutex> g(S->mu);
     S->lat_ns.clear();
     S->batches = S->batched_queries = S->text_bytes = S->out_bytes = S->overflow_allocs = S->waves = 0;
+    S->graph_launches = S->graph_builds = 0;
     S->first_arrival = S->last_done = 0;
     return SM_OK;
 }

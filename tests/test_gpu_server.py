@@ -98,12 +98,13 @@ def test_batch_find_all_in_small_waves(sm):
     c.close()
 
 
-@pytest.mark.parametrize("slots,max_batch,pool,host", [(2, 64, 0, 0), (1, 7, 1 << 16, 1 << 16),
-                                                       (3, 256, 8 * 5000 * 3, 1 << 20)])
-def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host):
+@pytest.mark.parametrize("slots,max_batch,pool,host,graphs", [(2, 64, 0, 0, True), (2, 64, 0, 0, False),
+                                                              (1, 7, 1 << 16, 1 << 16, True),
+                                                              (3, 256, 8 * 5000 * 3, 1 << 20, True)])
+def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host, graphs):
     sm.batch_set_write_policy(2 if slots == 3 else 0)
     texts = corpora_small()
-    srv = sm.Server(pool_bytes=pool, host_bytes=host, max_batch=max_batch, slots=slots)
+    srv = sm.Server(pool_bytes=pool, host_bytes=host, max_batch=max_batch, slots=slots, graphs=graphs)
     cs = [sm.Corpus(t) for t in texts]
     ids = [srv.add_corpus(c) for c in cs]
     qs = query_mix(texts, 150, seed=14)
@@ -122,6 +123,8 @@ def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host):
     assert 0 < st["p50_ns"] <= st["p99_ns"] <= st["p999_ns"] <= st["max_ns"]
     if pool:
         assert st["write_waves"] > st["batches"]  # outputs larger than a slot's pool share
+    if not graphs:
+        assert st["graph_launches"] == 0
     srv.close()
     sm.batch_set_write_policy(0)
     for c in cs:
@@ -136,14 +139,18 @@ def test_server_matches_single_path_and_reuses_memory(sm):
     cid = srv.add_corpus(c)
     pats = [dg.substring_pattern(t_np, int(m), seed=22, idx=i)[0]
             for i, m in enumerate(dg.log_uniform_lengths(96, 4, 256, seed=22))]
-    for rnd in range(3):  # results freed in and out of order; arena space is reused
+    for rnd in range(4):  # results freed in and out of order; arena space is reused
         tks = [srv.submit(cid, p) for p in pats]
         order = list(range(len(tks)))
         np.random.default_rng(rnd).shuffle(order)
         for k in order:
             got = srv.result(tks[k])
-            single = sm.find_all(t_dev, pats[k]).cpu().numpy()
+            single = sm.find_all(t_dev, pats[k]).cpu().numpy()  # eager work between replays
             assert np.array_equal(got, single), (rnd, k)
+        torch.cuda.synchronize()
+    st = srv.stats()
+    # the same batches again and again: graph executables are updated, not rebuilt
+    assert st["graph_launches"] > 0 and st["graph_builds"] < st["graph_launches"]
     srv.close()
     c.close()
 
