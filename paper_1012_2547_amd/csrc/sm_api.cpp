@@ -234,6 +234,9 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     }
     p.lane_bytes = o->lane_bytes ? o->lane_bytes : (use_entry && te.lane_bytes ? te.lane_bytes : 64);
     p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (use_entry && te.tiles_per_wg ? te.tiles_per_wg : 1);
+    // a tile of 256 * L starts expects 256 * L * sigma^-m hits on an i.i.d. text: at
+    // most the stash (256) when sigma^m >= L; denser tiles go to the emit pass anyway
+    p.slots = (double)m * std::log((double)sigma) >= std::log((double)p.lane_bytes) ? 1 : 0;
     return SM_OK;
 }
 

@@ -138,8 +138,12 @@ __device__ __forceinline__ void stage_commit(const Staged<PER> &st, uint4 *lds)
 // ---------------------------------------------------------------------------
 // Emitters: where a lane's hits go.
 // ---------------------------------------------------------------------------
+// Every emitter has put(rel) for one hit (in ascending order); saturated() tells a
+// bit-parallel scanner that further hits need only be counted, through add(k).
 struct NoEmit {
     __device__ __forceinline__ void put(int) {}
+    __device__ __forceinline__ bool saturated() const { return false; }
+    __device__ __forceinline__ void add(uint32_t) {}
 };
 
 // int64 global positions, bounded by cap
@@ -155,6 +159,8 @@ struct PosEmit {
         if (r < span) out[r] = (int64_t)(base + (uint64_t)(int64_t)rel);
         idx++;
     }
+    __device__ __forceinline__ bool saturated() const { return false; }
+    __device__ __forceinline__ void add(uint32_t) {}
 };
 
 // u16 offsets into an LDS list
@@ -162,6 +168,8 @@ struct ListEmit {
     uint16_t *dst;
     uint32_t idx;
     __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+    __device__ __forceinline__ bool saturated() const { return false; }
+    __device__ __forceinline__ void add(uint32_t) {}
 };
 
 // u16 offsets inside the tile (tile-local stash)
@@ -169,6 +177,8 @@ struct StashEmit {
     uint16_t *dst;
     uint32_t idx;
     __device__ __forceinline__ void put(int rel) { dst[idx++] = (uint16_t)rel; }
+    __device__ __forceinline__ bool saturated() const { return false; }
+    __device__ __forceinline__ void add(uint32_t) {}
 };
 
 // Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
@@ -201,7 +211,9 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *ma
                 uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
                 hits &= ((2u << jhi) - 1u) & ~((1u << jlo) - 1u);
                 if (hits) {
-                    if (WRITE) {
+                    if (WRITE && o.saturated()) {
+                        o.add((uint32_t)__builtin_popcount(hits));
+                    } else if (WRITE) {
                         // bit j <-> end e_last - j; ascending positions = descending j
                         while (hits) {
                             const int j = 31 - __builtin_clz(hits);

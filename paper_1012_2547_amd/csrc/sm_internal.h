@@ -51,6 +51,7 @@ struct Plan {
     int32_t q;            // Hash-q gram length
     int32_t hbits;        // Hash-q table bits
     int32_t tiles_per_wg; // consecutive tiles per workgroup (count kernel)
+    int32_t slots;        // find: keep lanes' first hits while counting (tiles expected sparse)
     uint64_t m;
 };
 

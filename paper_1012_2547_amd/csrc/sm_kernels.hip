@@ -54,6 +54,7 @@ struct ScanArgs {
     const Params *prm;
     const uint8_t *pat;
     uint32_t m, q, hbits, tiles_per_wg;
+    uint32_t slots;       // find: lanes keep their first hits while counting
     uint64_t ntiles;
     uint64_t *total;      // count mode: occurrences are added here
     uint32_t *tile_cnt;   // find mode: per-tile counts (count kernel writes, emit reads)
@@ -81,6 +82,31 @@ struct TileShared {
     uint64_t mask[(ALGO == ALGO_HASHQ) ? 1 : 256];
     uint8_t shift[(ALGO == ALGO_HASHQ) ? (1 << H_MAX) : 1];
     uint32_t w[BLOCK / 64];
+};
+
+// Find-mode count pass: counts every hit of the lane and keeps its first four
+// tile-relative starts (u16 pairs in two registers), so a tile with few hits
+// needs no second scan to fill its stash.
+constexpr uint32_t LANE_K = 4;
+struct CapEmit {
+    uint32_t p0 = 0, p1 = 0, n = 0;
+    __device__ __forceinline__ void put(int rel)
+    {
+        const uint32_t r = (uint32_t)rel & 0xFFFFu;
+        if (n == 0) p0 = r;
+        else if (n == 1) p0 |= r << 16;
+        else if (n == 2) p1 = r;
+        else if (n == 3) p1 |= r << 16;
+        n++;
+    }
+    // once more hits than slots are seen, the tile is scanned again anyway: count only
+    __device__ __forceinline__ bool saturated() const { return n > LANE_K; }
+    __device__ __forceinline__ void add(uint32_t k) { n += k; }
+    __device__ __forceinline__ uint16_t get(uint32_t k) const
+    {
+        const uint32_t w = k < 2 ? p0 : p1;
+        return (uint16_t)((k & 1) ? (w >> 16) : (w & 0xFFFFu));
+    }
 };
 
 // Pattern tables, read from the parameter block into registers (issue), then
@@ -223,16 +249,32 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         }
         const int lo = threadIdx.x * L;
         const int hi = (lo + L - 1) < cur.hi_rel ? (lo + L - 1) : cur.hi_rel;
-        NoEmit ne;
-        const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne);
+        // Shift-And (hits come as bit masks) counts while keeping the lane's first
+        // hits; the skip algorithms count (their hits are rare) and scan again
+        constexpr bool CAP_OK = FIND && ALGO == ALGO_SHIFT_AND;
+        const bool cap = CAP_OK && a.slots;  // uniform
+        uint32_t c;
+        CapEmit ce;
+        if (cap) {
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce);
+            c = ce.n;
+        } else {
+            NoEmit ne;
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne);
+        }
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
         if (threadIdx.x == 0) a.tile_cnt[t] = tot;
-        if (FIND && tot && tot <= STASH_K) {  // uniform: Hash-q lanes verify together
-            StashEmit se;
-            se.dst = a.stash + t * STASH_K;
-            se.idx = before;
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
+        if (FIND && tot && tot <= STASH_K) {  // uniform
+            uint16_t *dst = a.stash + t * STASH_K;
+            if (cap && !__syncthreads_or(c > LANE_K)) {
+                for (uint32_t k = 0; k < c; k++) dst[before + k] = ce.get(k);
+            } else {  // scan again into the stash
+                StashEmit se;
+                se.dst = dst;
+                se.idx = before;
+                run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
+            }
         }
     }
 }
@@ -551,6 +593,7 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
     a.q = (uint32_t)plan.q;
     a.hbits = (uint32_t)plan.hbits;
     a.tiles_per_wg = (uint32_t)plan.tiles_per_wg;
+    a.slots = (uint32_t)plan.slots;
     a.ntiles = ntiles;
     return a;
 }

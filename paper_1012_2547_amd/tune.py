@@ -9,7 +9,7 @@ fastest configuration of each cell becomes a table entry. The paper's own
 summary (Section 4) says the best algorithm depends on exactly these two
 quantities; this measures that map on MI355X.
 
-    python -m paper_1012_2547_amd.tune --out gpurun_out/tune      # on a GPU
+    python -m paper_1012_2547_amd.tune --out gpurun_out/tune --n-log2 30   # on a GPU
 writes tune.json (entries + timings) and tune_table.inc (C initialisers for
 csrc/tune_table.inc).
 """
@@ -32,20 +32,21 @@ def candidates(m: int, sigma: int):
     if m <= 64:
         for algo in (1, 2, 3):
             for L in (32, 64, 128):
-                out.append(dict(algo=algo, lane_bytes=L, q=0, tiles_per_wg=1))
-            out.append(dict(algo=algo, lane_bytes=64, q=0, tiles_per_wg=2))
+                for tpw in (1, 2, 4):
+                    out.append(dict(algo=algo, lane_bytes=L, q=0, tiles_per_wg=tpw))
     for q in QS:
         if q > m or sigma ** q < m:  # too few distinct q-grams to skip anything
             continue
         for L in (64, 128):
-            out.append(dict(algo=4, lane_bytes=L, q=q, tiles_per_wg=1))
+            for tpw in (1, 2):
+                out.append(dict(algo=4, lane_bytes=L, q=q, tiles_per_wg=tpw))
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="gpurun_out/tune")
-    ap.add_argument("--n-log2", type=int, default=28)
+    ap.add_argument("--n-log2", type=int, default=30)
     ap.add_argument("--patterns", type=int, default=3)
     ap.add_argument("--reps", type=int, default=2)
     args = ap.parse_args()
