@@ -69,7 +69,7 @@ enum sm_algo {
 typedef struct sm_opts {
     int32_t algo;         /* enum sm_algo */
     int32_t lane_bytes;   /* candidate starts per lane; a tile is 256 * lane_bytes starts */
-    int32_t q;            /* Hash-q gram length, 1..16 */
+    int32_t q;            /* Hash-q gram length, 1..16; for SBNDM the q-gram read at once, 1, 2, 4 or 8 */
     int32_t sigma_hint;   /* expected alphabet size of the text (planner input only) */
     int32_t tiles_per_wg; /* consecutive tiles per workgroup, >= 1 */
     int32_t hbits;        /* Hash-q table has 2^hbits buckets */

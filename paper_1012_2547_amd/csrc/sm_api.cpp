@@ -227,6 +227,11 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     p.algo = algo;
     p.q = 0;
     p.hbits = 0;
+    if (algo == ALGO_SBNDM) {  // q-gram width of the window's first read
+        const int q = o->q ? o->q : (use_entry ? te.q : 0);
+        if (q > 1 && q != 2 && q != 4 && q != 8) return fail(SM_EINVAL, "SBNDM takes q in {1, 2, 4, 8} (got %d)", q);
+        p.q = (q > 1 && (uint64_t)q <= m) ? q : 0;
+    }
     if (algo == ALGO_HASHQ) {
         p.q = o->q ? o->q : (use_entry && te.q ? te.q : choose_q(m, sigma));
         if ((uint64_t)p.q > m) p.q = (int)m;

@@ -133,7 +133,7 @@ __device__ __forceinline__ uint32_t batch_lane(BatchShared<ALGO, VAR> &S, const 
                                 reinterpret_cast<const uint64_t *>(tab), m, boff, lo, hi, o);
     } else if (ALGO == ALGO_SBNDM) {
         if (lo > hi) return 0u;
-        return lane_sbndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text),
+        return lane_sbndm<1, WRITE>(reinterpret_cast<const uint8_t *>(S.text),
                                  reinterpret_cast<const uint64_t *>(tab), m, (int)in.period, boff, lo,
                                  hi, o);
     } else {

@@ -262,8 +262,11 @@ __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_
 }
 
 // SBNDM: same masks; no prefix tracking; shift m-k+1 when the k-byte suffix is
-// not a factor of p; after a hit, shift by the smallest period of p.
-template <bool WRITE, class E>
+// not a factor of p; after a hit, shift by the smallest period of p. Q > 1 is the
+// q-gram form (SBNDMq, Fig. 3): the window's last Q bytes are read at once (Q
+// independent mask lookups combined by shifts) and a window whose Q-byte suffix
+// is not a factor of p is left with a shift of m-Q+1. Needs Q <= m.
+template <int Q, bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_sbndm(const uint8_t *lds8, const uint64_t *B, int m,
                                               int period, int li0, int lo, int hi, E &o)
 {
@@ -272,8 +275,22 @@ __device__ __forceinline__ uint32_t lane_sbndm(const uint8_t *lds8, const uint64
     int pos = lo;
     while (pos <= hi) {
         const uint8_t *w = lds8 + li0 + pos;  // window bytes w[0 .. m-1]
-        uint64_t D = B[w[m - 1]];
-        int k = 1;
+        uint64_t D;
+        int k;
+        if (Q > 1) {
+            // D after Q steps of D = (D << 1) & B[byte]: byte w[m-1-i] enters shifted by Q-1-i
+            D = B[w[m - Q]];
+#pragma unroll
+            for (int i = 0; i < Q - 1; i++) D &= B[w[m - 1 - i]] << (Q - 1 - i);
+            if (D == 0) {
+                pos += m - Q + 1;
+                continue;
+            }
+            k = Q;
+        } else {
+            D = B[w[m - 1]];
+            k = 1;
+        }
         while (D != 0 && k < m) {
             D = (D << 1) & B[w[m - 1 - k]];
             k++;

@@ -195,9 +195,10 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
         return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
     } else if (ALGO == ALGO_BNDM) {
         return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
-    } else if (ALGO == ALGO_SBNDM) {
-        return lane_sbndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
-                                 lo, hi, o);
+    } else if (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
+        constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : (VAR == 2 ? 4 : 8));
+        return lane_sbndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
+                                    lo, hi, o);
     } else {
         return lane_hashq<VAR, WRITE>(reinterpret_cast<const uint32_t *>(S.text), S.shift, m,
                                       (int)a.q, (int)a.hbits, sh1, period, period_lb, li0, lo, hi,
@@ -568,7 +569,11 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
         return launch_l<ALGO_SHIFT_AND, 3, KIND>(p, a, grid, st);
     }
     case ALGO_BNDM: return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
-    case ALGO_SBNDM: return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);
+    case ALGO_SBNDM:
+        if (p.q <= 1) return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);
+        if (p.q == 2) return launch_l<ALGO_SBNDM, 1, KIND>(p, a, grid, st);
+        if (p.q == 4) return launch_l<ALGO_SBNDM, 2, KIND>(p, a, grid, st);
+        return launch_l<ALGO_SBNDM, 3, KIND>(p, a, grid, st);
     case ALGO_HASHQ: {
         const int nw = (p.q + 3) / 4;
         if (nw <= 1) return launch_l<ALGO_HASHQ, 1, KIND>(p, a, grid, st);

@@ -34,6 +34,12 @@ def candidates(m: int, sigma: int):
             for L in (32, 64, 128):
                 for tpw in (1, 2, 4):
                     out.append(dict(algo=algo, lane_bytes=L, q=0, tiles_per_wg=tpw))
+        for q in (2, 4, 8):  # SBNDMq: the window's last q bytes read at once
+            if q > m:
+                continue
+            for L in (32, 64, 128):
+                for tpw in (1, 2, 4):
+                    out.append(dict(algo=3, lane_bytes=L, q=q, tiles_per_wg=tpw))
     for q in QS:
         if q > m or sigma ** q < m:  # too few distinct q-grams to skip anything
             continue

@@ -96,6 +96,27 @@ def test_hashq_every_q(sm):
                     assert np.array_equal(got, want) and tot == want.size, (sigma, m, q, L)
 
 
+def test_sbndm_every_q(sm):
+    """The q-gram form of SBNDM (q = 2, 4, 8) on small and large alphabets, with
+    periodic patterns and q = m."""
+    n = 40_000
+    for sigma in (2, 4, 64):
+        t_np = dg.uniform_text(n, sigma, seed=13)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        pats = [dg.substring_pattern(t_np, m, seed=19, idx=m)[0] for m in (2, 4, 5, 8, 9, 31, 64)]
+        pats += [b"\x01\x00" * 16, bytes(t_np[:8])]
+        for p in pats:
+            want = oracle.find_all(t_np, p)
+            for q in (2, 4, 8):
+                if q > len(p):
+                    continue
+                for L, tpw in ((16, 1), (64, 2)):
+                    got, tot = gpu_find(sm, t_dev, p, algo=3, lane=L, q=q, tpw=tpw)
+                    assert np.array_equal(got, want) and tot == want.size, (sigma, len(p), q, L)
+    with pytest.raises(sm.SmError):
+        gpu_find(sm, t_dev, b"abcdefgh", algo=3, lane=64, q=3)
+
+
 def test_tiles_per_workgroup_and_lanes_deterministic(sm):
     t_np = dg.uniform_text(300_001, 4, seed=8)
     t_dev = torch.from_numpy(t_np).to(DEV)
