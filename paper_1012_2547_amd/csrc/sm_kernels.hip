@@ -282,70 +282,105 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
 
 // Emit kernel: positions of the listed tiles, at their offsets, bounded by cap.
 // Tiles with at most STASH_K hits copy their stash. Denser tiles are rescanned
-// from LDS in sub-tiles of EMIT_SUB starts (16 per lane): each sub-tile's hits
-// are gathered in an LDS list in order, then written out coalesced.
+// from LDS in sub-tiles of EMIT_SUB starts (16 per lane): one scan keeps each
+// lane's hits in its own LDS slots, and a workgroup scan of the lanes' counts
+// gives each lane its output offset. Lanes write their hits there themselves in
+// sparse sub-tiles; dense ones are compacted in LDS and written coalesced.
 template <int ALGO, int L, int VAR>
 __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
 {
     constexpr int SUB_LANE = EMIT_SUB / BLOCK;
     __shared__ TileShared<ALGO, L> S;
+    // SUB_LANE per lane: all of a lane's hits in a sub-tile
     __shared__ uint16_t s_list[EMIT_SUB];
     const int m = (int)a.m;
     const uint64_t nl = *a.nlist;
     if ((uint64_t)blockIdx.x >= nl) return;
-    bool tables = false;
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
     const int period_lb = (int)a.prm->period_lb;
+    // 1. tiles with at most STASH_K hits: copy their stash
     for (uint64_t e = blockIdx.x; e < nl; e += gridDim.x) {
         const uint64_t t = a.list[e];
         const uint32_t tot = a.tile_cnt[t];
         const uint64_t off = a.tile_off[t];
-        if (off >= a.lo + a.cap || off + tot <= a.lo) continue;  // uniform over the workgroup
+        if (tot > STASH_K || off >= a.lo + a.cap || off + tot <= a.lo) continue;  // uniform
         const uint64_t s = t * (uint64_t)Geometry<ALGO, L>::T;
-        if (tot <= STASH_K) {
-            const uint16_t *src = a.stash + t * STASH_K;
-            for (uint32_t k = threadIdx.x; k < tot; k += BLOCK) {
-                const uint64_t r = off + k - a.lo;
-                if (r < a.cap) a.out[r] = (int64_t)(s + src[k]);
-            }
-            continue;
+        const uint16_t *src = a.stash + t * STASH_K;
+        for (uint32_t k = threadIdx.x; k < tot; k += BLOCK) {
+            const uint64_t r = off + k - a.lo;
+            if (r < a.cap) a.out[r] = (int64_t)(s + src[k]);
         }
-        if (!tables) {
-            const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
-            tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
-            tables = true;
+    }
+    // 2. denser tiles: rescan from LDS
+    auto next_dense = [&](uint64_t e) -> uint64_t {  // uniform over the workgroup
+        for (; e < nl; e += gridDim.x) {
+            const uint64_t t = a.list[e];
+            const uint32_t tot = a.tile_cnt[t];
+            const uint64_t off = a.tile_off[t];
+            if (tot > STASH_K && off < a.lo + a.cap && off + tot > a.lo) return e;
         }
-        uint64_t s2;
-        int li0, lo_t, hi_t;
+        return nl;
+    };
+    uint64_t e = next_dense(blockIdx.x);
+    if (e >= nl) return;
+    {
+        const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
+        tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
+    }
+    using G = Geometry<ALGO, L>;
+    for (; e < nl; e = next_dense(e + gridDim.x)) {
+        const uint64_t t = a.list[e];
+        const uint64_t off = a.tile_off[t];
+        const TileGeom cur = tile_geom<ALGO, L>(a, t);
+        Staged<G::PER> st;
+        stage_issue(st, a.text, cur.x0, cur.x1);
+        __syncthreads();  // the previous tile's LDS readers are done
+        stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+        const int li0 = st.boff - cur.r0;
         __syncthreads();
-        stage_tile<ALGO, L>(S, a, t, s2, li0, lo_t, hi_t);
-        __syncthreads();
-        const int hi_rel = (int)((a.n - a.m - s2) < (uint64_t)(Geometry<ALGO, L>::T - 1)
-                                     ? (a.n - a.m - s2) : (uint64_t)(Geometry<ALGO, L>::T - 1));
+        const uint64_t s2 = cur.s;
+        const int hi_rel = cur.hi_rel;
         uint64_t run = off;
         for (int sb = 0; sb <= hi_rel && run < a.lo + a.cap; sb += EMIT_SUB) {  // uniform
             const int lo = sb + SUB_LANE * (int)threadIdx.x;
             const int hi = (lo + SUB_LANE - 1) < hi_rel ? (lo + SUB_LANE - 1) : hi_rel;
-            NoEmit ne;
-            const uint32_t c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, ne);
+            // one scan: each lane keeps its hits (at most one per start) in its slots
+            ListEmit se;
+            se.dst = s_list + SUB_LANE * threadIdx.x;
+            se.idx = 0;
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, se);
+            const uint32_t c = se.idx;
             uint32_t ctot;
-            const uint32_t before = block_excl_scan(c, S.w, ctot);
+            const uint32_t before = block_excl_scan(c, S.w, ctot);  // ends with a barrier
             if (ctot == 0) continue;  // uniform
             if (run + ctot <= a.lo) {  // sub-tile entirely before the window (uniform)
                 run += ctot;
                 continue;
             }
-            ListEmit le;
-            le.dst = s_list;
-            le.idx = before;
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, le);
-            __syncthreads();
-            for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK) {
-                const uint64_t r = run + k - a.lo;
-                if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[k]);
+            if (ctot <= (uint32_t)(EMIT_SUB / 8)) {  // uniform
+                // sparse: each lane writes its hits at its offset (a wave's stores of one
+                // slot index land on neighbouring lines and are merged in L2)
+                for (uint32_t k = 0; k < c; k++) {
+                    const uint64_t r = run + before + k - a.lo;
+                    if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[SUB_LANE * threadIdx.x + k]);
+                }
+            } else {
+                // dense: the lanes' hits compacted in place, then written coalesced
+                uint16_t v[SUB_LANE];
+#pragma unroll
+                for (int k = 0; k < SUB_LANE; k++) v[k] = (uint32_t)k < c ? s_list[SUB_LANE * threadIdx.x + k] : 0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < SUB_LANE; k++)
+                    if ((uint32_t)k < c) s_list[before + k] = v[k];
+                __syncthreads();
+                for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK) {
+                    const uint64_t r = run + k - a.lo;
+                    if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[k]);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             run += ctot;
         }
     }
