@@ -39,6 +39,7 @@
 #include "../../include/sm.h"
 #include "sm_batch_host.h"
 #include "sm_ring.h"
+#include "sm_sched.h"
 
 using namespace sm;
 
@@ -307,28 +308,11 @@ void scheduler(sm_server *S)
             S->cv_slot.wait(lk, [&] { return S->stop || !s.busy; });
             S->cv_work.wait(lk, [&] { return S->stop || S->npending > 0; });
             if (S->stop) return;
-            // the corpus whose oldest query arrived first
-            size_t best = 0;
-            int64_t best_t = INT64_MAX;
-            uint64_t best_tk = UINT64_MAX;
-            for (size_t k = 0; k < S->pending.size(); k++) {
-                if (S->pending[k].empty()) continue;
-                const Query *q = S->pending[k].front();
-                if (q->arrival_ns < best_t || (q->arrival_ns == best_t && q->ticket < best_tk)) {
-                    best = k;
-                    best_t = q->arrival_ns;
-                    best_tk = q->ticket;
-                }
-            }
-            auto &dq = S->pending[best];
-            s.qs.clear();
+            // the corpus whose oldest query arrived first, up to max_batch of its queries
+            const size_t best = sched_pick(S->pending);
+            sched_take(S->pending[best], S->cfg.max_batch, s.qs);
             const int64_t t = now_ns();
-            while (!dq.empty() && s.qs.size() < S->cfg.max_batch) {
-                Query *q = dq.front();
-                dq.pop_front();
-                q->start_ns = t;
-                s.qs.push_back(q);
-            }
+            for (Query *q : s.qs) q->start_ns = t;
             S->npending -= s.qs.size();
             for (Query *q : s.qs) q->batch_size = (uint32_t)s.qs.size();
             c = S->corpora[best];
