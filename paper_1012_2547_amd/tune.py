@@ -9,7 +9,7 @@ fastest configuration of each cell becomes a table entry. The paper's own
 summary (Section 4) says the best algorithm depends on exactly these two
 quantities; this measures that map on MI355X.
 
-    python -m paper_1012_2547_amd.tune --out gpurun_out/tune --n-log2 30   # on a GPU
+    python -m paper_1012_2547_amd.tune --out tune_out --n-log2 30   # on a GPU
 writes tune.json (entries + timings) and tune_table.inc (C initialisers for
 csrc/tune_table.inc).
 """
@@ -51,7 +51,7 @@ def candidates(m: int, sigma: int):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/tune")
+    ap.add_argument("--out", default="tune_out")
     ap.add_argument("--n-log2", type=int, default=30)
     ap.add_argument("--patterns", type=int, default=3)
     ap.add_argument("--reps", type=int, default=2)
