@@ -38,7 +38,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sm_kernels.hip", "sm_internal.h"):
+    for f in ("sm_kernels.hip", "sm_device.h", "sm_internal.h"):
         with open(os.path.join(ROOT, "paper_1012_2547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -135,7 +135,7 @@ def main():
     corpora = {s: sm.Corpus(dev_texts[s]) for s in SIGMAS}
     sigma_eff = {s: round(corpora[s].stats()[2], 2) for s in SIGMAS}
     calls = [(s, m, p) for s in SIGMAS for m in MS for p in pats[(s, m)]]
-    work = torch.empty(sm.workspace_size(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
+    work = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
                        device=dev)
     counts_dev = torch.zeros(len(calls), dtype=torch.int64, device=dev)
     # exact counts (sizes the output buffer; checked after every step)
@@ -312,7 +312,7 @@ def batched_section(args, dev, stream):
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3 / reps
     # plain: one single-pattern count per pattern
-    w1 = torch.empty(sm.workspace_size(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
+    w1 = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
                      device=dev)
     d_p = torch.zeros(P, dtype=torch.int64, device=dev)
     for i in range(min(P, 64)):  # warm-up

@@ -348,10 +348,10 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     uint8_t *dpat = ws + w.pat;
     FindWs fw;
     fw.tile_cnt = reinterpret_cast<uint32_t *>(ws + w.tile_cnt);
-    fw.tile_off = reinterpret_cast<uint64_t *>(ws + w.tile_off);
-    fw.list = reinterpret_cast<uint32_t *>(ws + w.list);
+    fw.list = reinterpret_cast<TileEntry *>(ws + w.list);
     fw.nlist = reinterpret_cast<uint64_t *>(ws + w.nlist);
     fw.stash = reinterpret_cast<uint16_t *>(ws + w.stash);
+    fw.bits = w.bits ? reinterpret_cast<uint32_t *>(ws + w.bits) : nullptr;
     fw.ntiles = w.ntiles;
 
     bool prof;

@@ -181,6 +181,31 @@ struct StashEmit {
     __device__ __forceinline__ void add(uint32_t) {}
 };
 
+// Hits as a bitmap of the lane's starts (bit i of w[i / 64] <-> start lo + i),
+// kept in registers; the Shift-And scanner hands over whole hit masks.
+template <int NW>
+struct BitAcc {
+    uint64_t w[NW] = {};
+    // r: bit i <-> start lo + rel + i; every set bit lies in [0, 64 NW), rel > -32
+    __device__ __forceinline__ void put_mask(int rel, uint32_t r)
+    {
+#pragma unroll
+        for (int k = 0; k < NW; k++) {
+            const int s = rel - 64 * k;
+            if (NW > 1 && (s <= -32 || s >= 64)) continue;
+            w[k] |= s >= 0 ? (uint64_t)r << s : (uint64_t)(r >> -s);
+        }
+    }
+};
+template <class E>
+struct takes_masks {
+    static constexpr bool value = false;
+};
+template <int NW>
+struct takes_masks<BitAcc<NW>> {
+    static constexpr bool value = true;
+};
+
 // Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
 // hit checks (requires m - 1 + CHECK <= bits of W).
 template <typename W, int CHECK, bool WRITE, class E>
@@ -211,7 +236,12 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *ma
                 uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
                 hits &= ((2u << jhi) - 1u) & ~((1u << jlo) - 1u);
                 if (hits) {
-                    if (WRITE && o.saturated()) {
+                    if constexpr (takes_masks<E>::value) {
+                        // reversed, bit i <-> end e_last - CHECK + 1 + i, i.e. start
+                        // lo + (e_last - CHECK + 1 - e_lo) + i
+                        o.put_mask(e_last - CHECK + 1 - e_lo, __builtin_bitreverse32(hits) >> (32 - CHECK));
+                        cnt += __builtin_popcount(hits);
+                    } else if (WRITE && o.saturated()) {
                         o.add((uint32_t)__builtin_popcount(hits));
                     } else if (WRITE) {
                         // bit j <-> end e_last - j; ascending positions = descending j

@@ -55,10 +55,19 @@ struct Plan {
     uint64_t m;
 };
 
+// A tile with hits, as the tile-count scan lists it for the emit pass.
+struct TileEntry {
+    uint32_t t;    // tile index
+    uint32_t cnt;  // its hits
+    uint64_t off;  // hit number of its first hit
+};
+static_assert(sizeof(TileEntry) == 16, "one 16-byte load per entry");
+
 // Workspace layout (offsets in bytes from the workspace base):
-// [Params][pattern][tile_cnt u32][tile_off u64][list u32][nlist u64][stash u16 x STASH_K per tile]
+// [Params][pattern][tile_cnt u32][list TileEntry][nlist u64][stash u16 x STASH_K per tile]
+// [bits: one bit per start, m <= BP_MAX_M only]
 struct WsLayout {
-    uint64_t params, pat, tile_cnt, tile_off, list, nlist, stash;
+    uint64_t params, pat, tile_cnt, list, nlist, stash, bits;
     uint64_t need;        // minimum workspace size for find_all
     uint64_t need_count;  // minimum workspace size for count (params, pattern, tile_cnt)
     uint64_t ntiles;
@@ -86,14 +95,19 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
     w.tile_cnt = o;
     o = align_up(o + 4 * w.ntiles, 256);
     w.need_count = align_up(o, 256);
-    w.tile_off = o;
-    o = align_up(o + 8 * w.ntiles, 256);
     w.list = o;
-    o = align_up(o + 4 * w.ntiles, 256);
+    o = align_up(o + sizeof(TileEntry) * w.ntiles, 256);
     w.nlist = o;
     o = align_up(o + 8, 256);
     w.stash = o;
     o = align_up(o + 2ull * STASH_K * w.ntiles, 256);
+    // hit bitmaps of dense Shift-And tiles: tile t at bit t * tile; whatever the
+    // tile (at most BLOCK * 128 starts), the last one ends before bit n + BLOCK * 128
+    w.bits = 0;
+    if (m <= (uint64_t)BP_MAX_M && w.ntiles) {
+        w.bits = o;
+        o = align_up(o + (n + (uint64_t)BLOCK * 128) / 8 + 8, 256);
+    }
     w.need = o;
     return w;
 }
@@ -101,10 +115,10 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
 // Device pointers of the find_all workspace.
 struct FindWs {
     uint32_t *tile_cnt;
-    uint64_t *tile_off;
-    uint32_t *list;
+    TileEntry *list;
     uint64_t *nlist;
     uint16_t *stash;
+    uint32_t *bits;  // null when the layout has no bitmap region
     uint64_t ntiles;
 };
 

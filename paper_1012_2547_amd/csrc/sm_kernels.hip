@@ -59,9 +59,9 @@ struct ScanArgs {
     uint64_t *total;      // count mode: occurrences are added here
     uint32_t *tile_cnt;   // find mode: per-tile counts (count kernel writes, emit reads)
     uint16_t *stash;      // find mode: STASH_K offsets per tile
-    const uint64_t *tile_off;  // emit: exclusive prefix of tile_cnt
-    const uint32_t *list;      // emit: tiles with hits, ascending
+    const TileEntry *list;     // emit: tiles with hits, ascending, with their offsets
     const uint64_t *nlist;     // emit: list length
+    uint32_t *bits;       // find, bitmap form: hit bitmaps of the dense tiles (T / 32 words per tile)
     int64_t *out;         // emit: hit number k of the pattern goes to out[k - lo]
     uint64_t lo, cap;     // emit: window [lo, lo + cap) of hit numbers
 };
@@ -186,16 +186,16 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
                                              int li0, int lo, int hi, E &o)
 {
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
-    if (ALGO == ALGO_SHIFT_AND) {
+    if constexpr (ALGO == ALGO_SHIFT_AND) {
         if (VAR == 0)
             return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
                                                        m, li0, lo, hi, o);
         if (VAR == 1) return lane_shift_and<uint64_t, 16, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
         if (VAR == 2) return lane_shift_and<uint64_t, 4, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
         return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
-    } else if (ALGO == ALGO_BNDM) {
+    } else if constexpr (ALGO == ALGO_BNDM) {
         return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
-    } else if (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
+    } else if constexpr (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
         constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : (VAR == 2 ? 4 : 8));
         return lane_sbndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
                                     lo, hi, o);
@@ -206,16 +206,29 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
     }
 }
 
+// What the count kernel keeps besides the per-tile counts (find mode: each
+// tile with 1..STASH_K hits also stashes its hits' offsets).
+enum CountMode {
+    CM_COUNT = 0,  // counts only
+    CM_FIND = 1,   // stash tiles are scanned again into the stash
+    CM_CAP = 2,    // Shift-And, sparse tiles expected: lanes keep their first LANE_K hits
+    CM_BITS = 3,   // Shift-And, dense tiles expected (L >= 32): lanes keep hit bitmaps;
+                   // dense tiles' bitmaps go to the emit pass, the others fill the stash
+};
+
 // Count kernel: per-tile counts go to tile_cnt (the tile-count scan then sums
-// them: one atomic per workgroup on a single address would serialize). FIND:
-// tiles with 1..STASH_K hits also stash their hits' offsets.
+// them: one atomic per workgroup on a single address would serialize).
 // A workgroup owns tiles_per_wg consecutive tiles. PREFETCH: the next tile's
 // loads are in flight while the current tile is scanned (costs registers);
-// otherwise each tile is loaded after the previous one is done.
-template <int ALGO, int L, int VAR, bool FIND, bool PREFETCH>
+// otherwise each tile is loaded after the previous one is done. Each mode is a
+// kernel of its own: a mode's registers do not weigh on the others.
+template <int ALGO, int L, int VAR, int MODE, bool PREFETCH>
 __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
 {
     using G = Geometry<ALGO, L>;
+    static_assert(MODE == CM_COUNT || MODE == CM_FIND || ALGO == ALGO_SHIFT_AND, "hit masks come from Shift-And");
+    static_assert(MODE != CM_BITS || L >= 32, "bitmaps take lanes of >= 32 starts");
+    constexpr bool FIND = MODE != CM_COUNT;
     __shared__ TileShared<ALGO, L> S;
     const int m = (int)a.m;
 
@@ -250,13 +263,13 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         }
         const int lo = threadIdx.x * L;
         const int hi = (lo + L - 1) < cur.hi_rel ? (lo + L - 1) : cur.hi_rel;
-        // Shift-And (hits come as bit masks) counts while keeping the lane's first
-        // hits; the skip algorithms count (their hits are rare) and scan again
-        constexpr bool CAP_OK = FIND && ALGO == ALGO_SHIFT_AND;
-        const bool cap = CAP_OK && a.slots;  // uniform
+        constexpr int NW = L > 64 ? L / 64 : 1;
         uint32_t c;
-        CapEmit ce;
-        if (cap) {
+        [[maybe_unused]] CapEmit ce;
+        [[maybe_unused]] BitAcc<NW> ba;
+        if constexpr (MODE == CM_BITS) {
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba);
+        } else if constexpr (MODE == CM_CAP) {
             run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce);
             c = ce.n;
         } else {
@@ -266,15 +279,121 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
         if (threadIdx.x == 0) a.tile_cnt[t] = tot;
-        if (FIND && tot && tot <= STASH_K) {  // uniform
-            uint16_t *dst = a.stash + t * STASH_K;
-            if (cap && !__syncthreads_or(c > LANE_K)) {
-                for (uint32_t k = 0; k < c; k++) dst[before + k] = ce.get(k);
-            } else {  // scan again into the stash
-                StashEmit se;
-                se.dst = dst;
-                se.idx = before;
-                run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
+        if constexpr (MODE == CM_BITS) {
+            if (tot > STASH_K) {  // uniform: the tile's bitmap for the emit pass
+                uint32_t *dst = a.bits + t * (uint64_t)(G::T / 32) + threadIdx.x * (L / 32);
+                if (L == 32) {
+                    *dst = (uint32_t)ba.w[0];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NW; k++)
+                        reinterpret_cast<uint64_t *>(dst)[k] = ba.w[k];
+                }
+            } else if (tot) {  // uniform: stash from the bitmap
+                uint16_t *dst = a.stash + t * STASH_K;
+                uint32_t k = before;
+#pragma unroll
+                for (int i = 0; i < NW; i++) {
+                    uint64_t x = ba.w[i];
+                    while (x) {
+                        dst[k++] = (uint16_t)(lo + 64 * i + __builtin_ctzll(x));
+                        x &= x - 1;
+                    }
+                }
+            }
+        } else if constexpr (FIND) {
+            if (tot && tot <= STASH_K) {  // uniform
+                uint16_t *dst = a.stash + t * STASH_K;
+                if (MODE == CM_CAP && !__syncthreads_or(c > LANE_K)) {
+                    for (uint32_t k = 0; k < c; k++) dst[before + k] = ce.get(k);
+                } else {  // scan again into the stash
+                    StashEmit se;
+                    se.dst = dst;
+                    se.idx = before;
+                    run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Emit pass helpers. Waves work independently on list entries: wave g of G
+// takes entries g, g + G, g + 2G, ..., 64 at a time, one per lane, so their
+// list, count and offset loads are in flight together.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int k)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, k);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int k)
+{
+    return ((uint64_t)lane_u32((uint32_t)(v >> 32), k) << 32) | lane_u32((uint32_t)v, k);
+}
+
+// One batch of a wave's list entries: entry base + lane * G.
+struct EmitBatch {
+    uint32_t t = 0, cnt = 0;  // tile, its hits
+    uint64_t off = 0;         // its first hit number
+    uint64_t stash = 0;       // lanes whose tile overlaps the window and uses its stash
+    uint64_t dense = 0;       // lanes whose tile overlaps the window and has more hits
+};
+
+__device__ __forceinline__ EmitBatch emit_batch(const ScanArgs &a, uint64_t base, uint64_t G, uint64_t nl)
+{
+    EmitBatch b;
+    const uint64_t e = base + (uint64_t)(threadIdx.x & 63) * G;
+    if (e < nl) {
+        const TileEntry x = a.list[e];
+        b.t = x.t;
+        b.cnt = x.cnt;
+        b.off = x.off;
+    }
+    const bool in_win = b.cnt && b.off < a.lo + a.cap && b.off + b.cnt > a.lo;
+    b.stash = __ballot(in_win && b.cnt <= STASH_K);
+    b.dense = __ballot(in_win && b.cnt > STASH_K);
+    return b;
+}
+
+// The batch's stash tiles (tile-relative starts) to their offsets: four tiles
+// at a time, 16 lanes each, every load of the four issued before any store. A
+// lane reads 16-byte pieces (eight entries) at entries 8 sub and 8 sub + 128.
+__device__ __forceinline__ void emit_stash_batch(const ScanArgs &a, const EmitBatch &b, uint64_t T)
+{
+    static_assert(STASH_K == 256, "two 128-entry halves per tile");
+    uint64_t sm_ = b.stash;
+    const uint32_t lane = threadIdx.x & 63, q = lane >> 4, sub = lane & 15;
+    while (sm_) {  // uniform
+        // this lane group's tile: the q-th of the next four
+        uint32_t ck = 0;
+        uint64_t tk = 0, ok = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < 4; g++) {
+            if (!sm_) break;
+            const int k = __builtin_ctzll(sm_);
+            sm_ &= sm_ - 1;
+            const uint32_t c = lane_u32(b.cnt, k);
+            const uint64_t t = lane_u32(b.t, k), o = lane_u64(b.off, k);
+            if (q == g) {
+                ck = c;
+                tk = t;
+                ok = o;
+            }
+        }
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.stash + tk * STASH_K) + sub;
+        uint4 v[2] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+            if (8 * sub + 128 * h < ck) v[h] = src[16 * h];
+        const uint64_t s = tk * T;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t w[4] = {v[h].x, v[h].y, v[h].z, v[h].w};
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const uint32_t i = 8 * sub + 128 * h + e;
+                const uint64_t r = ok + i - a.lo;
+                if (i < ck && r < a.cap) a.out[r] = (int64_t)(s + ((w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu));
             }
         }
     }
@@ -299,89 +418,206 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
     const int period_lb = (int)a.prm->period_lb;
-    // 1. tiles with at most STASH_K hits: copy their stash
-    for (uint64_t e = blockIdx.x; e < nl; e += gridDim.x) {
-        const uint64_t t = a.list[e];
-        const uint32_t tot = a.tile_cnt[t];
-        const uint64_t off = a.tile_off[t];
-        if (tot > STASH_K || off >= a.lo + a.cap || off + tot <= a.lo) continue;  // uniform
-        const uint64_t s = t * (uint64_t)Geometry<ALGO, L>::T;
-        const uint16_t *src = a.stash + t * STASH_K;
-        for (uint32_t k = threadIdx.x; k < tot; k += BLOCK) {
-            const uint64_t r = off + k - a.lo;
-            if (r < a.cap) a.out[r] = (int64_t)(s + src[k]);
-        }
-    }
-    // 2. denser tiles: rescan from LDS
-    auto next_dense = [&](uint64_t e) -> uint64_t {  // uniform over the workgroup
-        for (; e < nl; e += gridDim.x) {
-            const uint64_t t = a.list[e];
-            const uint32_t tot = a.tile_cnt[t];
-            const uint64_t off = a.tile_off[t];
-            if (tot > STASH_K && off < a.lo + a.cap && off + tot > a.lo) return e;
-        }
-        return nl;
-    };
-    uint64_t e = next_dense(blockIdx.x);
-    if (e >= nl) return;
+    // 1. tiles with at most STASH_K hits: copy their stash (waves on their own)
     {
-        const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
-        tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
+        const uint64_t G = (uint64_t)gridDim.x * (BLOCK / 64);
+        const uint64_t g = (uint64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+        for (uint64_t base = g; base < nl; base += 64 * G)
+            emit_stash_batch(a, emit_batch(a, base, G, nl), (uint64_t)Geometry<ALGO, L>::T);
     }
+    // 2. denser tiles, rescanned from LDS: the workgroup's entries blockIdx.x +
+    // k gridDim.x are examined BLOCK at a time, one per thread, and the dense
+    // ones listed in LDS in order
+    __shared__ uint32_t s_dt[BLOCK];
+    __shared__ uint64_t s_do[BLOCK];
     using G = Geometry<ALGO, L>;
-    for (; e < nl; e = next_dense(e + gridDim.x)) {
-        const uint64_t t = a.list[e];
-        const uint64_t off = a.tile_off[t];
-        const TileGeom cur = tile_geom<ALGO, L>(a, t);
-        Staged<G::PER> st;
-        stage_issue(st, a.text, cur.x0, cur.x1);
-        __syncthreads();  // the previous tile's LDS readers are done
-        stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
-        const int li0 = st.boff - cur.r0;
+    bool tables = false;
+    for (uint64_t base = blockIdx.x; base < nl; base += (uint64_t)BLOCK * gridDim.x) {  // uniform
+        const uint64_t e0 = base + (uint64_t)threadIdx.x * gridDim.x;
+        TileEntry x{0u, 0u, 0ull};
+        if (e0 < nl) x = a.list[e0];
+        const uint32_t d = (x.cnt > STASH_K && x.off < a.lo + a.cap && x.off + x.cnt > a.lo) ? 1u : 0u;
+        uint32_t nd;
+        const uint32_t at = block_excl_scan(d, S.w, nd);  // ends with a barrier
+        if (nd == 0) continue;  // uniform
+        if (d) {
+            s_dt[at] = x.t;
+            s_do[at] = x.off;
+        }
+        if (!tables) {  // read by the scans after the next barrier
+            const uint4 tb = tables_issue<ALGO>(a.prm, a.hbits);
+            tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
+            tables = true;
+        }
         __syncthreads();
-        const uint64_t s2 = cur.s;
-        const int hi_rel = cur.hi_rel;
-        uint64_t run = off;
-        for (int sb = 0; sb <= hi_rel && run < a.lo + a.cap; sb += EMIT_SUB) {  // uniform
-            const int lo = sb + SUB_LANE * (int)threadIdx.x;
-            const int hi = (lo + SUB_LANE - 1) < hi_rel ? (lo + SUB_LANE - 1) : hi_rel;
-            // one scan: each lane keeps its hits (at most one per start) in its slots
-            ListEmit se;
-            se.dst = s_list + SUB_LANE * threadIdx.x;
-            se.idx = 0;
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, se);
-            const uint32_t c = se.idx;
-            uint32_t ctot;
-            const uint32_t before = block_excl_scan(c, S.w, ctot);  // ends with a barrier
-            if (ctot == 0) continue;  // uniform
-            if (run + ctot <= a.lo) {  // sub-tile entirely before the window (uniform)
+        for (uint32_t kd = 0; kd < nd; kd++) {
+            const uint64_t t = s_dt[kd];
+            const uint64_t off = s_do[kd];
+            const TileGeom cur = tile_geom<ALGO, L>(a, t);
+            Staged<G::PER> st;
+            stage_issue(st, a.text, cur.x0, cur.x1);
+            __syncthreads();  // the previous tile's LDS readers are done
+            stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+            const int li0 = st.boff - cur.r0;
+            __syncthreads();
+            const uint64_t s2 = cur.s;
+            const int hi_rel = cur.hi_rel;
+            uint64_t run = off;
+            for (int sb = 0; sb <= hi_rel && run < a.lo + a.cap; sb += EMIT_SUB) {  // uniform
+                const int lo = sb + SUB_LANE * (int)threadIdx.x;
+                const int hi = (lo + SUB_LANE - 1) < hi_rel ? (lo + SUB_LANE - 1) : hi_rel;
+                // one scan: each lane keeps its hits (at most one per start) in its slots
+                ListEmit se;
+                se.dst = s_list + SUB_LANE * threadIdx.x;
+                se.idx = 0;
+                run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, se);
+                const uint32_t c = se.idx;
+                uint32_t ctot;
+                const uint32_t before = block_excl_scan(c, S.w, ctot);  // ends with a barrier
+                if (ctot == 0) continue;  // uniform
+                if (run + ctot <= a.lo) {  // sub-tile entirely before the window (uniform)
+                    run += ctot;
+                    continue;
+                }
+                if (ctot <= (uint32_t)(EMIT_SUB / 8)) {  // uniform
+                    // sparse: each lane writes its hits at its offset (a wave's stores of one
+                    // slot index land on neighbouring lines and are merged in L2)
+                    for (uint32_t k = 0; k < c; k++) {
+                        const uint64_t r = run + before + k - a.lo;
+                        if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[SUB_LANE * threadIdx.x + k]);
+                    }
+                } else {
+                    // dense: the lanes' hits compacted in place, then written coalesced
+                    uint16_t v[SUB_LANE];
+#pragma unroll
+                    for (int k = 0; k < SUB_LANE; k++) v[k] = (uint32_t)k < c ? s_list[SUB_LANE * threadIdx.x + k] : 0;
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < SUB_LANE; k++)
+                        if ((uint32_t)k < c) s_list[before + k] = v[k];
+                    __syncthreads();
+                    for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK) {
+                        const uint64_t r = run + k - a.lo;
+                        if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[k]);
+                    }
+                    __syncthreads();
+                }
                 run += ctot;
-                continue;
             }
-            if (ctot <= (uint32_t)(EMIT_SUB / 8)) {  // uniform
-                // sparse: each lane writes its hits at its offset (a wave's stores of one
-                // slot index land on neighbouring lines and are merged in L2)
-                for (uint32_t k = 0; k < c; k++) {
-                    const uint64_t r = run + before + k - a.lo;
-                    if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[SUB_LANE * threadIdx.x + k]);
-                }
-            } else {
-                // dense: the lanes' hits compacted in place, then written coalesced
-                uint16_t v[SUB_LANE];
+        }
+        __syncthreads();  // s_dt / s_do are read before the next batch writes them
+    }
+}
+
+// LDS writes of one lane are seen by the other lanes of its wave after this
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// inclusive scan over the 64 lanes of a wave: DPP row shifts build the scan of
+// each row of 16 lanes, then the row broadcasts add the rows before it
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Emit kernel of the bitmap form (dense Shift-And tiles, L >= 32): the count
+// pass left each dense tile's hits as a bitmap of its T starts (64-bit words in
+// start order) and each sparse tile's in its stash. Waves work independently:
+// wave g of G takes list entries g, g + G, g + 2G, ..., 64 at a time (one per
+// lane, so their list, count and offset loads are in flight together). A stash
+// tile is copied by the whole wave, the next one's loads issued before this
+// one's stores. A dense tile is expanded 64 words (4096 starts) per round: a
+// wave scan of the words' bit counts places each lane's starts in the wave's
+// LDS list, which is copied to the output coalesced whenever the next round
+// might not fit, and at the tile's end; the next dense tile's words are loaded
+// meanwhile. The text is not read again.
+template <int L>
+__global__ __launch_bounds__(BLOCK) void emit_bits_kernel(ScanArgs a)
+{
+    constexpr int T = BLOCK * L;
+    constexpr int R = T / 64 / 64;  // rounds of 64 words per tile
+    constexpr int LIST = 64 * 64;   // a round's starts at most
+    static_assert(T <= 65536 && R >= 1, "tile-relative starts are kept as u16");
+    __shared__ uint16_t s_list[BLOCK / 64][LIST];
+    const uint64_t nl = *a.nlist;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t G = (uint64_t)gridDim.x * (BLOCK / 64);
+    const uint64_t g = (uint64_t)blockIdx.x * (BLOCK / 64) + (uint64_t)wv;
+    uint16_t *lst = s_list[wv];
+    const uint64_t *bits = reinterpret_cast<const uint64_t *>(a.bits);
+    for (uint64_t base = g; base < nl; base += 64 * G) {  // uniform over the wave
+        const EmitBatch bt = emit_batch(a, base, G, nl);
+        emit_stash_batch(a, bt, (uint64_t)T);
+        uint64_t dm = bt.dense;
+        // denser tiles: expand their bitmaps
+        if (dm) {
+            int k = __builtin_ctzll(dm);
+            dm &= dm - 1;
+            uint64_t tk = lane_u32(bt.t, k), ok = lane_u64(bt.off, k);
+            uint64_t x[R];
 #pragma unroll
-                for (int k = 0; k < SUB_LANE; k++) v[k] = (uint32_t)k < c ? s_list[SUB_LANE * threadIdx.x + k] : 0;
-                __syncthreads();
+            for (int r = 0; r < R; r++) x[r] = bits[tk * (uint64_t)(T / 64) + r * 64 + lane];
+            for (;;) {
+                const bool more = dm != 0;
+                uint64_t tk2 = 0, ok2 = 0;
+                uint64_t x2[R];
+                if (more) {  // the next dense tile's words are loaded during this one
+                    const int k2 = __builtin_ctzll(dm);
+                    dm &= dm - 1;
+                    tk2 = lane_u32(bt.t, k2);
+                    ok2 = lane_u64(bt.off, k2);
 #pragma unroll
-                for (int k = 0; k < SUB_LANE; k++)
-                    if ((uint32_t)k < c) s_list[before + k] = v[k];
-                __syncthreads();
-                for (uint32_t k = threadIdx.x; k < ctot; k += BLOCK) {
-                    const uint64_t r = run + k - a.lo;
-                    if (r < a.cap) a.out[r] = (int64_t)(s2 + s_list[k]);
+                    for (int r = 0; r < R; r++) x2[r] = bits[tk2 * (uint64_t)(T / 64) + r * 64 + lane];
                 }
-                __syncthreads();
+                const uint64_t s = tk * (uint64_t)T;
+                uint64_t run = ok;   // hit number of the list's first entry
+                uint32_t fill = 0;   // entries in the list
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const uint32_t pc = (uint32_t)__builtin_popcountll(x[r]);
+                    const uint32_t incl = wave_scan_dpp(pc);
+                    const uint32_t rt = lane_u32(incl, 63);  // this round's starts
+                    if (fill + rt > (uint32_t)LIST) {  // uniform: flush first
+                        wave_lds_sync();
+                        for (uint32_t i = lane; i < fill; i += 64) {
+                            const uint64_t o = run + i - a.lo;
+                            if (o < a.cap) a.out[o] = (int64_t)(s + lst[i]);
+                        }
+                        run += fill;
+                        fill = 0;
+                        wave_lds_sync();  // read before it is written again
+                    }
+                    uint32_t kk = fill + incl - pc;
+                    const int b0 = (r * 64 + lane) * 64;
+                    uint64_t y = x[r];
+                    while (y) {
+                        lst[kk++] = (uint16_t)(b0 + __builtin_ctzll(y));
+                        y &= y - 1;
+                    }
+                    fill += rt;
+                }
+                wave_lds_sync();
+                for (uint32_t i = lane; i < fill; i += 64) {
+                    const uint64_t o = run + i - a.lo;
+                    if (o < a.cap) a.out[o] = (int64_t)(s + lst[i]);
+                }
+                wave_lds_sync();
+                if (!more) break;
+                tk = tk2;
+                ok = ok2;
+#pragma unroll
+                for (int r = 0; r < R; r++) x[r] = x2[r];
             }
-            run += ctot;
         }
     }
 }
@@ -389,7 +625,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
 // Tile-count scan, SCAN_CHUNK tiles per workgroup of 1024 threads and no waiting
 // between workgroups: workgroup w first sums all counts before its chunk itself
 // (coalesced 16-byte loads, eight in flight per thread), then scans its chunk.
-// Writes exclusive offsets and the ascending list of tiles with hits; the last
+// Writes the ascending list of tiles with hits (with counts and offsets); the last
 // workgroup writes the total and the list length. With list == null only the
 // total is produced (count mode).
 __device__ __forceinline__ uint4 load_cnt4(const uint32_t *cnt, uint64_t i, uint64_t nt)
@@ -427,8 +663,8 @@ __device__ __forceinline__ void block_sum2_1024(uint64_t &a, uint32_t &b, uint64
 }
 
 __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint64_t nt,
-                                                         uint64_t *off, uint64_t *total,
-                                                         uint32_t *list, uint64_t *nlist)
+                                                         uint64_t *total, TileEntry *list,
+                                                         uint64_t *nlist)
 {
     __shared__ uint64_t s_a[16];
     __shared__ uint32_t s_b[16];
@@ -487,11 +723,14 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, ui
         uint64_t zp = pnz + zb + zincl - mz;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            if (i + k < nt) {
-                off[i + k] = o;
-                if (c[k]) list[zp++] = (uint32_t)(i + k);
-                o += c[k];
+            if (i + k < nt && c[k]) {
+                TileEntry x;
+                x.t = (uint32_t)(i + k);
+                x.cnt = c[k];
+                x.off = o;
+                list[zp++] = x;
             }
+            o += c[k];
         }
     }
     if (tid == 0 && blockIdx.x == gridDim.x - 1) {
@@ -570,12 +809,28 @@ hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
     if (grid == 0) return hipSuccess;
     const bool pf = a.tiles_per_wg > 1;
     if (KIND == K_COUNT) {
-        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false, true>), dim3(grid), dim3(BLOCK), 0, st, a);
-        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, false, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_COUNT, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_COUNT, false>), dim3(grid), dim3(BLOCK), 0, st, a);
     } else if (KIND == K_FIND_COUNT) {
-        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true, true>), dim3(grid), dim3(BLOCK), 0, st, a);
-        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, true, false>), dim3(grid), dim3(BLOCK), 0, st, a);
-    } else
+        // Shift-And: hit bitmaps when dense tiles are expected, else the lanes' first hits
+        if constexpr (ALGO == ALGO_SHIFT_AND) {
+            if (L >= 32 && a.bits) {
+                constexpr int LB = L >= 32 ? L : 32;
+                if (pf) hipLaunchKernelGGL((count_kernel<ALGO, LB, VAR, CM_BITS, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+                else hipLaunchKernelGGL((count_kernel<ALGO, LB, VAR, CM_BITS, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+                return hipGetLastError();
+            }
+            if (a.slots) {
+                if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_CAP, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+                else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_CAP, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+                return hipGetLastError();
+            }
+        }
+        if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_FIND, true>), dim3(grid), dim3(BLOCK), 0, st, a);
+        else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_FIND, false>), dim3(grid), dim3(BLOCK), 0, st, a);
+    } else if (ALGO == ALGO_SHIFT_AND && L >= 32 && a.bits)
+        hipLaunchKernelGGL((emit_bits_kernel<L >= 32 ? L : 32>), dim3(grid), dim3(BLOCK), 0, st, a);
+    else
         hipLaunchKernelGGL((emit_kernel<ALGO, L, VAR>), dim3(grid), dim3(BLOCK), 0, st, a);
     return hipGetLastError();
 }
@@ -678,8 +933,7 @@ static hipError_t launch_tile_scan(const FindWs &w, uint64_t *d_total, bool find
 {
     const uint64_t nb = (w.ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     hipLaunchKernelGGL(tile_scan_kernel, dim3((uint32_t)nb), dim3(1024), 0, stream, w.tile_cnt,
-                       w.ntiles, find ? w.tile_off : nullptr, d_total, find ? w.list : nullptr,
-                       find ? w.nlist : nullptr);
+                       w.ntiles, d_total, find ? w.list : nullptr, find ? w.nlist : nullptr);
     return hipGetLastError();
 }
 
@@ -708,12 +962,13 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, w.ntiles);
     a.tile_cnt = w.tile_cnt;
     a.stash = w.stash;
-    a.tile_off = w.tile_off;
     a.list = w.list;
     a.nlist = w.nlist;
     a.out = d_out;
     a.lo = first;
     a.cap = cap;
+    // bitmap form for Shift-And scans that expect dense tiles (lanes of >= 32 starts)
+    if (plan.algo == ALGO_SHIFT_AND && !plan.slots && plan.lane_bytes >= 32) a.bits = w.bits;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
     hipError_t e = launch_any<K_FIND_COUNT>(plan, a, g, stream);

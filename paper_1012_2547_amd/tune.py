@@ -69,7 +69,7 @@ def main():
     dev = torch.device("cuda:0")
     n = 1 << args.n_log2
     stream = torch.cuda.current_stream()
-    work = torch.empty(sm.workspace_size(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
+    work = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
                        device=dev)
     dc = torch.zeros(1, dtype=torch.int64, device=dev)
     results = []

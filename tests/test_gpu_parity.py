@@ -28,8 +28,8 @@ BP_ALGOS = (1, 2, 3)       # Shift-And, BNDM, SBNDM (m <= 64)
 ALL_ALGOS = (1, 2, 3, 4)   # + Hash-q
 
 
-def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0):
-    o = sm.opts(algo=algo, lane_bytes=lane, q=q, tiles_per_wg=tpw)
+def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0):
+    o = sm.opts(algo=algo, lane_bytes=lane, q=q, tiles_per_wg=tpw, sigma_hint=sigma_hint)
     n, m = text_t.numel(), len(pat)
     work = torch.empty(max(sm.workspace_size(n, m, o), 256), dtype=torch.uint8, device=DEV)
     dc = torch.zeros(1, dtype=torch.int64, device=DEV)
@@ -172,6 +172,32 @@ def test_truncation(sm):
             assert np.array_equal(got, want[:cap]), (a, cap)
 
 
+def test_dense_bitmap_form_mixed_tiles(sm):
+    """Shift-And scans that expect dense tiles (sigma^m < L, lanes of >= 32 starts)
+    keep each dense tile's hits as a bitmap in the count pass and expand it in the
+    emit pass; tiles with few hits go through the stash. A text of dense, sparse
+    and empty regions of ragged lengths, every lane width, with truncation; the
+    same searches planned as sparse (sigma hint 256) and at L = 16 take the other
+    paths and must agree."""
+    parts = [np.zeros(9001, np.uint8), dg.uniform_text(70_003, 4, seed=31),
+             np.zeros(5003, np.uint8), dg.uniform_text(40_009, 2, seed=32),
+             np.full(33_331, 200, np.uint8), np.zeros(20_011, np.uint8),
+             dg.uniform_text(31_999, 2, seed=33)]
+    t_np = np.concatenate(parts)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    pats = [b"\0", b"\0\0", b"\0\0\0\0", b"\0\1", bytes([1, 0, 1, 1, 0]), b"\0" * 7]
+    for p in pats:
+        want = oracle.find_all(t_np, p)
+        for L, tpw, hint in ((32, 1, 2), (64, 1, 2), (64, 3, 2), (128, 2, 2), (128, 1, 256),
+                             (16, 1, 2), (64, 2, 256)):
+            got, tot = gpu_find(sm, t_dev, p, algo=1, lane=L, tpw=tpw, sigma_hint=hint)
+            assert tot == want.size, (p, L, tpw, hint, tot, want.size)
+            assert np.array_equal(got, want), (p, L, tpw, hint)
+        for cap in (0, 3, want.size // 3, want.size - 1):
+            got, tot = gpu_find(sm, t_dev, p, algo=1, lane=64, cap=cap, sigma_hint=2)
+            assert tot == want.size and np.array_equal(got, want[:cap]), (p, cap)
+
+
 def test_edges_and_alignment(sm):
     rng = np.random.default_rng(0)
     base_np = rng.integers(0, 3, 20_000, dtype=np.uint8)
@@ -267,7 +293,9 @@ def test_workspace_reuse_across_calls(sm):
     """One workspace, many calls with varying n, m, algorithm and workspace size:
     nothing left in the workspace by earlier calls may leak into later ones."""
     rng = np.random.default_rng(5)
-    big = torch.empty(sm.workspace_size(1 << 19, 4096) + (1 << 16), dtype=torch.uint8, device=DEV)
+    # the largest need: the most tiles (16-byte lanes) with the bitmap region (m <= 64)
+    most = max(sm.workspace_size(1 << 19, m, sm.opts(lane_bytes=16)) for m in (1, 4096))
+    big = torch.empty(most + (1 << 16), dtype=torch.uint8, device=DEV)
     base_np = dg.uniform_text(1 << 19, 4, seed=77)
     base = torch.from_numpy(base_np).to(DEV)
     for i in range(400):
@@ -298,7 +326,7 @@ def test_corpus_async_paths(sm):
     for t_np in (dg.zipf_text(300_000, 64, 1.0, seed=3), dg.uniform_text(300_000, 2, seed=3)):
         t_dev = torch.from_numpy(t_np).to(DEV)
         c = sm.Corpus(t_dev)
-        work = torch.empty(sm.workspace_size(t_np.size, 1024, sm.opts(lane_bytes=16)),
+        work = torch.empty(max(sm.workspace_size(t_np.size, m_, sm.opts(lane_bytes=16)) for m_ in (1, 1024)),
                            dtype=torch.uint8, device=DEV)
         dc = torch.zeros(1, dtype=torch.int64, device=DEV)
         for m in (1, 3, 8, 20, 64, 65, 300, 1024):
