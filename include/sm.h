@@ -122,8 +122,8 @@ int sm_count_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t
  * find_all runs three kernels: a count pass over the text (which also keeps the
  * hit offsets of tiles with few hits), a scan of the per-tile counts, and an
  * emit pass that writes positions. Tiles with many hits are re-read by the emit
- * pass, except in Shift-And scans planned as dense (sigma^m below the lane
- * width), where the count pass keeps their hits as a bitmap of starts. count
+ * pass, except in Shift-And scans with lanes of >= 32 starts, where the count
+ * pass keeps their hits as a bitmap of starts. count
  * runs the first kernel only; its workspace may be smaller.
  *
  * The size depends on m: for m <= 64 it holds that bitmap (n bits), and fewer

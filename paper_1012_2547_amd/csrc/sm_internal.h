@@ -28,7 +28,7 @@ constexpr uint32_t PERIOD_MAX = 64;  // periods searched by the prep kernel
 constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass
 constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
 constexpr int EMIT_SUB = 4096;       // starts per sub-tile when a dense tile is rescanned
-constexpr uint64_t SCAN_CHUNK = 4096; // tile counts per workgroup of the tile-count scan
+constexpr uint64_t SCAN_CHUNK = 4096;  // tile counts per workgroup of the tile-count scan (4 per thread)
 constexpr int AUTO_MIN_LANE = 64;    // lane_bytes of the planner's heuristic (no table entry)
 
 // Device-side parameter block at the start of the caller's workspace; the

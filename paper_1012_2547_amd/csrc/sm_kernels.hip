@@ -211,9 +211,9 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
 enum CountMode {
     CM_COUNT = 0,  // counts only
     CM_FIND = 1,   // stash tiles are scanned again into the stash
-    CM_CAP = 2,    // Shift-And, sparse tiles expected: lanes keep their first LANE_K hits
-    CM_BITS = 3,   // Shift-And, dense tiles expected (L >= 32): lanes keep hit bitmaps;
-                   // dense tiles' bitmaps go to the emit pass, the others fill the stash
+    CM_CAP = 2,    // Shift-And, L = 16, sparse tiles expected: lanes keep their first LANE_K hits
+    CM_BITS = 3,   // Shift-And, L >= 32: lanes keep hit bitmaps; the bitmaps of tiles with
+                   // more than STASH_K hits go to the emit pass, the others fill the stash
 };
 
 // Count kernel: per-tile counts go to tile_cnt (the tile-count scan then sums
@@ -624,7 +624,8 @@ __global__ __launch_bounds__(BLOCK) void emit_bits_kernel(ScanArgs a)
 
 // Tile-count scan, SCAN_CHUNK tiles per workgroup of 1024 threads and no waiting
 // between workgroups: workgroup w first sums all counts before its chunk itself
-// (coalesced 16-byte loads, eight in flight per thread), then scans its chunk.
+// (coalesced 16-byte loads, eight in flight per thread), then scans its chunk,
+// SCAN_CHUNK / 1024 consecutive counts per thread.
 // Writes the ascending list of tiles with hits (with counts and offsets); the last
 // workgroup writes the total and the list length. With list == null only the
 // total is produced (count mode).
@@ -687,12 +688,26 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, ui
         }
     }
     block_sum2_1024(pre, pnz, s_a, s_b);
-    // 2. this chunk: SCAN_CHUNK / 1024 = 4 consecutive counts per thread
-    const uint64_t i = c0 + 4 * (uint64_t)tid;
-    const uint4 v = load_cnt4(cnt, i, nt);
-    const uint32_t c[4] = {v.x, v.y, v.z, v.w};
-    const uint64_t my = (uint64_t)c[0] + c[1] + c[2] + c[3];
-    const uint32_t mz = (c[0] != 0) + (c[1] != 0) + (c[2] != 0) + (c[3] != 0);
+    // 2. this chunk: SCAN_CHUNK / 1024 consecutive counts per thread
+    constexpr int PER = (int)(SCAN_CHUNK / 1024);
+    static_assert(PER % 4 == 0, "whole 16-byte loads");
+    const uint64_t i = c0 + PER * (uint64_t)tid;
+    uint32_t c[PER];
+#pragma unroll
+    for (int k = 0; k < PER / 4; k++) {
+        const uint4 v = load_cnt4(cnt, i + 4 * k, nt);
+        c[4 * k] = v.x;
+        c[4 * k + 1] = v.y;
+        c[4 * k + 2] = v.z;
+        c[4 * k + 3] = v.w;
+    }
+    uint64_t my = 0;
+    uint32_t mz = 0;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        my += c[k];
+        mz += c[k] != 0;
+    }
     uint64_t incl = my;
     uint32_t zincl = mz;
 #pragma unroll
@@ -722,7 +737,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, ui
         uint64_t o = pre + wb + incl - my;
         uint64_t zp = pnz + zb + zincl - mz;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < PER; k++) {
             if (i + k < nt && c[k]) {
                 TileEntry x;
                 x.t = (uint32_t)(i + k);
@@ -812,7 +827,8 @@ hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
         if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_COUNT, true>), dim3(grid), dim3(BLOCK), 0, st, a);
         else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_COUNT, false>), dim3(grid), dim3(BLOCK), 0, st, a);
     } else if (KIND == K_FIND_COUNT) {
-        // Shift-And: hit bitmaps when dense tiles are expected, else the lanes' first hits
+        // Shift-And: hit bitmaps, else (16-byte lanes) the lanes' first hits when sparse
+        // tiles are expected
         if constexpr (ALGO == ALGO_SHIFT_AND) {
             if (L >= 32 && a.bits) {
                 constexpr int LB = L >= 32 ? L : 32;
@@ -967,8 +983,8 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     a.out = d_out;
     a.lo = first;
     a.cap = cap;
-    // bitmap form for Shift-And scans that expect dense tiles (lanes of >= 32 starts)
-    if (plan.algo == ALGO_SHIFT_AND && !plan.slots && plan.lane_bytes >= 32) a.bits = w.bits;
+    // bitmap form for Shift-And scans with lanes of >= 32 starts
+    if (plan.algo == ALGO_SHIFT_AND && plan.lane_bytes >= 32) a.bits = w.bits;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
     hipError_t e = launch_any<K_FIND_COUNT>(plan, a, g, stream);

@@ -173,12 +173,12 @@ def test_truncation(sm):
 
 
 def test_dense_bitmap_form_mixed_tiles(sm):
-    """Shift-And scans that expect dense tiles (sigma^m < L, lanes of >= 32 starts)
-    keep each dense tile's hits as a bitmap in the count pass and expand it in the
-    emit pass; tiles with few hits go through the stash. A text of dense, sparse
-    and empty regions of ragged lengths, every lane width, with truncation; the
-    same searches planned as sparse (sigma hint 256) and at L = 16 take the other
-    paths and must agree."""
+    """Shift-And scans with lanes of >= 32 starts keep each lane's hits as a
+    bitmap in the count pass; tiles with more hits than the stash holds leave it
+    to the emit pass, which expands it, and the others fill their stash from it.
+    A text of dense, sparse and empty regions of ragged lengths, every lane
+    width, with truncation; at L = 16 the same searches take the rescanning
+    paths (first-hit slots when planned sparse, sigma hint 256) and must agree."""
     parts = [np.zeros(9001, np.uint8), dg.uniform_text(70_003, 4, seed=31),
              np.zeros(5003, np.uint8), dg.uniform_text(40_009, 2, seed=32),
              np.full(33_331, 200, np.uint8), np.zeros(20_011, np.uint8),
@@ -189,7 +189,7 @@ def test_dense_bitmap_form_mixed_tiles(sm):
     for p in pats:
         want = oracle.find_all(t_np, p)
         for L, tpw, hint in ((32, 1, 2), (64, 1, 2), (64, 3, 2), (128, 2, 2), (128, 1, 256),
-                             (16, 1, 2), (64, 2, 256)):
+                             (16, 1, 2), (16, 2, 256), (64, 2, 256)):
             got, tot = gpu_find(sm, t_dev, p, algo=1, lane=L, tpw=tpw, sigma_hint=hint)
             assert tot == want.size, (p, L, tpw, hint, tot, want.size)
             assert np.array_equal(got, want), (p, L, tpw, hint)
