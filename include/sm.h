@@ -57,14 +57,19 @@ enum sm_algo {
     SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel, m <= 64 (Fig. 3) */
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */
     SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
-    SM_ALGO_HASHQ = 4      /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
+    SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
+    SM_ALGO_BLOCK = 5      /* 16-byte block fingerprint filter after SSEF (Fig. 1), 32 <= m <= 4096:
+                              one 16-byte block per m - 15 text bytes is read and looked up among
+                              the pattern's blocks, candidates verified byte-exactly */
 };
 
 /*
  * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
  * Options change speed only, never results. Invalid combinations (a bit-parallel
- * algorithm with m > 64, q > m or q > 16, lane_bytes not in {16,32,64,128},
- * hbits outside [8,12]) are SM_EINVAL.
+ * algorithm with m > 64, the block filter with m outside [32, 4096], q > m or
+ * q > 16, lane_bytes not in {16,32,64,128}, hbits outside [8,12]) are SM_EINVAL.
+ * lane_bytes, q and hbits do not apply to the block filter (its tile is the
+ * starts of 256 sampled blocks).
  */
 typedef struct sm_opts {
     int32_t algo;         /* enum sm_algo */
@@ -335,6 +340,8 @@ typedef struct sm_prof {
     double emit_ms;        /* tile scan + emit kernels (find_all only) */
     double total_ms;       /* whole calls: pattern preparation + all kernels */
     uint64_t text_bytes;   /* sum of n over the calls */
+    uint64_t sampled_calls;   /* of the calls, those whose count pass is the block filter, */
+    double sampled_count_ms;  /* which reads one 16-byte block per m - 15 bytes, and its time */
 } sm_prof;
 int sm_prof_enable(int on);
 int sm_prof_collect(sm_prof *out);

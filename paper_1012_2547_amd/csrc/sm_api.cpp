@@ -200,7 +200,10 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
         return fail(SM_EINVAL, "hbits must be in [%d, %d]", H_MIN, H_MAX);
     if (o->tiles_per_wg < 0 || o->tiles_per_wg > 4096)
         return fail(SM_EINVAL, "tiles_per_wg must be in [1, 4096]");
-    if (o->algo != ALGO_AUTO && o->algo != ALGO_HASHQ && m > BP_MAX_M)
+    if (o->algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M))
+        return fail(SM_EINVAL, "the block filter needs %d <= m <= %d (m = %llu)", BF_MIN_M, BF_MAX_M,
+                    (unsigned long long)m);
+    if (o->algo != ALGO_AUTO && o->algo != ALGO_HASHQ && o->algo != ALGO_BLOCK && m > BP_MAX_M)
         return fail(SM_EINVAL, "bit-parallel algorithms need m <= %d (m = %llu)", BP_MAX_M,
                     (unsigned long long)m);
     if (o->q && (uint64_t)o->q > m)
@@ -214,8 +217,12 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     sm_tune_entry te;
     const bool have = tune_lookup(sigma, m, te);
     int algo = have ? te.algo : 0;
-    if (algo != ALGO_HASHQ && m > BP_MAX_M) algo = 0;  // entry not applicable to this m
+    // entries not applicable to this m
+    if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && m > BP_MAX_M) algo = 0;
+    if (algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M)) algo = 0;
     if (have && te.algo == ALGO_HASHQ && te.q && (uint64_t)te.q > m) algo = 0;
+    // the block filter expects varied 16-byte blocks: not on a text of (nearly) one symbol
+    if (algo == ALGO_BLOCK && sigma < 2) algo = 0;
     const bool use_entry = algo != 0 && (o->algo == ALGO_AUTO || o->algo == algo);
     if (o->algo != ALGO_AUTO) algo = o->algo;
     if (algo == 0) {  // heuristic when no table entry applies
@@ -238,11 +245,17 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
         p.hbits = o->hbits ? o->hbits : (use_entry && te.hbits ? te.hbits : choose_hbits(m, p.q));
     }
     p.lane_bytes = o->lane_bytes ? o->lane_bytes : (use_entry && te.lane_bytes ? te.lane_bytes : 64);
+    if (algo == ALGO_BLOCK) p.lane_bytes = (int32_t)(m - 15);  // starts per sampled block
     p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg : (use_entry && te.tiles_per_wg ? te.tiles_per_wg : 1);
     // a tile of 256 * L starts expects 256 * L * sigma^-m hits on an i.i.d. text: at
     // most the stash (256) when sigma^m >= L; denser tiles go to the emit pass anyway
     p.slots = (double)m * std::log((double)sigma) >= std::log((double)p.lane_bytes) ? 1 : 0;
     return SM_OK;
+}
+
+int sm::plan_pattern_opts(const uint8_t *pat, uint64_t m, const sm_opts *o, Plan &p)
+{
+    return make_plan(pat, m, o, 0, p);
 }
 
 int sm::plan_pattern(const uint8_t *pat, uint64_t m, int sigma, Plan &p)
@@ -257,6 +270,7 @@ namespace {
 struct ProfRec {
     hipEvent_t e0, e1, e2, e3;  // start, after prep, after the count kernel, end
     uint64_t n;
+    bool sampled;  // block filter: the count pass reads sampled blocks only
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -289,6 +303,10 @@ extern "C" int sm_prof_collect(sm_prof *out)
             out->emit_ms += b;
             out->total_ms += c;
             out->text_bytes += r.n;
+            if (r.sampled) {
+                out->sampled_calls++;
+                out->sampled_count_ms += a;
+            }
         } else {
             st = fail(SM_EDEVICE, "event timing failed");
         }
@@ -314,8 +332,15 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
 
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
-    // explicit lanes, else the smallest the planner could pick for this m
+    // explicit lanes, else the smallest the planner could pick for this m (the
+    // block filter's tiles hold 256 (m - 15) starts)
     int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : min_auto_lane(m);
+    const bool block = opts && opts->algo == ALGO_BLOCK;
+    if (block) lb = (int)(m - 15);
+    else if ((!opts || opts->algo == ALGO_AUTO) && m >= (uint64_t)BF_MIN_M && m <= (uint64_t)BF_MAX_M &&
+             (int)(m - 15) < lb)
+        lb = (int)(m - 15);
+    if (lb < 1) lb = 1;
     Plan p;
     p.lane_bytes = lb;
     return ws_layout(n, m, tile_starts(p)).need;
@@ -366,6 +391,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         HIP_TRY(hipEventCreate(&rec.e2));
         HIP_TRY(hipEventCreate(&rec.e3));
         rec.n = n;
+        rec.sampled = plan.algo == ALGO_BLOCK;
         HIP_TRY(hipEventRecord(rec.e0, st));
     }
     HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, st));

@@ -269,6 +269,13 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         Plan p;
         int r = plan_pattern(pats + pat_off[i], m, sigma, p);
         if (r) return r;
+        if (p.algo == ALGO_BLOCK) {  // single-pattern only: the batch takes Hash-q instead
+            sm_opts o;
+            memset(&o, 0, sizeof o);
+            o.algo = ALGO_HASHQ;
+            o.sigma_hint = sigma;
+            if ((r = plan_pattern_opts(pats + pat_off[i], m, &o, p))) return r;
+        }
         BatchPat bp;
         memset(&bp, 0, sizeof bp);
         bp.m = (uint32_t)m;

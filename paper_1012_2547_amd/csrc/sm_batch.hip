@@ -668,7 +668,7 @@ __global__ __launch_bounds__(BLOCK) void batch_prep_kernel(const BatchPat *pats,
         P->q = bp.q;
         P->hbits = bp.hbits;
     }
-    build_tables(patbytes + bp.pat_off, bp.m, bp.algo, bp.q, bp.hbits, P, s_tab, s_bad);
+    build_tables(patbytes + bp.pat_off, bp.m, bp.algo, bp.q, bp.hbits, P, s_tab, s_bad, nullptr);
 }
 
 // One workgroup per sorted pattern: per-chunk counts -> exclusive offsets and the

@@ -42,6 +42,16 @@ __device__ __forceinline__ uint32_t qhash(uint32_t w0, uint32_t w1, uint32_t w2,
     return h >> (32 - hbits);
 }
 
+// Block filter hash of 16 bytes (four little-endian words) to BF_H bits. Any
+// hash is correct: every candidate is compared byte-exactly.
+__device__ __forceinline__ uint32_t bf_hash(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
+{
+    uint32_t h = (w0 * 0x9E3779B1u) ^ (w1 * 0x85EBCA77u) ^ (w2 * 0xC2B2AE3Du) ^ (w3 * 0x27D4EB2Fu);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    return h >> (32 - BF_H);
+}
+
 __device__ __forceinline__ uint32_t byte_mask(int nbytes)  // nbytes in [0, 4]
 {
     return nbytes >= 4 ? 0xFFFFFFFFu : ((1u << (8 * nbytes)) - 1u);
@@ -394,6 +404,88 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Block filter (after SSEF, Fig. 1). With S = m - 15, an occurrence at i contains
+// the 16-byte block at x whenever i <= x <= i + m - 16, an interval of S starts; so
+// the blocks at x_b = b S + S - 1 meet every occurrence, and block b is the only
+// one to test for the starts it owns, [b S, b S + S): i = x_b - j for an alignment
+// j < S with p[j, j + 16) equal to the block. The text is read at one block per S
+// bytes; the pattern's alignments are bucketed by the block hash.
+// ---------------------------------------------------------------------------
+// The 16 bytes at p, any alignment, from the one or two aligned 16-byte chunks
+// that hold them (both lie inside the buffer when the 16 bytes do).
+__device__ __forceinline__ uint4 load16_chunks(const uint8_t *p)
+{
+    const uintptr_t a = (uintptr_t)p;
+    const uint4 *c = reinterpret_cast<const uint4 *>(a & ~(uintptr_t)15);
+    const uint32_t r = (uint32_t)(a & 15);
+    const uint4 c0 = c[0];
+    const uint4 c1 = r ? c[1] : uint4{0u, 0u, 0u, 0u};
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    const uint32_t q = r >> 2, sh = r & 3;
+    uint32_t v[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++)
+        v[k] = q == 0 ? w[k] : (q == 1 ? w[k + 1] : (q == 2 ? w[k + 2] : w[k + 3]));
+    uint4 o;
+    o.x = alignbyte(v[1], v[0], sh);
+    o.y = alignbyte(v[2], v[1], sh);
+    o.z = alignbyte(v[3], v[2], sh);
+    o.w = alignbyte(v[4], v[3], sh);
+    return o;
+}
+
+// t[g + off, g + off + len) == p[off, off + len), compared in 16-byte pieces from
+// the end (the window [g, g + m) lies inside the text; p is padded by 16 bytes)
+__device__ __forceinline__ bool bf_equal(const uint8_t *text, uint64_t g, const uint8_t *pat,
+                                         uint32_t m, uint32_t off, uint32_t len)
+{
+    const uint8_t *tlast = text + g + m - 1, *plast = pat + m + 15;
+    for (uint32_t e = len; e > 0;) {
+        const uint32_t b = e >= 16 ? e - 16 : 0;
+        if (diff16(load16(text + g + off + b, tlast), load16(pat + off + b, plast), e - b)) return false;
+        e = b;
+    }
+    return true;
+}
+
+// Occurrences among the starts [ilo, ihi] of sampled block x (ihi <= x, x - ilo < S,
+// x + 16 <= n); blk = the block's 16 bytes. Candidates come in ascending order, so
+// an occurrence v already found rules out starts closer than the pattern's smallest
+// period, and one exactly a period away needs only its last period bytes.
+template <bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_block(const uint8_t *text, const uint8_t *pat, uint32_t m,
+                                               const Params *prm, uint32_t period, uint32_t period_lb,
+                                               uint64_t x, uint64_t ilo, uint64_t ihi, uint4 blk,
+                                               uint64_t base, E &o)
+{
+    const uint32_t h = bf_hash(blk.x, blk.y, blk.z, blk.w);
+    const uint32_t k0 = prm->bf_start[h], k1 = prm->bf_start[h + 1];
+    uint32_t cnt = 0;
+    bool have = false;
+    uint64_t v = 0;
+    for (uint32_t k = k0; k < k1; k++) {
+        const uint32_t j = prm->bf_js[k];
+        const uint64_t i = x - j;  // >= ilo since j < S
+        if (i > ihi) break;        // j descending: the remaining starts are larger still
+        const uint4 pb = load16(pat + j, pat + m + 15);
+        if ((pb.x ^ blk.x) | (pb.y ^ blk.y) | (pb.z ^ blk.z) | (pb.w ^ blk.w)) continue;
+        if (have && i - v < period_lb) continue;
+        bool ok;
+        if (have && period && i - v == period)
+            ok = bf_equal(text, i, pat, m, m - period, period);
+        else
+            ok = bf_equal(text, i, pat, m, j + 16, m - j - 16) && bf_equal(text, i, pat, m, 0, j);
+        if (ok) {
+            have = true;
+            v = i;
+            if (WRITE) o.put((int)(i - base));
+            else cnt++;
+        }
+    }
+    return cnt;
+}
+
 // Hash-q over the lane's windows. The LDS holds text positions from m-q on;
 // li0 is the LDS index of relative position 0 (may be negative).
 // Wave-cooperative: all 64 lanes of the wave call it (lanes without starts have
@@ -478,9 +570,70 @@ __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint
 // Tables of one pattern (masks, Hash-q shift table and sh1, period bounds) into
 // *P, by one whole workgroup of BLOCK threads. pp: the pattern (global or LDS);
 // s_tab: LDS scratch of 1 << H_MAX words; s_bad: LDS scratch of PERIOD_MAX + 1.
+// Block filter tables: hash every alignment j < S = m - 15 (counts per bucket in
+// s_tab, then their exclusive scan is bf_start), and sort the keys (hash, 4095 - j)
+// bitonically in s_key (4096 entries): bf_js lists each bucket in descending j.
+__device__ __forceinline__ void build_block_tables(const uint8_t *pp, uint32_t m, Params *P,
+                                                   uint32_t *s_tab, uint32_t *s_key, uint32_t *s_w)
+{
+    const int tid = threadIdx.x;
+    const uint32_t S = m - 15, nb = 1u << BF_H;
+    uint32_t N = 16;
+    while (N < S) N <<= 1;
+    for (uint32_t k = tid; k < nb; k += BLOCK) s_tab[k] = 0;
+    __syncthreads();
+    for (uint32_t j = tid; j < N; j += BLOCK) {
+        uint32_t key = 0xFFFFFFFFu;
+        if (j < S) {
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (uint32_t k = 0; k < 16; k++) w[k >> 2] |= (uint32_t)pp[j + k] << (8 * (k & 3));
+            const uint32_t h = bf_hash(w[0], w[1], w[2], w[3]);
+            atomicAdd(&s_tab[h], 1u);
+            key = (h << 12) | (4095u - j);
+        }
+        s_key[j] = key;
+    }
+    __syncthreads();
+    // exclusive scan of the nb counts, 16 per thread
+    {
+        constexpr uint32_t PER = (1u << BF_H) / BLOCK;
+        uint32_t c[PER], sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) {
+            c[k] = s_tab[tid * PER + k];
+            sum += c[k];
+        }
+        uint32_t tot;
+        uint32_t run = block_excl_scan(sum, s_w, tot);
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) {
+            P->bf_start[tid * PER + k] = (uint16_t)run;
+            run += c[k];
+        }
+        if (tid == 0) P->bf_start[nb] = (uint16_t)S;
+    }
+    // bitonic sort of s_key[0, N)
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (uint32_t i = tid; i < N / 2; i += BLOCK) {
+                const uint32_t lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint32_t a = s_key[lo], b = s_key[hi];
+                if ((a > b) == up) {
+                    s_key[lo] = b;
+                    s_key[hi] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < S; k += BLOCK) P->bf_js[k] = (uint16_t)(4095u - (s_key[k] & 4095u));
+}
+
 __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint32_t algo,
                                              uint32_t q_, uint32_t hbits, Params *P,
-                                             uint32_t *s_tab, uint32_t *s_bad)
+                                             uint32_t *s_tab, uint32_t *s_bad, uint32_t *s_key)
 {
     const int tid = threadIdx.x;
     if (algo == ALGO_SHIFT_AND) {
@@ -520,6 +673,8 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
             uint32_t v = (k == hl) ? 0u : s_tab[k];
             P->shift[k] = (uint8_t)(v > 255u ? 255u : v);
         }
+    } else if (algo == ALGO_BLOCK && s_key) {
+        build_block_tables(pp, m, P, s_tab, s_key, s_bad);
     }
 
     // Smallest period of p among 1..PERIOD_MAX: d is a period iff p[i] == p[i+d]

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <hip/hip_runtime.h>
 
+struct sm_opts;  // include/sm.h
+
 namespace sm {
 
 // Scan algorithms (values match SM_ALGO_* in include/sm.h).
@@ -14,7 +16,9 @@ enum Algo : int32_t {
     ALGO_BNDM = 2,       // bit-parallel backward factor automaton, m <= 64 (Fig. 3, BNDM)
     ALGO_SBNDM = 3,      // BNDM without prefix tracking, m <= 64 (Fig. 3, SBNDM)
     ALGO_HASHQ = 4,      // hashed q-gram skip filter + verification, any m >= q (Fig. 1, HASHq)
-    ALGO_COUNT_ = 5
+    ALGO_BLOCK = 5,      // 16-byte block fingerprint filter, BF_MIN_M <= m <= BF_MAX_M (after
+                         // SSEF, Fig. 1): reads one block per m - 15 text bytes
+    ALGO_COUNT_ = 6
 };
 
 constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
@@ -24,6 +28,9 @@ constexpr int H_MIN = 8;           // hash table bits range
 constexpr int H_MAX = 12;
 constexpr int PREP_INLINE = 3072;  // pattern bytes carried in the prep kernel's arguments
 constexpr uint32_t PERIOD_MAX = 64;  // periods searched by the prep kernel
+constexpr int BF_H = 12;             // block filter: bucket bits of the block hash
+constexpr int BF_MIN_M = 32;         // block filter pattern lengths
+constexpr int BF_MAX_M = 4096;
 
 constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass
 constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
@@ -41,13 +48,19 @@ struct alignas(16) Params {
     uint32_t pad0;
     uint64_t mask[256];          // Shift-And (complemented form) or BNDM masks
     uint8_t shift[1 << H_MAX];   // Hash-q shift per hash bucket (capped at 255)
+    // Block filter: the alignments j < m - 15 of the pattern's 16-byte blocks
+    // p[j, j + 16), bucketed by the block's hash, each bucket in descending j;
+    // bucket h holds bf_js[bf_start[h] .. bf_start[h + 1]).
+    uint16_t bf_start[(1 << BF_H) + 1];
+    uint16_t bf_js[BF_MAX_M - 15];
 };
 static_assert(sizeof(Params) % 16 == 0, "Params must keep the pattern 16-byte aligned");
 
 // Host-side plan: everything the launches need that is known on the host.
 struct Plan {
     int32_t algo;
-    int32_t lane_bytes;   // L: candidate starts per lane; tile = BLOCK * L starts
+    int32_t lane_bytes;   // L: candidate starts per lane; tile = BLOCK * L starts (block
+                          // filter: m - 15, the starts of one sampled block)
     int32_t q;            // Hash-q gram length
     int32_t hbits;        // Hash-q table bits
     int32_t tiles_per_wg; // consecutive tiles per workgroup (count kernel)
@@ -251,8 +264,10 @@ int corpus_find_window_async(sm_corpus *c, const uint8_t *pat, uint64_t m, int64
                              uint64_t first, uint64_t cap, uint64_t *d_count, void *d_work,
                              uint64_t work_bytes, hipStream_t stream);
 
-// Plan one pattern as the single-pattern path would (sigma from the corpus).
+// Plan one pattern as the single-pattern path would (sigma from the corpus), or
+// with explicit options.
 int plan_pattern(const uint8_t *pat, uint64_t m, int sigma, Plan &p);
+int plan_pattern_opts(const uint8_t *pat, uint64_t m, const ::sm_opts *o, Plan &p);
 const char *sm_set_error(int status, const char *msg);
 
 // Kernel launchers (sm_kernels.hip). All are asynchronous on `stream` and

@@ -55,6 +55,7 @@ struct ScanArgs {
     const uint8_t *pat;
     uint32_t m, q, hbits, tiles_per_wg;
     uint32_t slots;       // find: lanes keep their first hits while counting
+    uint32_t bs;          // block filter: starts per sampled block (m - 15)
     uint64_t ntiles;
     uint64_t *total;      // count mode: occurrences are added here
     uint32_t *tile_cnt;   // find mode: per-tile counts (count kernel writes, emit reads)
@@ -509,6 +510,94 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block filter kernels. A tile is 256 sampled blocks, one per lane: lane l of
+// tile t tests block b = 256 t + l at x = b S + S - 1 for the starts [b S, b S + S).
+// Only the sampled blocks are read from the text (plus the bytes of candidates).
+// ---------------------------------------------------------------------------
+struct BlockLane {
+    uint64_t x, ilo, ihi;  // the block, and the starts it owns (ilo > ihi: none)
+};
+
+__device__ __forceinline__ BlockLane block_lane(const ScanArgs &a, uint64_t t)
+{
+    BlockLane L;
+    const uint64_t S = a.bs, b = t * BLOCK + threadIdx.x;
+    L.ilo = b * S;
+    L.x = L.ilo + S - 1;
+    const uint64_t last = a.n - a.m;  // n >= m
+    L.ihi = L.x < last ? L.x : last;
+    return L;
+}
+
+// Count pass (count and find modes alike: the emit pass tests the tiles with hits
+// again). PREFETCH: the next tile's blocks are loaded while this tile's are tested.
+template <bool PREFETCH>
+__global__ __launch_bounds__(BLOCK) void block_count_kernel(ScanArgs a)
+{
+    __shared__ uint32_t s_w[BLOCK / 64];
+    const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+    const uint64_t t_begin = wg * a.tiles_per_wg;
+    uint64_t t_end = t_begin + a.tiles_per_wg;
+    if (t_end > a.ntiles) t_end = a.ntiles;
+    const uint32_t period = a.prm->period, period_lb = a.prm->period_lb;
+    BlockLane L = block_lane(a, t_begin);
+    uint4 blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+    for (uint64_t t = t_begin; t < t_end; t++) {
+        if (!PREFETCH && t != t_begin) {
+            L = block_lane(a, t);
+            blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+        }
+        const BlockLane cur = L;
+        const uint4 cb = blk;
+        if (PREFETCH && t + 1 < t_end) {
+            L = block_lane(a, t + 1);
+            blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+        }
+        NoEmit ne;
+        const uint32_t c = cur.ilo <= cur.ihi
+                               ? lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, cur.x,
+                                                   cur.ilo, cur.ihi, cb, 0, ne)
+                               : 0u;
+        uint32_t tot;
+        block_excl_scan(c, s_w, tot);
+        if (threadIdx.x == 0) a.tile_cnt[t] = tot;
+    }
+}
+
+// Emit pass: every listed tile is tested again, once to count each lane's hits
+// (their workgroup scan places the lanes) and once to write them.
+__global__ __launch_bounds__(BLOCK) void block_emit_kernel(ScanArgs a)
+{
+    __shared__ uint32_t s_w[BLOCK / 64];
+    const uint64_t nl = *a.nlist;
+    const uint32_t period = a.prm->period, period_lb = a.prm->period_lb;
+    const uint64_t T = (uint64_t)BLOCK * a.bs;
+    for (uint64_t e = blockIdx.x; e < nl; e += gridDim.x) {  // uniform
+        const TileEntry te = a.list[e];
+        if (te.off >= a.lo + a.cap || te.off + te.cnt <= a.lo) continue;  // outside the window
+        const BlockLane L = block_lane(a, te.t);
+        const bool any = L.ilo <= L.ihi;
+        const uint4 blk = any ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+        NoEmit ne;
+        const uint32_t c = any ? lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x,
+                                                   L.ilo, L.ihi, blk, 0, ne)
+                               : 0u;
+        uint32_t tot;
+        const uint32_t before = block_excl_scan(c, s_w, tot);
+        if (c) {
+            PosEmit pe;
+            pe.out = a.out;
+            pe.idx = te.off + before;
+            pe.lo = a.lo;
+            pe.span = a.cap;
+            pe.base = te.t * T;
+            lane_block<true>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ilo, L.ihi, blk,
+                             te.t * T, pe);
+        }
+    }
+}
+
 // LDS writes of one lane are seen by the other lanes of its wave after this
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -795,7 +884,8 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
     const uint8_t *pp = a.inline_len ? s_pat : a.pat;
 
     __shared__ uint32_t s_bad[PERIOD_MAX + 1];
-    build_tables(pp, m, a.algo, a.q, a.hbits, P, s_tab, s_bad);
+    __shared__ uint32_t s_key[BF_MAX_M];
+    build_tables(pp, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
 }
 
 __global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }
@@ -905,6 +995,7 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
     a.hbits = (uint32_t)plan.hbits;
     a.tiles_per_wg = (uint32_t)plan.tiles_per_wg;
     a.slots = (uint32_t)plan.slots;
+    a.bs = plan.algo == ALGO_BLOCK ? (uint32_t)plan.lane_bytes : 0u;
     a.ntiles = ntiles;
     return a;
 }
@@ -953,6 +1044,13 @@ static hipError_t launch_tile_scan(const FindWs &w, uint64_t *d_total, bool find
     return hipGetLastError();
 }
 
+static hipError_t launch_block_count(const ScanArgs &a, uint32_t grid, hipStream_t st)
+{
+    if (a.tiles_per_wg > 1) hipLaunchKernelGGL(block_count_kernel<true>, dim3(grid), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL(block_count_kernel<false>, dim3(grid), dim3(BLOCK), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, const Params *d_params,
                         const uint8_t *d_pat, const FindWs &w, uint64_t *d_total, hipStream_t stream,
                         hipEvent_t after_count)
@@ -963,7 +1061,8 @@ hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, con
     a.tile_cnt = w.tile_cnt;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
-    hipError_t e = launch_any<K_COUNT>(plan, a, g, stream);
+    hipError_t e = plan.algo == ALGO_BLOCK ? launch_block_count(a, g, stream)
+                                           : launch_any<K_COUNT>(plan, a, g, stream);
     if (e != hipSuccess) return e;
     if (after_count && (e = hipEventRecord(after_count, stream)) != hipSuccess) return e;
     return launch_tile_scan(w, d_total, false, stream);
@@ -987,7 +1086,8 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     if (plan.algo == ALGO_SHIFT_AND && plan.lane_bytes >= 32) a.bits = w.bits;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
-    hipError_t e = launch_any<K_FIND_COUNT>(plan, a, g, stream);
+    const bool block = plan.algo == ALGO_BLOCK;
+    hipError_t e = block ? launch_block_count(a, g, stream) : launch_any<K_FIND_COUNT>(plan, a, g, stream);
     if (e != hipSuccess) return e;
     if (after_count) {
         e = hipEventRecord(after_count, stream);
@@ -996,6 +1096,10 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     if ((e = launch_tile_scan(w, d_total, true, stream)) != hipSuccess) return e;
     if (cap == 0) return hipSuccess;
     uint64_t eg = w.ntiles < EMIT_GRID ? w.ntiles : EMIT_GRID;
+    if (block) {
+        hipLaunchKernelGGL(block_emit_kernel, dim3((uint32_t)eg), dim3(BLOCK), 0, stream, a);
+        return hipGetLastError();
+    }
     return launch_any<K_EMIT>(plan, a, (uint32_t)eg, stream);
 }
 

@@ -2,8 +2,8 @@
 
 For each alphabet-size bucket (representative sigma in 2, 4, 16, 64, 256) and a
 grid of pattern lengths, every applicable configuration -- algorithm (Shift-And,
-BNDM, SBNDM, Hash-q with its gram length q), starts per lane and tiles per
-workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
+BNDM, SBNDM, Hash-q with its gram length q, the block filter), starts per lane
+and tiles per workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
 benchmark's seed 1) with substring patterns, as whole find_all calls. The
 fastest configuration of each cell becomes a table entry. The paper's own
 summary (Section 4) says the best algorithm depends on exactly these two
@@ -48,6 +48,9 @@ def candidates(m: int, sigma: int):
         for L in (64, 128):
             for tpw in (1, 2):
                 out.append(dict(algo=4, lane_bytes=L, q=q, tiles_per_wg=tpw))
+    if 32 <= m <= 4096:  # block filter: its tile is 256 sampled blocks
+        for tpw in (1, 2, 4, 8):
+            out.append(dict(algo=5, lane_bytes=0, q=0, tiles_per_wg=tpw))
     return out
 
 

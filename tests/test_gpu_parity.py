@@ -24,8 +24,8 @@ def sm():
 
 
 DEV = "cuda:0"
-BP_ALGOS = (1, 2, 3)       # Shift-And, BNDM, SBNDM (m <= 64)
-ALL_ALGOS = (1, 2, 3, 4)   # + Hash-q
+BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (m <= 64)
+ALL_ALGOS = (1, 2, 3, 4, 5)   # + Hash-q, block filter (32 <= m <= 4096)
 
 
 def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0):
@@ -50,6 +50,8 @@ def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0
 def applicable(algo, m, q=0):
     if algo in BP_ALGOS:
         return m <= 64
+    if algo == 5:
+        return 32 <= m <= 4096
     return m >= max(q, 1)
 
 
@@ -117,6 +119,52 @@ def test_sbndm_every_q(sm):
         gpu_find(sm, t_dev, b"abcdefgh", algo=3, lane=64, q=3)
 
 
+def test_block_filter(sm):
+    """The block filter reads one 16-byte block per m - 15 text bytes: every length
+    from its smallest (32: a block per 17 starts) to its largest (4096), pattern
+    lengths around block boundaries, small and large alphabets, planted
+    occurrences at both text ends, periodic patterns (the period rule), patterns
+    whose blocks recur in the text without an occurrence, tiles per workgroup, and
+    truncation. Out-of-range lengths are rejected."""
+    rng = np.random.default_rng(21)
+    for sigma in (2, 4, 256):
+        n = 300_001
+        t_np = dg.uniform_text(n, sigma, seed=40 + sigma)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for i, m in enumerate((32, 33, 47, 48, 100, 255, 256, 257, 1000, 1024, 4096)):
+            pats = [dg.substring_pattern(t_np, m, seed=41, idx=i)[0], bytes(t_np[:m]),
+                    bytes(t_np[n - m:]), bytes(rng.integers(0, sigma, m, dtype=np.uint8))]
+            for p in pats:
+                want = oracle.find_all(t_np, p)
+                for tpw in (1, 2, 3):
+                    got, tot = gpu_find(sm, t_dev, p, algo=5, tpw=tpw)
+                    assert tot == want.size and np.array_equal(got, want), (sigma, m, tpw)
+    # periodic texts and patterns: many candidates per block, dense occurrences
+    for per in (1, 2, 3, 7, 16, 17, 40, 64, 65):
+        base = bytes(rng.integers(0, 4, per, dtype=np.uint8))
+        t_np = np.frombuffer((base * (200_000 // per + 2))[:200_003], np.uint8).copy()
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for m in (32, 64, 100, 513):
+            p = bytes(t_np[5:5 + m])
+            want = oracle.find_all(t_np, p)
+            got, tot = gpu_find(sm, t_dev, p, algo=5, tpw=2)
+            assert tot == want.size and np.array_equal(got, want), (per, m)
+            for cap in (1, want.size // 2):
+                got, tot = gpu_find(sm, t_dev, p, algo=5, cap=cap)
+                assert np.array_equal(got, want[:cap]), (per, m, cap)
+    # a run of one byte with a different last byte: every block matches, no occurrence
+    t_np = np.full(100_000, 7, np.uint8)
+    t_np[77_777] = 9
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for m in (32, 200, 3000):
+        p = bytes([7] * (m - 1) + [9])
+        got, tot = gpu_find(sm, t_dev, p, algo=5)
+        assert tot == 1 and got.tolist() == [77_777 - m + 1], m
+    for m in (31, 4097):
+        with pytest.raises(sm.SmError):
+            gpu_find(sm, t_dev, bytes(m), algo=5)
+
+
 def test_tiles_per_workgroup_and_lanes_deterministic(sm):
     t_np = dg.uniform_text(300_001, 4, seed=8)
     t_dev = torch.from_numpy(t_np).to(DEV)
@@ -166,6 +214,8 @@ def test_truncation(sm):
     want = oracle.find_all(t_np, p)
     assert want.size > 1000
     for a in ALL_ALGOS:
+        if not applicable(a, len(p)):
+            continue
         for cap in (0, 1, 77, want.size - 1, want.size, want.size + 5):
             got, tot = gpu_find(sm, t_dev, p, algo=a, cap=cap)
             assert tot == want.size
@@ -237,7 +287,7 @@ def test_zero_bytes_at_text_end(sm):
 def test_m_equals_n_and_m_greater_than_n(sm):
     t_np = dg.uniform_text(64, 4, seed=2)
     t_dev = torch.from_numpy(t_np).to(DEV)
-    for a in ALL_ALGOS:
+    for a in ALL_ALGOS:  # m = n = 64
         got, tot = gpu_find(sm, t_dev, bytes(t_np), algo=a)
         assert got.tolist() == [0]
         got, tot = gpu_find(sm, t_dev, bytes(t_np[:63]) + b"\xff", algo=a)
@@ -256,6 +306,8 @@ def test_config1_exact(sm):
     got = sm.find_all(t_dev, p).cpu().numpy()
     assert np.array_equal(got, want)
     for a in ALL_ALGOS:
+        if not applicable(a, len(p)):
+            continue
         g2, _ = gpu_find(sm, t_dev, p, algo=a)
         assert np.array_equal(g2, want), a
 
@@ -303,7 +355,8 @@ def test_workspace_reuse_across_calls(sm):
         m = int(rng.integers(1, 1200)) if i % 3 else int(rng.integers(1, 20))
         if m > n:
             m = n
-        algo = int(rng.choice([1, 2, 3, 4])) if m <= 64 else 4
+        algo = int(rng.choice([1, 2, 3, 4] + ([5] if 32 <= m <= 4096 else []))) if m <= 64 else \
+            int(rng.choice([4, 5])) if m <= 4096 else 4
         o = sm.opts(algo=algo, lane_bytes=int(rng.choice([16, 64])))
         need = sm.workspace_size(n, m, o)
         work = big[:need + int(rng.integers(0, 1 << 16)) // 256 * 256]
