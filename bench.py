@@ -181,7 +181,7 @@ def main():
     calls_n = max(prof["calls"], 1)
     full_n = max(prof["calls"] - prof["sampled_calls"], 1)
     avg_count_s = (prof["count_ms"] - prof["sampled_count_ms"]) / full_n / 1e3
-    count_gbs = n / avg_count_s / 1e9
+    count_gbs = n / avg_count_s / 1e9 if avg_count_s > 0 else 0.0
     sampled = None
     if prof["sampled_calls"]:
         avg_s = prof["sampled_count_ms"] / prof["sampled_calls"] / 1e3

@@ -333,14 +333,10 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
     // explicit lanes, else the smallest the planner could pick for this m (the
-    // block filter's tiles hold 256 (m - 15) starts)
+    // block filter's tiles of 256 (m - 15) starts are larger than any lanes' tiles)
     int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : min_auto_lane(m);
-    const bool block = opts && opts->algo == ALGO_BLOCK;
-    if (block) lb = (int)(m - 15);
-    else if ((!opts || opts->algo == ALGO_AUTO) && m >= (uint64_t)BF_MIN_M && m <= (uint64_t)BF_MAX_M &&
-             (int)(m - 15) < lb)
+    if (opts && opts->algo == ALGO_BLOCK && m >= (uint64_t)BF_MIN_M && m <= (uint64_t)BF_MAX_M)
         lb = (int)(m - 15);
-    if (lb < 1) lb = 1;
     Plan p;
     p.lane_bytes = lb;
     return ws_layout(n, m, tile_starts(p)).need;

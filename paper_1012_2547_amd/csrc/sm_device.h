@@ -435,48 +435,66 @@ __device__ __forceinline__ uint4 load16_chunks(const uint8_t *p)
     return o;
 }
 
-// t[g + off, g + off + len) == p[off, off + len), compared in 16-byte pieces from
-// the end (the window [g, g + m) lies inside the text; p is padded by 16 bytes)
-__device__ __forceinline__ bool bf_equal(const uint8_t *text, uint64_t g, const uint8_t *pat,
-                                         uint32_t m, uint32_t off, uint32_t len)
-{
-    const uint8_t *tlast = text + g + m - 1, *plast = pat + m + 15;
-    for (uint32_t e = len; e > 0;) {
-        const uint32_t b = e >= 16 ? e - 16 : 0;
-        if (diff16(load16(text + g + off + b, tlast), load16(pat + off + b, plast), e - b)) return false;
-        e = b;
-    }
-    return true;
-}
-
 // Occurrences among the starts [ilo, ihi] of sampled block x (ihi <= x, x - ilo < S,
-// x + 16 <= n); blk = the block's 16 bytes. Candidates come in ascending order, so
-// an occurrence v already found rules out starts closer than the pattern's smallest
-// period, and one exactly a period away needs only its last period bytes.
+// x + 16 <= n); blk = the block's 16 bytes. Wave-cooperative: all 64 lanes of the
+// wave call it (lanes without starts pass active = false). A lane walks its
+// bucket in descending j, i.e. ascending start i = x - j, and keeps the candidates
+// whose p[j, j + 16) equals the block; the wave verifies them 1024 bytes per round
+// trip. An occurrence v already found rules out starts closer than the pattern's
+// smallest period, and one exactly a period away needs only its last period bytes.
 template <bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_block(const uint8_t *text, const uint8_t *pat, uint32_t m,
                                                const Params *prm, uint32_t period, uint32_t period_lb,
-                                               uint64_t x, uint64_t ilo, uint64_t ihi, uint4 blk,
+                                               uint64_t x, uint64_t ihi, uint4 blk, bool active,
                                                uint64_t base, E &o)
 {
-    const uint32_t h = bf_hash(blk.x, blk.y, blk.z, blk.w);
-    const uint32_t k0 = prm->bf_start[h], k1 = prm->bf_start[h + 1];
+    uint32_t k = 0, k1 = 0;
+    if (active) {
+        const uint32_t h = bf_hash(blk.x, blk.y, blk.z, blk.w);
+        k = prm->bf_start[h];
+        k1 = prm->bf_start[h + 1];
+    }
+    active = active && k < k1;
     uint32_t cnt = 0;
     bool have = false;
     uint64_t v = 0;
-    for (uint32_t k = k0; k < k1; k++) {
-        const uint32_t j = prm->bf_js[k];
-        const uint64_t i = x - j;  // >= ilo since j < S
-        if (i > ihi) break;        // j descending: the remaining starts are larger still
-        const uint4 pb = load16(pat + j, pat + m + 15);
-        if ((pb.x ^ blk.x) | (pb.y ^ blk.y) | (pb.z ^ blk.z) | (pb.w ^ blk.w)) continue;
-        if (have && i - v < period_lb) continue;
-        bool ok;
-        if (have && period && i - v == period)
-            ok = bf_equal(text, i, pat, m, m - period, period);
-        else
-            ok = bf_equal(text, i, pat, m, j + 16, m - j - 16) && bf_equal(text, i, pat, m, 0, j);
-        if (ok) {
+    while (__ballot(active)) {
+        // 1. this lane's next candidate
+        bool cand = false;
+        uint64_t i = 0;
+        while (active && !cand) {
+            const uint32_t j = prm->bf_js[k++];
+            i = x - j;  // >= ilo since j < S
+            if (i > ihi) {
+                active = false;  // j descending: the remaining starts are larger still
+                break;
+            }
+            const uint4 pb = load16(pat + j, pat + m + 15);
+            cand = ((pb.x ^ blk.x) | (pb.y ^ blk.y) | (pb.z ^ blk.z) | (pb.w ^ blk.w)) == 0;
+            if (k >= k1) active = false;
+        }
+        // 2. the period rule, then a check by the lane (<= 16 bytes) or by the wave
+        bool hit = false, need_wave = false;
+        uint32_t voff = 0, vlen = m;
+        if (cand && !(have && i - v < period_lb)) {
+            if (have && period && i - v == period) {
+                voff = m - period;
+                vlen = period;
+            }
+            if (vlen <= 16) hit = verify_lane16(text, i, pat, m, voff, vlen);
+            else need_wave = true;
+        }
+        uint64_t pend = __ballot(need_wave);
+        while (pend) {
+            const int kl = __builtin_ctzll(pend);
+            pend &= pend - 1;
+            const uint64_t ki = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(i >> 32), kl, 64) << 32) |
+                                (uint32_t)__shfl((int)(uint32_t)i, kl, 64);
+            const uint32_t koff = (uint32_t)__shfl((int)voff, kl, 64), klen = (uint32_t)__shfl((int)vlen, kl, 64);
+            const bool ok = verify_wave(text, ki, pat, m, koff, klen);
+            if ((int)(threadIdx.x & 63) == kl) hit = ok;
+        }
+        if (hit) {
             have = true;
             v = i;
             if (WRITE) o.put((int)(i - base));
@@ -570,33 +588,38 @@ __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint
 // Tables of one pattern (masks, Hash-q shift table and sh1, period bounds) into
 // *P, by one whole workgroup of BLOCK threads. pp: the pattern (global or LDS);
 // s_tab: LDS scratch of 1 << H_MAX words; s_bad: LDS scratch of PERIOD_MAX + 1.
-// Block filter tables: hash every alignment j < S = m - 15 (counts per bucket in
-// s_tab, then their exclusive scan is bf_start), and sort the keys (hash, 4095 - j)
-// bitonically in s_key (4096 entries): bf_js lists each bucket in descending j.
+// LDS the block filter's table build takes (32-bit words)
+constexpr int BF_BUILD_LDS = 2 * BF_MAX_M + 64;
+
+// Block filter tables: the hash of every alignment j < S = m - 15, counts per
+// bucket, their exclusive scan (bf_start); then each j goes to its bucket in any
+// order (LDS atomics) and every bucket is sorted in descending j: buckets of at
+// most 32 by one thread each (insertion sort), larger ones (periodic or
+// repetitive patterns) one after another by the whole workgroup (bitonic sort).
+// s_tab: 1 << BF_H words; s: BF_BUILD_LDS words (hashes, then sort scratch | the
+// bucketed j | the list of large buckets).
 __device__ __forceinline__ void build_block_tables(const uint8_t *pp, uint32_t m, Params *P,
-                                                   uint32_t *s_tab, uint32_t *s_key, uint32_t *s_w)
+                                                   uint32_t *s_tab, uint32_t *s, uint32_t *s_w)
 {
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const uint32_t S = m - 15, nb = 1u << BF_H;
-    uint32_t N = 16;
-    while (N < S) N <<= 1;
+    uint32_t *s_h = s, *s_js = s + BF_MAX_M, *s_big = s + 2 * BF_MAX_M;
+    constexpr uint32_t SMALL = 32, BIG_MAX = 64;  // buckets > 32 (at most 123) are listed 64 at a time
     for (uint32_t k = tid; k < nb; k += BLOCK) s_tab[k] = 0;
     __syncthreads();
-    for (uint32_t j = tid; j < N; j += BLOCK) {
-        uint32_t key = 0xFFFFFFFFu;
-        if (j < S) {
-            uint32_t w[4] = {0, 0, 0, 0};
-            for (uint32_t k = 0; k < 16; k++) w[k >> 2] |= (uint32_t)pp[j + k] << (8 * (k & 3));
-            const uint32_t h = bf_hash(w[0], w[1], w[2], w[3]);
-            atomicAdd(&s_tab[h], 1u);
-            key = (h << 12) | (4095u - j);
-        }
-        s_key[j] = key;
+    for (uint32_t j = tid; j < S; j += BLOCK) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t k = 0; k < 16; k++) w[k >> 2] |= (uint32_t)pp[j + k] << (8 * (k & 3));
+        const uint32_t h = bf_hash(w[0], w[1], w[2], w[3]);
+        s_h[j] = h;
+        atomicAdd(&s_tab[h], 1u);
     }
     __syncthreads();
-    // exclusive scan of the nb counts, 16 per thread
+    // exclusive scan of the nb counts, 16 per thread; s_tab becomes the cursors
+    constexpr uint32_t PER = (1u << BF_H) / BLOCK;
+    uint32_t bstart[PER];
     {
-        constexpr uint32_t PER = (1u << BF_H) / BLOCK;
         uint32_t c[PER], sum = 0;
 #pragma unroll
         for (uint32_t k = 0; k < PER; k++) {
@@ -604,36 +627,87 @@ __device__ __forceinline__ void build_block_tables(const uint8_t *pp, uint32_t m
             sum += c[k];
         }
         uint32_t tot;
-        uint32_t run = block_excl_scan(sum, s_w, tot);
+        uint32_t run = block_excl_scan(sum, s_w, tot);  // ends with a barrier
 #pragma unroll
         for (uint32_t k = 0; k < PER; k++) {
+            bstart[k] = run;
             P->bf_start[tid * PER + k] = (uint16_t)run;
+            s_tab[tid * PER + k] = run;
             run += c[k];
         }
         if (tid == 0) P->bf_start[nb] = (uint16_t)S;
     }
-    // bitonic sort of s_key[0, N)
-    for (uint32_t size = 2; size <= N; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (uint32_t i = tid; i < N / 2; i += BLOCK) {
-                const uint32_t lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint32_t a = s_key[lo], b = s_key[hi];
-                if ((a > b) == up) {
-                    s_key[lo] = b;
-                    s_key[hi] = a;
+    __syncthreads();
+    for (uint32_t j = tid; j < S; j += BLOCK) s_js[atomicAdd(&s_tab[s_h[j]], 1u)] = j;
+    __syncthreads();
+    // s_tab[h] is now the end of bucket h; small buckets: this thread's 16
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        const uint32_t b0 = bstart[k], b1 = s_tab[tid * PER + k];
+        if (b1 - b0 <= SMALL) {
+            for (uint32_t x = b0 + 1; x < b1; x++) {  // insertion sort, descending
+                const uint32_t v = s_js[x];
+                uint32_t y = x;
+                while (y > b0 && s_js[y - 1] < v) {
+                    s_js[y] = s_js[y - 1];
+                    y--;
                 }
+                s_js[y] = v;
             }
         }
     }
+    // large buckets, in passes of at most BIG_MAX listed ones
+    for (uint32_t pass_lo = 0;; pass_lo += BIG_MAX) {  // uniform
+        __syncthreads();
+        // list the large buckets with rank in [pass_lo, pass_lo + BIG_MAX) in bucket order
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) mine += (s_tab[tid * PER + k] - bstart[k]) > SMALL;
+        uint32_t tot;
+        uint32_t rank = block_excl_scan(mine, s_w, tot);
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) {
+            if ((s_tab[tid * PER + k] - bstart[k]) > SMALL) {
+                if (rank >= pass_lo && rank < pass_lo + BIG_MAX) s_big[rank - pass_lo] = tid * PER + k;
+                rank++;
+            }
+        }
+        __syncthreads();
+        const uint32_t nlist = tot > pass_lo ? (tot - pass_lo < BIG_MAX ? tot - pass_lo : BIG_MAX) : 0;
+        for (uint32_t q = 0; q < nlist; q++) {
+            __syncthreads();  // the previous bucket's copy back is done with the scratch
+            const uint32_t h = s_big[q];
+            const uint32_t b0 = h ? s_tab[h - 1] : 0, b1 = s_tab[h], B = b1 - b0;
+            uint32_t N = 64;
+            while (N < B) N <<= 1;
+            // scratch: j + 1, zero padding; bitonic sort descending
+            for (uint32_t x = tid; x < N; x += BLOCK) s_h[x] = x < B ? s_js[b0 + x] + 1 : 0;
+            for (uint32_t size = 2; size <= N; size <<= 1) {
+                for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                    __syncthreads();
+                    for (uint32_t i = tid; i < N / 2; i += BLOCK) {
+                        const uint32_t lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                        const bool down = (lo & size) == 0;
+                        const uint32_t a = s_h[lo], b = s_h[hi];
+                        if ((a < b) == down) {
+                            s_h[lo] = b;
+                            s_h[hi] = a;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t x = tid; x < B; x += BLOCK) s_js[b0 + x] = s_h[x] - 1;
+        }
+        if (tot <= pass_lo + BIG_MAX) break;
+    }
     __syncthreads();
-    for (uint32_t k = tid; k < S; k += BLOCK) P->bf_js[k] = (uint16_t)(4095u - (s_key[k] & 4095u));
+    for (uint32_t k = tid; k < S; k += BLOCK) P->bf_js[k] = (uint16_t)s_js[k];
 }
 
 __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint32_t algo,
                                              uint32_t q_, uint32_t hbits, Params *P,
-                                             uint32_t *s_tab, uint32_t *s_bad, uint32_t *s_key)
+                                             uint32_t *s_tab, uint32_t *s_bad, uint32_t *s_key)  // s_key: BF_BUILD_LDS
 {
     const int tid = threadIdx.x;
     if (algo == ALGO_SHIFT_AND) {

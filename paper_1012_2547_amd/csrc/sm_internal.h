@@ -29,7 +29,8 @@ constexpr int H_MAX = 12;
 constexpr int PREP_INLINE = 3072;  // pattern bytes carried in the prep kernel's arguments
 constexpr uint32_t PERIOD_MAX = 64;  // periods searched by the prep kernel
 constexpr int BF_H = 12;             // block filter: bucket bits of the block hash
-constexpr int BF_MIN_M = 32;         // block filter pattern lengths
+constexpr int BF_MIN_M = 144;        // block filter pattern lengths (a tile of 256 blocks then
+                                     // holds more starts than one of the widest lanes, 128)
 constexpr int BF_MAX_M = 4096;
 
 constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass

@@ -555,10 +555,8 @@ __global__ __launch_bounds__(BLOCK) void block_count_kernel(ScanArgs a)
             blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
         }
         NoEmit ne;
-        const uint32_t c = cur.ilo <= cur.ihi
-                               ? lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, cur.x,
-                                                   cur.ilo, cur.ihi, cb, 0, ne)
-                               : 0u;
+        const uint32_t c = lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, cur.x,
+                                             cur.ihi, cb, cur.ilo <= cur.ihi, 0, ne);
         uint32_t tot;
         block_excl_scan(c, s_w, tot);
         if (threadIdx.x == 0) a.tile_cnt[t] = tot;
@@ -580,21 +578,18 @@ __global__ __launch_bounds__(BLOCK) void block_emit_kernel(ScanArgs a)
         const bool any = L.ilo <= L.ihi;
         const uint4 blk = any ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
         NoEmit ne;
-        const uint32_t c = any ? lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x,
-                                                   L.ilo, L.ihi, blk, 0, ne)
-                               : 0u;
+        const uint32_t c = lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ihi,
+                                             blk, any, 0, ne);
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, s_w, tot);
-        if (c) {
-            PosEmit pe;
-            pe.out = a.out;
-            pe.idx = te.off + before;
-            pe.lo = a.lo;
-            pe.span = a.cap;
-            pe.base = te.t * T;
-            lane_block<true>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ilo, L.ihi, blk,
-                             te.t * T, pe);
-        }
+        PosEmit pe;
+        pe.out = a.out;
+        pe.idx = te.off + before;
+        pe.lo = a.lo;
+        pe.span = a.cap;
+        pe.base = te.t * T;
+        lane_block<true>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ihi, blk, c != 0,
+                         te.t * T, pe);
     }
 }
 
@@ -852,25 +847,41 @@ struct PrepArgs {
     uint64_t *zero;    // set to 0 (the running total), may be null
     uint32_t m, algo, q, hbits;
     uint32_t inline_len;  // pattern bytes carried below (0: already in pat)
-    uint8_t inline_pat[PREP_INLINE];
+    alignas(4) uint8_t inline_pat[PREP_INLINE];
 };
 
 __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
 {
     __shared__ uint32_t s_tab[1 << H_MAX];
-    __shared__ uint8_t s_pat[PREP_INLINE];
+    __shared__ __align__(16) uint8_t s_pat[PREP_INLINE];
     const int tid = threadIdx.x;
     const uint32_t m = a.m;
     Params *P = a.prm;
 
     if (a.inline_len) {
-        for (uint32_t k = tid; k < a.inline_len; k += BLOCK) {
-            a.pat[k] = a.inline_pat[k];
-            s_pat[k] = a.inline_pat[k];
+        // whole words (the argument block is word aligned), every load issued before
+        // any store: at most PREP_INLINE / 4 / BLOCK words per thread; the words past
+        // the pattern are zeroed, and the copy is zero padded to a multiple of 16
+        constexpr int WPT = PREP_INLINE / 4 / BLOCK;
+        static_assert(PREP_INLINE % (4 * BLOCK) == 0, "whole words per thread");
+        const uint32_t nw = (a.inline_len + 3) / 4;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.inline_pat);
+        uint32_t w[WPT];
+#pragma unroll
+        for (int u = 0; u < WPT; u++) {
+            const uint32_t k = tid + BLOCK * u;
+            w[u] = k < nw ? src[k] : 0u;
+            if (k == nw - 1 && (a.inline_len & 3)) w[u] &= (1u << (8 * (a.inline_len & 3))) - 1u;
         }
-        // zero padding up to a multiple of 16
-        const uint32_t padded = (m + 15) & ~15u;
-        for (uint32_t k = m + tid; k < padded; k += BLOCK) a.pat[k] = 0;
+        uint32_t *s_pat32 = reinterpret_cast<uint32_t *>(s_pat);
+        uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.pat);  // 16-byte aligned in the workspace
+        const uint32_t padw = ((m + 15) & ~15u) / 4;
+#pragma unroll
+        for (int u = 0; u < WPT; u++) {
+            const uint32_t k = tid + BLOCK * u;
+            if (k < nw) s_pat32[k] = w[u];
+            if (k < padw) dst32[k] = w[u];
+        }
     }
     if (tid == 0) {
         P->m = m;
@@ -881,11 +892,12 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
     }
     __syncthreads();
     // pattern bytes: from LDS when inline, else from the workspace copy
-    const uint8_t *pp = a.inline_len ? s_pat : a.pat;
-
+    // (two calls: each reads its pattern copy through its own address space, LDS
+    // reads rather than generic ones for the inline copy)
     __shared__ uint32_t s_bad[PERIOD_MAX + 1];
-    __shared__ uint32_t s_key[BF_MAX_M];
-    build_tables(pp, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
+    __shared__ __align__(16) uint32_t s_key[BF_BUILD_LDS];
+    if (a.inline_len) build_tables(s_pat, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
+    else build_tables(a.pat, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
 }
 
 __global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }

@@ -48,7 +48,7 @@ def candidates(m: int, sigma: int):
         for L in (64, 128):
             for tpw in (1, 2):
                 out.append(dict(algo=4, lane_bytes=L, q=q, tiles_per_wg=tpw))
-    if 32 <= m <= 4096:  # block filter: its tile is 256 sampled blocks
+    if 144 <= m <= 4096:  # block filter: its tile is 256 sampled blocks
         for tpw in (1, 2, 4, 8):
             out.append(dict(algo=5, lane_bytes=0, q=0, tiles_per_wg=tpw))
     return out

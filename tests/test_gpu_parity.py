@@ -25,7 +25,7 @@ def sm():
 
 DEV = "cuda:0"
 BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (m <= 64)
-ALL_ALGOS = (1, 2, 3, 4, 5)   # + Hash-q, block filter (32 <= m <= 4096)
+ALL_ALGOS = (1, 2, 3, 4, 5)   # + Hash-q, block filter (144 <= m <= 4096)
 
 
 def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0):
@@ -51,7 +51,7 @@ def applicable(algo, m, q=0):
     if algo in BP_ALGOS:
         return m <= 64
     if algo == 5:
-        return 32 <= m <= 4096
+        return 144 <= m <= 4096
     return m >= max(q, 1)
 
 
@@ -121,7 +121,7 @@ def test_sbndm_every_q(sm):
 
 def test_block_filter(sm):
     """The block filter reads one 16-byte block per m - 15 text bytes: every length
-    from its smallest (32: a block per 17 starts) to its largest (4096), pattern
+    from its smallest (144: a block per 129 starts) to its largest (4096), pattern
     lengths around block boundaries, small and large alphabets, planted
     occurrences at both text ends, periodic patterns (the period rule), patterns
     whose blocks recur in the text without an occurrence, tiles per workgroup, and
@@ -131,7 +131,7 @@ def test_block_filter(sm):
         n = 300_001
         t_np = dg.uniform_text(n, sigma, seed=40 + sigma)
         t_dev = torch.from_numpy(t_np).to(DEV)
-        for i, m in enumerate((32, 33, 47, 48, 100, 255, 256, 257, 1000, 1024, 4096)):
+        for i, m in enumerate((144, 145, 159, 160, 200, 255, 256, 257, 1000, 1024, 4096)):
             pats = [dg.substring_pattern(t_np, m, seed=41, idx=i)[0], bytes(t_np[:m]),
                     bytes(t_np[n - m:]), bytes(rng.integers(0, sigma, m, dtype=np.uint8))]
             for p in pats:
@@ -144,7 +144,7 @@ def test_block_filter(sm):
         base = bytes(rng.integers(0, 4, per, dtype=np.uint8))
         t_np = np.frombuffer((base * (200_000 // per + 2))[:200_003], np.uint8).copy()
         t_dev = torch.from_numpy(t_np).to(DEV)
-        for m in (32, 64, 100, 513):
+        for m in (144, 145, 300, 513):
             p = bytes(t_np[5:5 + m])
             want = oracle.find_all(t_np, p)
             got, tot = gpu_find(sm, t_dev, p, algo=5, tpw=2)
@@ -156,11 +156,11 @@ def test_block_filter(sm):
     t_np = np.full(100_000, 7, np.uint8)
     t_np[77_777] = 9
     t_dev = torch.from_numpy(t_np).to(DEV)
-    for m in (32, 200, 3000):
+    for m in (144, 200, 3000):
         p = bytes([7] * (m - 1) + [9])
         got, tot = gpu_find(sm, t_dev, p, algo=5)
         assert tot == 1 and got.tolist() == [77_777 - m + 1], m
-    for m in (31, 4097):
+    for m in (143, 4097):
         with pytest.raises(sm.SmError):
             gpu_find(sm, t_dev, bytes(m), algo=5)
 
@@ -288,12 +288,25 @@ def test_m_equals_n_and_m_greater_than_n(sm):
     t_np = dg.uniform_text(64, 4, seed=2)
     t_dev = torch.from_numpy(t_np).to(DEV)
     for a in ALL_ALGOS:  # m = n = 64
+        if not applicable(a, 64):
+            continue
         got, tot = gpu_find(sm, t_dev, bytes(t_np), algo=a)
         assert got.tolist() == [0]
         got, tot = gpu_find(sm, t_dev, bytes(t_np[:63]) + b"\xff", algo=a)
         assert tot == 0
     got, tot = gpu_find(sm, t_dev, bytes(65))
     assert tot == 0
+    t_np = dg.uniform_text(300, 4, seed=3)  # the block filter at m = n and m = n + 1
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    got, tot = gpu_find(sm, t_dev, bytes(t_np), algo=5)
+    assert got.tolist() == [0]
+    got, tot = gpu_find(sm, t_dev, bytes(t_np[:299]) + b"\xff", algo=5)
+    assert tot == 0
+    o = sm.opts(algo=5)
+    work = torch.empty(1 << 16, dtype=torch.uint8, device=DEV)
+    dc = torch.zeros(1, dtype=torch.int64, device=DEV)
+    sm.count_async(t_dev, bytes(t_np) + b"\x00", dc, work, o)
+    assert int(dc.item()) == 0
 
 
 def test_config1_exact(sm):
@@ -355,8 +368,8 @@ def test_workspace_reuse_across_calls(sm):
         m = int(rng.integers(1, 1200)) if i % 3 else int(rng.integers(1, 20))
         if m > n:
             m = n
-        algo = int(rng.choice([1, 2, 3, 4] + ([5] if 32 <= m <= 4096 else []))) if m <= 64 else \
-            int(rng.choice([4, 5])) if m <= 4096 else 4
+        algo = int(rng.choice([1, 2, 3, 4])) if m <= 64 else \
+            int(rng.choice([4, 5])) if 144 <= m <= 4096 else 4
         o = sm.opts(algo=algo, lane_bytes=int(rng.choice([16, 64])))
         need = sm.workspace_size(n, m, o)
         work = big[:need + int(rng.integers(0, 1 << 16)) // 256 * 256]
