@@ -103,10 +103,16 @@ def test_invalid_options(L):
 def test_planner_choices(L):
     import paper_1012_2547_amd as sm
     assert sm.plan_query(b"ab")["algo"] in ("shift_and", "bndm", "sbndm")
-    p = sm.plan_query(bytes(range(4)) * 64)   # m = 256 over 4 symbols
+    hq = sm.opts(algo=sm.ALGO_HASHQ)
+    p = sm.plan_query(bytes(range(4)) * 64, hq)   # m = 256 over 4 symbols
     assert p["algo"] == "hashq" and 2 <= p["q"] <= 16 and 8 <= p["hbits"] <= 13
-    p2 = sm.plan_query(bytes(range(256)) * 2)  # m = 512 over 256 symbols: short grams suffice
+    p2 = sm.plan_query(bytes(range(256)) * 2, hq)  # m = 512 over 256 symbols: short grams suffice
     assert p2["q"] < p["q"]
+    # long patterns: the block filter, one block per m - 15 starts; not on one symbol
+    b = sm.plan_query(bytes(range(4)) * 64)
+    assert b["algo"] == "block" and b["lane_bytes"] == 256 - 15
+    assert sm.plan_query(b"a" * 300)["algo"] != "block"
+    assert sm.plan_query(bytes(range(4)) * 25)["algo"] != "block"  # m = 100 < 144
     f = sm.plan_query(b"x" * 30, sm.opts(algo=sm.ALGO_BNDM, lane_bytes=32))
     assert f["algo"] == "bndm" and f["lane_bytes"] == 32
 
@@ -123,7 +129,7 @@ def test_tuning_table_roundtrip(L):
     import paper_1012_2547_amd as sm
     base = sm.tune_get()
     assert len(base) > 50
-    assert all(1 <= e["algo"] <= 4 and e["m_lo"] <= e["m_hi"] for e in base)
+    assert all(1 <= e["algo"] <= 5 and e["m_lo"] <= e["m_hi"] for e in base)
     # every (sigma, m) of the sweep grid is covered by some entry
     for s in (2, 4, 16, 64, 256):
         for m in (1, 2, 3, 5, 8, 63, 64, 65, 100, 1000, 5000):
@@ -146,7 +152,7 @@ def test_tuning_table_roundtrip(L):
 
 def test_sigma_estimate_from_pattern_steers_plan(L):
     import paper_1012_2547_amd as sm
-    # a 1000-byte pattern over 2 symbols plans long q-grams, over 256 symbols short ones
-    lo = sm.plan_query(bytes([0, 1]) * 500)
-    hi = sm.plan_query(bytes(range(256)) * 4)
+    # a 200-byte pattern over 2 symbols plans long q-grams, over 200 symbols short ones
+    lo = sm.plan_query(bytes([0, 1]) * 100)
+    hi = sm.plan_query(bytes(range(200)))
     assert lo["algo"] == hi["algo"] == "hashq" and lo["q"] > hi["q"]
