@@ -58,15 +58,18 @@ enum sm_algo {
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */
     SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
     SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
-    SM_ALGO_BLOCK = 5      /* 16-byte block fingerprint filter after SSEF (Fig. 1), 144 <= m <= 4096:
+    SM_ALGO_BLOCK = 5,     /* 16-byte block fingerprint filter after SSEF (Fig. 1), 144 <= m <= 4096:
                               one 16-byte block per m - 15 text bytes is read and looked up among
                               the pattern's blocks, candidates verified byte-exactly */
+    SM_ALGO_BRUTE = 6      /* brute force (Fig. 1, BF) over packed bytes, m <= 8: the four starts of a
+                              text word are compared with the pattern at once, byte-parallel */
 };
 
 /*
  * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
  * Options change speed only, never results. Invalid combinations (a bit-parallel
- * algorithm with m > 64, the block filter with m outside [144, 4096], q > m or
+ * algorithm with m > 64, the block filter with m outside [144, 4096], brute force with
+ * m > 8, q > m or
  * q > 16, lane_bytes not in {16,32,64,128}, hbits outside [8,12]) are SM_EINVAL.
  * lane_bytes, q and hbits do not apply to the block filter (its tile is the
  * starts of 256 sampled blocks).

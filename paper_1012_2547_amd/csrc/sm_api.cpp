@@ -200,6 +200,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
         return fail(SM_EINVAL, "hbits must be in [%d, %d]", H_MIN, H_MAX);
     if (o->tiles_per_wg < 0 || o->tiles_per_wg > 4096)
         return fail(SM_EINVAL, "tiles_per_wg must be in [1, 4096]");
+    if (o->algo == ALGO_BRUTE && m > (uint64_t)BRUTE_MAX_M)
+        return fail(SM_EINVAL, "brute force takes m <= %d (m = %llu)", BRUTE_MAX_M, (unsigned long long)m);
     if (o->algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M))
         return fail(SM_EINVAL, "the block filter needs %d <= m <= %d (m = %llu)", BF_MIN_M, BF_MAX_M,
                     (unsigned long long)m);
@@ -220,6 +222,7 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     // entries not applicable to this m
     if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && m > BP_MAX_M) algo = 0;
     if (algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M)) algo = 0;
+    if (algo == ALGO_BRUTE && m > (uint64_t)BRUTE_MAX_M) algo = 0;
     if (have && te.algo == ALGO_HASHQ && te.q && (uint64_t)te.q > m) algo = 0;
     // the block filter expects varied 16-byte blocks: not on a text of (nearly) one symbol
     if (algo == ALGO_BLOCK && sigma < 2) algo = 0;

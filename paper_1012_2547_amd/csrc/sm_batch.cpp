@@ -269,10 +269,10 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         Plan p;
         int r = plan_pattern(pats + pat_off[i], m, sigma, p);
         if (r) return r;
-        if (p.algo == ALGO_BLOCK) {  // single-pattern only: the batch takes Hash-q instead
-            sm_opts o;
+        if (p.algo == ALGO_BLOCK || p.algo == ALGO_BRUTE) {  // single-pattern only: the batch
+            sm_opts o;                                           // takes Hash-q or Shift-And
             memset(&o, 0, sizeof o);
-            o.algo = ALGO_HASHQ;
+            o.algo = p.algo == ALGO_BLOCK ? ALGO_HASHQ : ALGO_SHIFT_AND;
             o.sigma_hint = sigma;
             if ((r = plan_pattern_opts(pats + pat_off[i], m, &o, p))) return r;
         }

@@ -404,6 +404,61 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
     return true;
 }
 
+// Brute force (Fig. 1, BF) over packed bytes, m <= BRUTE_MAX_M. For the four
+// starts of a text word, word k of the text shifted by k bytes is compared with
+// p[k] replicated in all four bytes (pw[k]); a start matches when its byte is
+// zero in the OR of the m differences. The exact zero-byte test sets 0x80 in
+// each zero byte; a multiply gathers the four flags. Hits come as masks of the
+// 16 starts of an LDS unit, in ascending order, like Shift-And's.
+template <bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_brute(const uint4 *lds, const uint32_t *pw, int m, int li0,
+                                               int lo, int hi, E &o)
+{
+    const int u0 = (lo + li0) >> 4, u1 = (hi + li0) >> 4;
+    uint4 cur = lds[swz((uint32_t)u0)];
+    uint32_t cnt = 0;
+    for (int u = u0; u <= u1; u++) {
+        const uint4 nx = lds[swz((uint32_t)(u + 1))];
+        const uint32_t w[6] = {cur.x, cur.y, cur.z, cur.w, nx.x, nx.y};
+        uint32_t z[4];
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            uint32_t x = w[d] ^ pw[0];
+#pragma unroll
+            for (int k = 1; k < BRUTE_MAX_M; k++)
+                if (k < m) x |= alignbyte(w[d + (k >> 2) + 1], w[d + (k >> 2)], (uint32_t)(k & 3)) ^ pw[k];
+            z[d] = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+        }
+        if (z[0] | z[1] | z[2] | z[3]) {
+            uint32_t hits = 0;
+#pragma unroll
+            for (int d = 0; d < 4; d++) hits |= (((z[d] >> 7) * 0x10204080u) >> 28) << (4 * d);
+            // bit i <-> relative start base + i; keep the lane's starts [lo, hi]
+            const int base = 16 * u - li0;
+            int ilo = lo - base, ihi = hi - base;
+            ilo = ilo < 0 ? 0 : ilo;
+            ihi = ihi > 15 ? 15 : ihi;
+            hits &= ((2u << ihi) - 1u) & ~((1u << ilo) - 1u);
+            if (hits) {
+                if constexpr (takes_masks<E>::value) {
+                    o.put_mask(base - lo, hits);
+                    cnt += __builtin_popcount(hits);
+                } else if (WRITE) {
+                    while (hits) {
+                        const int b = __builtin_ctz(hits);
+                        hits &= hits - 1;
+                        o.put(base + b);
+                    }
+                } else {
+                    cnt += __builtin_popcount(hits);
+                }
+            }
+        }
+        cur = nx;
+    }
+    return cnt;
+}
+
 // ---------------------------------------------------------------------------
 // Block filter (after SSEF, Fig. 1). With S = m - 15, an occurrence at i contains
 // the 16-byte block at x whenever i <= x <= i + m - 16, an interval of S starts; so
@@ -747,6 +802,8 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
             uint32_t v = (k == hl) ? 0u : s_tab[k];
             P->shift[k] = (uint8_t)(v > 255u ? 255u : v);
         }
+    } else if (algo == ALGO_BRUTE) {  // each pattern byte in the four bytes of a word
+        if (tid < (uint32_t)BRUTE_MAX_M) P->mask[tid] = tid < m ? (uint32_t)pp[tid] * 0x01010101u : 0u;
     } else if (algo == ALGO_BLOCK && s_key) {
         build_block_tables(pp, m, P, s_tab, s_key, s_bad);
     }

@@ -18,8 +18,10 @@ enum Algo : int32_t {
     ALGO_HASHQ = 4,      // hashed q-gram skip filter + verification, any m >= q (Fig. 1, HASHq)
     ALGO_BLOCK = 5,      // 16-byte block fingerprint filter, BF_MIN_M <= m <= BF_MAX_M (after
                          // SSEF, Fig. 1): reads one block per m - 15 text bytes
-    ALGO_COUNT_ = 6
+    ALGO_BRUTE = 6,      // brute force over packed bytes, m <= BRUTE_MAX_M (Fig. 1, BF)
+    ALGO_COUNT_ = 7
 };
+constexpr int BRUTE_MAX_M = 8;
 
 constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
 constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register

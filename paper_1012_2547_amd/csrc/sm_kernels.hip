@@ -149,6 +149,11 @@ struct TileGeom {
     int hi_rel, r0;
 };
 
+// scanners that read the tile in 16-byte units per lane take the swizzled layout
+constexpr bool swz_tile(int algo) { return algo == ALGO_SHIFT_AND || algo == ALGO_BRUTE; }
+// scanners whose hits come as masks (bitmap form, first-hit slots)
+constexpr bool mask_hits(int algo) { return algo == ALGO_SHIFT_AND || algo == ALGO_BRUTE; }
+
 template <int ALGO, int L>
 __device__ __forceinline__ TileGeom tile_geom(const ScanArgs &a, uint64_t t)
 {
@@ -174,17 +179,30 @@ __device__ __forceinline__ void stage_tile(TileShared<ALGO, L> &S, const ScanArg
     const TileGeom g = tile_geom<ALGO, L>(a, t);
     Staged<G::PER> st;
     stage_issue(st, a.text, g.x0, g.x1);
-    stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+    stage_commit<swz_tile(ALGO)>(st, S.text);
     s = g.s;
     li0 = st.boff - g.r0;
     lo = threadIdx.x * L;
     hi = (lo + L - 1) < g.hi_rel ? (lo + L - 1) : g.hi_rel;
 }
 
+// Pattern words of the brute-force scanner (uniform: scalar registers).
+struct BruteWords {
+    uint32_t w[BRUTE_MAX_M];
+};
+template <int ALGO>
+__device__ __forceinline__ BruteWords brute_words(const Params *prm)
+{
+    BruteWords b;
+#pragma unroll
+    for (int k = 0; k < BRUTE_MAX_M; k++) b.w[k] = ALGO == ALGO_BRUTE ? (uint32_t)prm->mask[k] : 0u;
+    return b;
+}
+
 template <int ALGO, int L, int VAR, bool WRITE, class E>
 __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanArgs &a, int m,
                                              int sh1, int period, int period_lb, uint64_t s,
-                                             int li0, int lo, int hi, E &o)
+                                             int li0, int lo, int hi, E &o, const BruteWords &bw)
 {
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if constexpr (ALGO == ALGO_SHIFT_AND) {
@@ -196,6 +214,8 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
         return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
     } else if constexpr (ALGO == ALGO_BNDM) {
         return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
+    } else if constexpr (ALGO == ALGO_BRUTE) {
+        return lane_brute<WRITE>(S.text, bw.w, m, li0, lo, hi, o);
     } else if constexpr (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
         constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : (VAR == 2 ? 4 : 8));
         return lane_sbndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
@@ -213,7 +233,7 @@ enum CountMode {
     CM_COUNT = 0,  // counts only
     CM_FIND = 1,   // stash tiles are scanned again into the stash
     CM_CAP = 2,    // Shift-And, L = 16, sparse tiles expected: lanes keep their first LANE_K hits
-    CM_BITS = 3,   // Shift-And, L >= 32: lanes keep hit bitmaps; the bitmaps of tiles with
+    CM_BITS = 3,   // Shift-And or brute force, L >= 32: lanes keep hit bitmaps; the bitmaps of tiles with
                    // more than STASH_K hits go to the emit pass, the others fill the stash
 };
 
@@ -227,7 +247,8 @@ template <int ALGO, int L, int VAR, int MODE, bool PREFETCH>
 __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
 {
     using G = Geometry<ALGO, L>;
-    static_assert(MODE == CM_COUNT || MODE == CM_FIND || ALGO == ALGO_SHIFT_AND, "hit masks come from Shift-And");
+    static_assert(MODE == CM_COUNT || MODE == CM_FIND || mask_hits(ALGO), "hit masks come from Shift-And or brute force");
+    static_assert(MODE != CM_CAP || ALGO == ALGO_SHIFT_AND, "first-hit slots: Shift-And");
     static_assert(MODE != CM_BITS || L >= 32, "bitmaps take lanes of >= 32 starts");
     constexpr bool FIND = MODE != CM_COUNT;
     __shared__ TileShared<ALGO, L> S;
@@ -246,6 +267,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
     const int period_lb = (int)a.prm->period_lb;
+    const BruteWords bw = brute_words<ALGO>(a.prm);
     tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
 
     for (uint64_t t = t_begin; t < t_end; t++) {
@@ -254,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
             stage_issue(st, a.text, g.x0, g.x1);
         }
         __syncthreads();  // previous tile's LDS readers are done
-        stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+        stage_commit<swz_tile(ALGO)>(st, S.text);
         const TileGeom cur = g;
         const int li0 = st.boff - cur.r0;
         __syncthreads();
@@ -269,13 +291,13 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         [[maybe_unused]] CapEmit ce;
         [[maybe_unused]] BitAcc<NW> ba;
         if constexpr (MODE == CM_BITS) {
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba, bw);
         } else if constexpr (MODE == CM_CAP) {
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce);
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce, bw);
             c = ce.n;
         } else {
             NoEmit ne;
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne, bw);
         }
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
@@ -311,7 +333,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
                     StashEmit se;
                     se.dst = dst;
                     se.idx = before;
-                    run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se);
+                    run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, se, bw);
                 }
             }
         }
@@ -419,6 +441,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
     const int sh1 = (int)a.prm->sh1;
     const int period = (int)a.prm->period;
     const int period_lb = (int)a.prm->period_lb;
+    const BruteWords bw = brute_words<ALGO>(a.prm);
     // 1. tiles with at most STASH_K hits: copy their stash (waves on their own)
     {
         const uint64_t G = (uint64_t)gridDim.x * (BLOCK / 64);
@@ -458,7 +481,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
             Staged<G::PER> st;
             stage_issue(st, a.text, cur.x0, cur.x1);
             __syncthreads();  // the previous tile's LDS readers are done
-            stage_commit<ALGO == ALGO_SHIFT_AND>(st, S.text);
+            stage_commit<swz_tile(ALGO)>(st, S.text);
             const int li0 = st.boff - cur.r0;
             __syncthreads();
             const uint64_t s2 = cur.s;
@@ -471,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
                 ListEmit se;
                 se.dst = s_list + SUB_LANE * threadIdx.x;
                 se.idx = 0;
-                run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, se);
+                run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, s2, li0, lo, hi, se, bw);
                 const uint32_t c = se.idx;
                 uint32_t ctot;
                 const uint32_t before = block_excl_scan(c, S.w, ctot);  // ends with a barrier
@@ -931,13 +954,15 @@ hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
     } else if (KIND == K_FIND_COUNT) {
         // Shift-And: hit bitmaps, else (16-byte lanes) the lanes' first hits when sparse
         // tiles are expected
-        if constexpr (ALGO == ALGO_SHIFT_AND) {
+        if constexpr (mask_hits(ALGO)) {
             if (L >= 32 && a.bits) {
                 constexpr int LB = L >= 32 ? L : 32;
                 if (pf) hipLaunchKernelGGL((count_kernel<ALGO, LB, VAR, CM_BITS, true>), dim3(grid), dim3(BLOCK), 0, st, a);
                 else hipLaunchKernelGGL((count_kernel<ALGO, LB, VAR, CM_BITS, false>), dim3(grid), dim3(BLOCK), 0, st, a);
                 return hipGetLastError();
             }
+        }
+        if constexpr (ALGO == ALGO_SHIFT_AND) {
             if (a.slots) {
                 if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_CAP, true>), dim3(grid), dim3(BLOCK), 0, st, a);
                 else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_CAP, false>), dim3(grid), dim3(BLOCK), 0, st, a);
@@ -946,7 +971,7 @@ hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
         }
         if (pf) hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_FIND, true>), dim3(grid), dim3(BLOCK), 0, st, a);
         else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_FIND, false>), dim3(grid), dim3(BLOCK), 0, st, a);
-    } else if (ALGO == ALGO_SHIFT_AND && L >= 32 && a.bits)
+    } else if (mask_hits(ALGO) && L >= 32 && a.bits)
         hipLaunchKernelGGL((emit_bits_kernel<L >= 32 ? L : 32>), dim3(grid), dim3(BLOCK), 0, st, a);
     else
         hipLaunchKernelGGL((emit_kernel<ALGO, L, VAR>), dim3(grid), dim3(BLOCK), 0, st, a);
@@ -977,6 +1002,7 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
         return launch_l<ALGO_SHIFT_AND, 3, KIND>(p, a, grid, st);
     }
     case ALGO_BNDM: return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
+    case ALGO_BRUTE: return launch_l<ALGO_BRUTE, 0, KIND>(p, a, grid, st);
     case ALGO_SBNDM:
         if (p.q <= 1) return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);
         if (p.q == 2) return launch_l<ALGO_SBNDM, 1, KIND>(p, a, grid, st);
@@ -1094,8 +1120,8 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     a.out = d_out;
     a.lo = first;
     a.cap = cap;
-    // bitmap form for Shift-And scans with lanes of >= 32 starts
-    if (plan.algo == ALGO_SHIFT_AND && plan.lane_bytes >= 32) a.bits = w.bits;
+    // bitmap form for the mask-producing scans with lanes of >= 32 starts
+    if ((plan.algo == ALGO_SHIFT_AND || plan.algo == ALGO_BRUTE) && plan.lane_bytes >= 32) a.bits = w.bits;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
     const bool block = plan.algo == ALGO_BLOCK;

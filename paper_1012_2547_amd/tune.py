@@ -2,7 +2,7 @@
 
 For each alphabet-size bucket (representative sigma in 2, 4, 16, 64, 256) and a
 grid of pattern lengths, every applicable configuration -- algorithm (Shift-And,
-BNDM, SBNDM, Hash-q with its gram length q, the block filter), starts per lane
+BNDM, SBNDM, Hash-q with its gram length q, the block filter, brute force), starts per lane
 and tiles per workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
 benchmark's seed 1) with substring patterns, as whole find_all calls. The
 fastest configuration of each cell becomes a table entry. The paper's own
@@ -36,6 +36,10 @@ def candidates(m: int, sigma: int):
             for L in (32, 64, 128):
                 for tpw in (1, 2, 4):
                     out.append(dict(algo=algo, lane_bytes=L, q=1 if algo == 3 else 0, tiles_per_wg=tpw))
+        if m <= 8:  # brute force over packed bytes
+            for L in (32, 64, 128):
+                for tpw in (1, 2, 4):
+                    out.append(dict(algo=6, lane_bytes=L, q=0, tiles_per_wg=tpw))
         for q in (2, 4, 8):  # SBNDMq: the window's last q bytes read at once
             if q > m:
                 continue

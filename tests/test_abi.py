@@ -129,7 +129,7 @@ def test_tuning_table_roundtrip(L):
     import paper_1012_2547_amd as sm
     base = sm.tune_get()
     assert len(base) > 50
-    assert all(1 <= e["algo"] <= 5 and e["m_lo"] <= e["m_hi"] for e in base)
+    assert all(1 <= e["algo"] <= 6 and e["m_lo"] <= e["m_hi"] for e in base)
     # every (sigma, m) of the sweep grid is covered by some entry
     for s in (2, 4, 16, 64, 256):
         for m in (1, 2, 3, 5, 8, 63, 64, 65, 100, 1000, 5000):

@@ -25,7 +25,7 @@ def sm():
 
 DEV = "cuda:0"
 BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (m <= 64)
-ALL_ALGOS = (1, 2, 3, 4, 5)   # + Hash-q, block filter (144 <= m <= 4096)
+ALL_ALGOS = (1, 2, 3, 4, 5, 6)   # + Hash-q, block filter (144 <= m <= 4096), brute force (m <= 8)
 
 
 def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0):
@@ -52,6 +52,8 @@ def applicable(algo, m, q=0):
         return m <= 64
     if algo == 5:
         return 144 <= m <= 4096
+    if algo == 6:
+        return m <= 8
     return m >= max(q, 1)
 
 
@@ -163,6 +165,38 @@ def test_block_filter(sm):
     for m in (143, 4097):
         with pytest.raises(sm.SmError):
             gpu_find(sm, t_dev, bytes(m), algo=5)
+
+
+def test_brute_force_packed(sm):
+    """Brute force over packed bytes (m <= 8): every m, every lane width (the bitmap
+    form from 32 starts per lane, rescans at 16), every text offset modulo 16,
+    sparse and dense outputs, bytes 0x00, 0x7F, 0x80, 0xFF (edge cases of the
+    zero-byte test), truncation."""
+    rng = np.random.default_rng(31)
+    base_np = rng.choice(np.array([0, 0x7F, 0x80, 0xFF], np.uint8), 70_000)
+    base = torch.from_numpy(base_np).to(DEV)
+    for off in (0, 1, 3, 7, 13):
+        t_np = base_np[off:off + 60_001]
+        t_dev = base[off:off + 60_001]
+        for m in range(1, 9):
+            for p in (bytes(t_np[101:101 + m]), bytes(t_np[-m:]), bytes([0x80] * m)):
+                want = oracle.find_all(t_np, p)
+                for L, tpw in ((16, 1), (32, 2), (64, 1), (128, 3)):
+                    got, tot = gpu_find(sm, t_dev, p, algo=6, lane=L, tpw=tpw)
+                    assert tot == want.size and np.array_equal(got, want), (off, m, L, tpw)
+    for sigma in (2, 256):
+        t_np = dg.uniform_text(200_003, sigma, seed=50 + sigma)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for m in (1, 2, 5, 8):
+            p, _ = dg.substring_pattern(t_np, m, seed=51, idx=m)
+            want = oracle.find_all(t_np, p)
+            got, tot = gpu_find(sm, t_dev, p, algo=6, lane=64)
+            assert tot == want.size and np.array_equal(got, want), (sigma, m)
+            for cap in (1, want.size // 2):
+                got, tot = gpu_find(sm, t_dev, p, algo=6, lane=64, cap=cap)
+                assert np.array_equal(got, want[:cap]), (sigma, m, cap)
+    with pytest.raises(sm.SmError):
+        gpu_find(sm, t_dev, bytes(9), algo=6)
 
 
 def test_tiles_per_workgroup_and_lanes_deterministic(sm):
@@ -368,7 +402,7 @@ def test_workspace_reuse_across_calls(sm):
         m = int(rng.integers(1, 1200)) if i % 3 else int(rng.integers(1, 20))
         if m > n:
             m = n
-        algo = int(rng.choice([1, 2, 3, 4])) if m <= 64 else \
+        algo = int(rng.choice([1, 2, 3, 4] + ([6] if m <= 8 else []))) if m <= 64 else \
             int(rng.choice([4, 5])) if 144 <= m <= 4096 else 4
         o = sm.opts(algo=algo, lane_bytes=int(rng.choice([16, 64])))
         need = sm.workspace_size(n, m, o)
