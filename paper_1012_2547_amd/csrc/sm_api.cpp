@@ -372,6 +372,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     uint8_t *dpat = ws + w.pat;
     FindWs fw;
     fw.tile_cnt = reinterpret_cast<uint32_t *>(ws + w.tile_cnt);
+    fw.super = reinterpret_cast<uint64_t *>(ws + w.super);
     fw.list = reinterpret_cast<TileEntry *>(ws + w.list);
     fw.nlist = reinterpret_cast<uint64_t *>(ws + w.nlist);
     fw.stash = reinterpret_cast<uint16_t *>(ws + w.stash);
@@ -393,7 +394,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         rec.sampled = plan.algo == ALGO_BLOCK;
         HIP_TRY(hipEventRecord(rec.e0, st));
     }
-    HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, st));
+    HIP_TRY(launch_prep(plan, pat, prm, dpat, d_count, fw.super, num_super(w.ntiles), st));
     if (prof) HIP_TRY(hipEventRecord(rec.e1, st));
     if (write) {
         HIP_TRY(launch_find(plan, d_text, n, prm, dpat, fw, d_out, first, cap, d_count, st,

@@ -39,6 +39,8 @@ constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the c
 constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
 constexpr int EMIT_SUB = 4096;       // starts per sub-tile when a dense tile is rescanned
 constexpr uint64_t SCAN_CHUNK = 4096;  // tile counts per workgroup of the tile-count scan (4 per thread)
+constexpr int SUPER_SHIFT = 6;        // tiles per super-chunk total: 64
+constexpr int SUPER_NZ_SHIFT = 40;    // super-chunk total: (tiles with hits << 40) | hits
 constexpr int AUTO_MIN_LANE = 64;    // lane_bytes of the planner's heuristic (no table entry)
 
 // Device-side parameter block at the start of the caller's workspace; the
@@ -80,10 +82,10 @@ struct TileEntry {
 static_assert(sizeof(TileEntry) == 16, "one 16-byte load per entry");
 
 // Workspace layout (offsets in bytes from the workspace base):
-// [Params][pattern][tile_cnt u32][list TileEntry][nlist u64][stash u16 x STASH_K per tile]
-// [bits: one bit per start, m <= BP_MAX_M only]
+// [Params][pattern][tile_cnt u32][super u64 per 64 tiles][list TileEntry][nlist u64]
+// [stash u16 x STASH_K per tile][bits: one bit per start, m <= BP_MAX_M only]
 struct WsLayout {
-    uint64_t params, pat, tile_cnt, list, nlist, stash, bits;
+    uint64_t params, pat, tile_cnt, super, list, nlist, stash, bits;
     uint64_t need;        // minimum workspace size for find_all
     uint64_t need_count;  // minimum workspace size for count (params, pattern, tile_cnt)
     uint64_t ntiles;
@@ -99,6 +101,8 @@ inline uint64_t num_tiles(uint64_t n, uint64_t m, uint64_t tile)
     return (n - m + 1 + tile - 1) / tile;
 }
 
+inline uint64_t num_super(uint64_t ntiles) { return (ntiles + (1ull << SUPER_SHIFT) - 1) >> SUPER_SHIFT; }
+
 inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
 {
     WsLayout w;
@@ -110,6 +114,8 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
     o = align_up(o + m + 64, 256);
     w.tile_cnt = o;
     o = align_up(o + 4 * w.ntiles, 256);
+    w.super = o;
+    o = align_up(o + 8 * num_super(w.ntiles), 256);
     w.need_count = align_up(o, 256);
     w.list = o;
     o = align_up(o + sizeof(TileEntry) * w.ntiles, 256);
@@ -131,6 +137,7 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
 // Device pointers of the find_all workspace.
 struct FindWs {
     uint32_t *tile_cnt;
+    uint64_t *super;  // per 64 tiles: (tiles with hits << 40) | hits, added by the count pass
     TileEntry *list;
     uint64_t *nlist;
     uint16_t *stash;
@@ -275,9 +282,11 @@ const char *sm_set_error(int status, const char *msg);
 
 // Kernel launchers (sm_kernels.hip). All are asynchronous on `stream` and
 // return the HIP error of the launch.
-// Builds the pattern's tables in d_params; zeroes *d_zero when not null.
+// Builds the pattern's tables in d_params; zeroes *d_zero when not null, and the
+// nsuper super-chunk totals at d_super.
 hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_params,
-                       uint8_t *d_pat, uint64_t *d_zero, hipStream_t stream);
+                       uint8_t *d_pat, uint64_t *d_zero, uint64_t *d_super, uint64_t nsuper,
+                       hipStream_t stream);
 // count -> sum: total -> *d_total (uses w.tile_cnt only).
 // `after_count` (may be null) is recorded after the count kernel.
 hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n,

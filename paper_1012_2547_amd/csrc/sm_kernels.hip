@@ -58,7 +58,8 @@ struct ScanArgs {
     uint32_t bs;          // block filter: starts per sampled block (m - 15)
     uint64_t ntiles;
     uint64_t *total;      // count mode: occurrences are added here
-    uint32_t *tile_cnt;   // find mode: per-tile counts (count kernel writes, emit reads)
+    uint32_t *tile_cnt;   // per-tile counts (count kernel writes, tile scan and emit read)
+    uint64_t *super;      // per 64 tiles: (tiles with hits << 40) | hits, added by the count kernel
     uint16_t *stash;      // find mode: STASH_K offsets per tile
     const TileEntry *list;     // emit: tiles with hits, ascending, with their offsets
     const uint64_t *nlist;     // emit: list length
@@ -227,6 +228,26 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
     }
 }
 
+// Super-chunk totals: the count pass adds each workgroup's tiles into the total of
+// their 64-tile super-chunk (one device-scope atomic per workgroup and super-chunk,
+// none for tiles without hits), so the tile scan reads 1/64 of the counts before
+// its chunk. Thread 0 keeps the pending total of the current super-chunk.
+__device__ __forceinline__ void super_flush(const ScanArgs &a, uint64_t i, uint64_t v)
+{
+    if (v) atomicAdd(reinterpret_cast<unsigned long long *>(a.super + i), (unsigned long long)v);
+}
+__device__ __forceinline__ void super_add(const ScanArgs &a, uint64_t t, uint32_t tot, uint64_t &i,
+                                          uint64_t &v)
+{
+    const uint64_t k = t >> SUPER_SHIFT;
+    if (k != i) {
+        super_flush(a, i, v);
+        i = k;
+        v = 0;
+    }
+    if (tot) v += (1ull << SUPER_NZ_SHIFT) | tot;
+}
+
 // What the count kernel keeps besides the per-tile counts (find mode: each
 // tile with 1..STASH_K hits also stashes its hits' offsets).
 enum CountMode {
@@ -269,6 +290,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
     const int period_lb = (int)a.prm->period_lb;
     const BruteWords bw = brute_words<ALGO>(a.prm);
     tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
+    uint64_t sup_i = ~0ull, sup_v = 0;  // this workgroup's pending super-chunk total (thread 0)
 
     for (uint64_t t = t_begin; t < t_end; t++) {
         if (!PREFETCH && t != t_begin) {
@@ -301,7 +323,10 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         }
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
-        if (threadIdx.x == 0) a.tile_cnt[t] = tot;
+        if (threadIdx.x == 0) {
+            a.tile_cnt[t] = tot;
+            super_add(a, t, tot, sup_i, sup_v);
+        }
         if constexpr (MODE == CM_BITS) {
             if (tot > STASH_K) {  // uniform: the tile's bitmap for the emit pass
                 uint32_t *dst = a.bits + t * (uint64_t)(G::T / 32) + threadIdx.x * (L / 32);
@@ -338,6 +363,7 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
             }
         }
     }
+    if (threadIdx.x == 0) super_flush(a, sup_i, sup_v);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,6 +590,7 @@ __global__ __launch_bounds__(BLOCK) void block_count_kernel(ScanArgs a)
     uint64_t t_end = t_begin + a.tiles_per_wg;
     if (t_end > a.ntiles) t_end = a.ntiles;
     const uint32_t period = a.prm->period, period_lb = a.prm->period_lb;
+    uint64_t sup_i = ~0ull, sup_v = 0;
     BlockLane L = block_lane(a, t_begin);
     uint4 blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
     for (uint64_t t = t_begin; t < t_end; t++) {
@@ -582,8 +609,12 @@ __global__ __launch_bounds__(BLOCK) void block_count_kernel(ScanArgs a)
                                              cur.ihi, cb, cur.ilo <= cur.ihi, 0, ne);
         uint32_t tot;
         block_excl_scan(c, s_w, tot);
-        if (threadIdx.x == 0) a.tile_cnt[t] = tot;
+        if (threadIdx.x == 0) {
+            a.tile_cnt[t] = tot;
+            super_add(a, t, tot, sup_i, sup_v);
+        }
     }
+    if (threadIdx.x == 0) super_flush(a, sup_i, sup_v);
 }
 
 // Emit pass: every listed tile is tested again, once to count each lane's hits
@@ -730,9 +761,9 @@ __global__ __launch_bounds__(BLOCK) void emit_bits_kernel(ScanArgs a)
 }
 
 // Tile-count scan, SCAN_CHUNK tiles per workgroup of 1024 threads and no waiting
-// between workgroups: workgroup w first sums all counts before its chunk itself
-// (coalesced 16-byte loads, eight in flight per thread), then scans its chunk,
-// SCAN_CHUNK / 1024 consecutive counts per thread.
+// between workgroups: workgroup w first sums the super-chunk totals before its
+// chunk itself (one per 64 tiles, eight loads in flight per thread), then scans
+// its chunk, SCAN_CHUNK / 1024 consecutive counts per thread.
 // Writes the ascending list of tiles with hits (with counts and offsets); the last
 // workgroup writes the total and the list length. With list == null only the
 // total is produced (count mode).
@@ -770,28 +801,30 @@ __device__ __forceinline__ void block_sum2_1024(uint64_t &a, uint32_t &b, uint64
     __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, uint64_t nt,
-                                                         uint64_t *total, TileEntry *list,
+__global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, const uint64_t *super,
+                                                         uint64_t nt, uint64_t *total, TileEntry *list,
                                                          uint64_t *nlist)
 {
     __shared__ uint64_t s_a[16];
     __shared__ uint32_t s_b[16];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t c0 = (uint64_t)blockIdx.x * SCAN_CHUNK;
-    // 1. occurrences and listed tiles before this chunk
+    // 1. occurrences and listed tiles before this chunk, from the super-chunk totals
+    static_assert(SCAN_CHUNK % (1ull << SUPER_SHIFT) == 0, "chunks of whole super-chunks");
     uint64_t pre = 0;
     uint32_t pnz = 0;
-    for (uint64_t i0 = 0; i0 < c0; i0 += 8 * 4 * 1024) {
-        uint4 v[8];
+    const uint64_t s0 = c0 >> SUPER_SHIFT;
+    for (uint64_t i0 = 0; i0 < s0; i0 += 8 * 1024) {
+        uint64_t v[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            const uint64_t i = i0 + 4 * (uint64_t)(tid + 1024 * k);
-            v[k] = i < c0 ? load_cnt4(cnt, i, c0) : uint4{0u, 0u, 0u, 0u};
+            const uint64_t i = i0 + (uint64_t)tid + 1024 * k;
+            v[k] = i < s0 ? super[i] : 0ull;
         }
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            pre += (uint64_t)v[k].x + v[k].y + v[k].z + v[k].w;
-            pnz += (v[k].x != 0) + (v[k].y != 0) + (v[k].z != 0) + (v[k].w != 0);
+            pre += v[k] & ((1ull << SUPER_NZ_SHIFT) - 1);
+            pnz += (uint32_t)(v[k] >> SUPER_NZ_SHIFT);
         }
     }
     block_sum2_1024(pre, pnz, s_a, s_b);
@@ -868,6 +901,8 @@ struct PrepArgs {
     Params *prm;
     uint8_t *pat;      // destination of the pattern in the workspace
     uint64_t *zero;    // set to 0 (the running total), may be null
+    uint64_t *super;   // super-chunk totals to zero (nsuper of them)
+    uint64_t nsuper;
     uint32_t m, algo, q, hbits;
     uint32_t inline_len;  // pattern bytes carried below (0: already in pat)
     alignas(4) uint8_t inline_pat[PREP_INLINE];
@@ -906,6 +941,7 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
             if (k < padw) dst32[k] = w[u];
         }
     }
+    for (uint64_t k = tid; k < a.nsuper; k += BLOCK) a.super[k] = 0;
     if (tid == 0) {
         P->m = m;
         P->algo = a.algo;
@@ -1047,12 +1083,14 @@ uint32_t count_grid(const ScanArgs &a)
 }  // namespace
 
 hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_params, uint8_t *d_pat,
-                       uint64_t *d_zero, hipStream_t stream)
+                       uint64_t *d_zero, uint64_t *d_super, uint64_t nsuper, hipStream_t stream)
 {
     PrepArgs a;
     a.prm = d_params;
     a.pat = d_pat;
     a.zero = d_zero;
+    a.super = d_super;
+    a.nsuper = d_super ? nsuper : 0;
     a.m = (uint32_t)plan.m;
     a.algo = (uint32_t)plan.algo;
     a.q = (uint32_t)plan.q;
@@ -1078,7 +1116,8 @@ static hipError_t launch_tile_scan(const FindWs &w, uint64_t *d_total, bool find
 {
     const uint64_t nb = (w.ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     hipLaunchKernelGGL(tile_scan_kernel, dim3((uint32_t)nb), dim3(1024), 0, stream, w.tile_cnt,
-                       w.ntiles, d_total, find ? w.list : nullptr, find ? w.nlist : nullptr);
+                       (const uint64_t *)w.super, w.ntiles, d_total, find ? w.list : nullptr,
+                       find ? w.nlist : nullptr);
     return hipGetLastError();
 }
 
@@ -1097,6 +1136,7 @@ hipError_t launch_count(const Plan &plan, const uint8_t *d_text, uint64_t n, con
     if (w.ntiles > 0xFFFFFFFFull) return hipErrorInvalidValue;
     ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, w.ntiles);
     a.tile_cnt = w.tile_cnt;
+    a.super = w.super;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;
     hipError_t e = plan.algo == ALGO_BLOCK ? launch_block_count(a, g, stream)
@@ -1114,6 +1154,7 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     if (w.ntiles > 0xFFFFFFFFull) return hipErrorInvalidValue;
     ScanArgs a = make_args(plan, d_text, n, d_params, d_pat, w.ntiles);
     a.tile_cnt = w.tile_cnt;
+    a.super = w.super;
     a.stash = w.stash;
     a.list = w.list;
     a.nlist = w.nlist;
