@@ -26,6 +26,20 @@ if ROOT not in sys.path:
 
 METRIC = "text GB/s scanned (and % of HBM peak); batched patterns×GB/s; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
+
+# The paper's own timings, as context only (other hardware, other text sizes): mean
+# search time of the best algorithm per pattern length on its uniform 4-symbol text
+# of 5e6 bytes, one core of an Intel Core2 at 1.66 GHz (Section 3; the Rand4 table of
+# Section 4), converted to GB/s = 5e6 / t.
+PAPER_CONTEXT = {
+    "hardware": "one core of an Intel Core2 at 1.66 GHz",
+    "text": "uniform, 4 symbols, 5e6 bytes",
+    "best_gbs_by_m": {"2": {"algo": "SA", "ms": 16.4, "gbs": 0.30},
+                      "8": {"algo": "HASH3", "ms": 8.30, "gbs": 0.60},
+                      "64": {"algo": "HASH8", "ms": 2.46, "gbs": 2.03},
+                      "1024": {"algo": "SSEF", "ms": 0.54, "gbs": 9.26}},
+    "note": "context only; not the target",
+}
 SIGMAS = (2, 4, 16, 64, 256)
 MS = (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)
 PER_CELL = 20
@@ -282,6 +296,7 @@ def main():
         "sigma_eff": sigma_eff,
         "batched": batched,
         "serving": serving,
+        "paper_context": PAPER_CONTEXT,
     }
     if batched_waves is not None:
         res["batched_find_all"] = batched_waves
