@@ -189,7 +189,7 @@ int sm_batch_find_all_async(sm_corpus *corpus, const uint8_t *pats, const uint64
  * the patterns at open; sm_batch_close waits for the device and frees the batch.
  *
  * sm_batch_find_all writes through the same windows, in waves of at most the
- * budget set by sm_batch_set_wave_bytes (default 16 GiB, 0 restores it; it is
+ * budget set by sm_batch_set_wave_bytes (default 64 GiB, 0 restores it; it is
  * also kept below half of the free device memory), so the device never holds
  * the whole output.
  */
@@ -202,11 +202,15 @@ int sm_batch_close(sm_batch *batch);
 int sm_batch_set_wave_bytes(uint64_t bytes);
 /* How the write pass of sm_batch_open, sm_batch_find_all and the server finds the
  * positions of each pattern with occurrences (speed only, never results):
- * 0 = automatic (from the counts: a shared prefix-filter pass for q-classes whose
- * patterns would otherwise rescan most of the text), 1 = every pattern's own
- * scanner, 2 = the shared pass for every pattern sparse enough for it (at most 16
- * occurrences per 4096 text bytes) in q-classes of at least 3 such patterns.
- * Process-wide; SM_EINVAL outside 0..2. */
+ * 0 = automatic (from the counts of the window: the single-pattern pipeline for
+ * patterns of at most 64 bytes with at least one occurrence per 384 text bytes, a
+ * shared prefix-filter pass for q-classes whose patterns would otherwise rescan
+ * most of the text, each pattern's own scanner for the rest), 1 = every
+ * pattern's own scanner, 2 = the shared pass for every pattern sparse enough for
+ * it (at most 16 occurrences per 4096 text bytes) in q-classes of at least 3 such
+ * patterns, 3 = the single-pattern pipeline for every pattern of at most 64
+ * bytes. Patterns longer than 2048 bytes always take the single-pattern
+ * pipeline. Process-wide; SM_EINVAL outside 0..3. */
 int sm_batch_set_write_policy(int policy);
 
 /*

@@ -321,7 +321,8 @@ def batch_set_wave_bytes(nbytes: int) -> None:
 
 def batch_set_write_policy(policy: int) -> None:
     """Batched write pass: 0 automatic, 1 each pattern's own scanner, 2 shared filter
-    whenever the pattern is sparse enough (speed only; results are identical)."""
+    whenever the pattern is sparse enough, 3 the single-pattern pipeline for every
+    pattern of at most 64 bytes (speed only; results are identical)."""
     check(load().sm_batch_set_write_policy(policy))
 
 

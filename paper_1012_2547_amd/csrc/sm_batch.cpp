@@ -245,8 +245,8 @@ struct DevFree {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
-                   bool long_ws, BatchJob &j)
+int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P, int ws,
+                   BatchJob &j)
 {
     if (!pats || !pat_off) return err(SM_EINVAL, "patterns or offsets are NULL");
     j.c = c;
@@ -364,7 +364,16 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         j.chunk_tiles = ct;
         j.nchunks = (j.ntiles + ct - 1) / ct;
     }
-    j.L = layout_of(j, long_ws ? single : 0);
+    if (ws == WS_WRITE && !j.bpats.empty()) {
+        // single-pattern scratch for every m up to single_max_m: the size over that
+        // range is at most its value at m = 1 or at the top
+        uint32_t top = 0;
+        for (const auto &bp : j.bpats) top = std::max(top, bp.m);
+        j.single_max_m = std::min<uint32_t>(top, SINGLE_ROUTE_MAX_M);
+        single = std::max({single, sm_workspace_size(c->n, 1, nullptr),
+                           sm_workspace_size(c->n, j.single_max_m, nullptr)});
+    }
+    j.L = layout_of(j, ws == WS_NONE ? 0 : single);
     return SM_OK;
 }
 
@@ -418,12 +427,14 @@ int sm::batch_count_enqueue(BatchJob &j, uint8_t *ws, const uint8_t *h_image, ui
 }
 
 namespace {
-std::atomic<int> g_write_policy{0};  // 0 automatic, 1 own scanners only, 2 shared filter when sparse
+// 0 automatic, 1 own scanners only, 2 shared filter when sparse, 3 single-pattern
+// pipeline wherever the workspace allows
+std::atomic<int> g_write_policy{0};
 }
 
 extern "C" int sm_batch_set_write_policy(int policy)
 {
-    if (policy < 0 || policy > 2) return err(SM_EINVAL, "write policy must be 0, 1 or 2");
+    if (policy < 0 || policy > 3) return err(SM_EINVAL, "write policy must be 0, 1, 2 or 3");
     g_write_policy = policy;
     return SM_OK;
 }
@@ -445,16 +456,22 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
     j.wgroups.clear();
     j.mqw.clear();
     j.mqwtab.clear();
+    j.singlep.clear();
     if (j.bpats.empty()) return SM_OK;
     // A pattern may share a filter write pass when its own scanner would rescan at
     // least 1/16 of the text (the chunks holding its hits; estimated from its
     // count) and its hits are sparse enough to be sorted in LDS (at most 16 per
     // 4096 starts on average). A q-class shares a pass when the rescans it replaces
     // exceed 2.5 texts: one shared pass runs at about 2/5 of a per-pattern rescan's
-    // rate.
+    // rate. A pattern with at least one occurrence per SINGLE_ROUTE_DENSITY text
+    // bytes in the window goes to the single-pattern pipeline instead: one text
+    // read plus a coalesced emit, against 40 to 60 ps per position written from a
+    // batch pass.
     const double n = (double)j.c->n, nch = (double)j.nchunks;
     const double chunk_bytes = (double)j.chunk_tiles * BT;
-    std::vector<uint8_t> route(j.bpats.size(), 0);  // 0: none, 1: own scanner, 2: filter
+    // 0: none, 1: own scanner, 2: filter, 3: single-pattern pipeline
+    std::vector<uint8_t> route(j.bpats.size(), 0);
+    std::vector<double> wcount(j.bpats.size(), 0.0);  // occurrences inside the window
     std::vector<double> qcover(MQ_QMAX + 1, 0.0);
     std::vector<uint32_t> qn(MQ_QMAX + 1, 0);
     for (size_t k = 0; k < j.bpats.size(); k++) {
@@ -463,6 +480,13 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
         const uint64_t a0 = std::max(h_csr[i], lo), a1 = std::min(h_csr[i + 1], hi);
         const double c = a0 < a1 ? (double)(a1 - a0) : 0.0;
         if (c == 0) continue;
+        wcount[k] = c;
+        if (j.bpats[k].m <= j.single_max_m &&
+            (policy == 3 || (policy == 0 && c * SINGLE_ROUTE_DENSITY >= n))) {
+            route[k] = 3;
+            j.singlep.push_back(i);
+            continue;
+        }
         const double cover = nch * (1.0 - std::exp(-c / nch)) * chunk_bytes;
         const bool sparse = c * 4096.0 / n <= 16.0;
         const bool filt = policy == 2 ? sparse : (policy == 0 && sparse && cover * 16 >= n);
@@ -476,6 +500,28 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
     for (size_t k = 0; k < j.bpats.size(); k++) {
         const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
         if (route[k] == 2 && (qn[qc] < (uint32_t)MQ_MIN || (policy == 0 && qcover[qc] < 2.5 * n))) route[k] = 1;
+    }
+    if (policy == 0 && j.single_max_m) {
+        // A filter class costs one text pass per group of MQ_G patterns in every
+        // window; when the window holds few of its patterns, the single-pattern
+        // pipeline (about one text read each, plus the coalesced emit) is cheaper.
+        std::vector<double> alone(MQ_QMAX + 1, 0.0);
+        std::vector<uint8_t> can(MQ_QMAX + 1, 1);
+        for (size_t k = 0; k < j.bpats.size(); k++) {
+            if (route[k] != 2) continue;
+            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
+            if (j.bpats[k].m > j.single_max_m) can[qc] = 0;
+            alone[qc] += n * SINGLE_COST_PER_BYTE + wcount[k] * SINGLE_COST_PER_POS;
+        }
+        for (size_t k = 0; k < j.bpats.size(); k++) {
+            if (route[k] != 2) continue;
+            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
+            const double passes = (double)((qn[qc] + MQ_G - 1) / MQ_G);
+            if (can[qc] && alone[qc] < passes * n * FILTER_COST_PER_BYTE) {
+                route[k] = 3;
+                j.singlep.push_back(j.bpats[k].index);
+            }
+        }
     }
     // per-pattern write groups: consecutive sorted patterns routed to their own scanner
     for (uint32_t k = 0; k < j.bpats.size();) {
@@ -573,14 +619,18 @@ int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, con
         B.write = true;
         HIP_OK(launch_batch(B, st));
     }
-    if (!j.longp.empty() && !h_csr) return err(SM_EINVAL, "long patterns need the host offsets");
-    for (uint32_t i : j.longp) {  // one search each, into the window's part of its slice
-        const uint64_t a = std::max(h_csr[i], lo), b = std::min(h_csr[i + 1], hi);
-        if (a >= b) continue;
-        const uint64_t m = j.pat_off[i + 1] - j.pat_off[i];
-        int r = corpus_find_window_async(j.c, j.pats + j.pat_off[i], m, d_out + (a - lo), a - h_csr[i],
-                                         b - a, d_totals + i, ws + j.L.single, j.L.need - j.L.single, st);
-        if (r) return r;
+    if ((!j.longp.empty() || !j.singlep.empty()) && !h_csr)
+        return err(SM_EINVAL, "single-pattern searches need the host offsets");
+    // one search each, into the window's part of its slice
+    for (const auto *list : {&j.longp, &j.singlep}) {
+        for (uint32_t i : *list) {
+            const uint64_t a = std::max(h_csr[i], lo), b = std::min(h_csr[i + 1], hi);
+            if (a >= b) continue;
+            const uint64_t m = j.pat_off[i + 1] - j.pat_off[i];
+            int r = corpus_find_window_async(j.c, j.pats + j.pat_off[i], m, d_out + (a - lo), a - h_csr[i], b - a,
+                                             d_totals + i, ws + j.L.single, j.L.need - j.L.single, st);
+            if (r) return r;
+        }
     }
     return SM_OK;
 }
@@ -619,7 +669,7 @@ extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *
     for (uint64_t i = 0; i <= P; i++) b->pat_off[i] = pat_off[i] - base;
     b->pats.assign(pats + base, pats + pat_off[P]);
     b->pats.resize(b->pats.size() + 16);
-    if ((r = batch_plan(c, b->pats.data(), b->pat_off.data(), P, true, b->j))) return r;
+    if ((r = batch_plan(c, b->pats.data(), b->pat_off.data(), P, WS_WRITE, b->j))) return r;
     HIP_OK(hipMalloc((void **)&b->ws, b->j.L.need));
     uint64_t *d_tot = (uint64_t *)(b->ws + b->j.L.totals), *d_csr = (uint64_t *)(b->ws + b->j.L.csr);
     if ((r = batch_count_enqueue(b->j, b->ws, nullptr, d_tot, d_csr, true, nullptr))) return r;
@@ -672,7 +722,7 @@ extern "C" uint64_t sm_batch_workspace_size(const sm_corpus *c, const uint8_t *p
 {
     if (!c) return 0;
     BatchJob j;
-    if (batch_plan(const_cast<sm_corpus *>(c), pats, pat_off, P, true, j)) return 0;
+    if (batch_plan(const_cast<sm_corpus *>(c), pats, pat_off, P, WS_LONG, j)) return 0;
     return j.L.need;
 }
 
@@ -685,7 +735,7 @@ extern "C" int sm_batch_count_async(sm_corpus *c, const uint8_t *pats, const uin
     if (P == 0) return SM_OK;
     if (!d_counts) return err(SM_EINVAL, "d_counts is NULL");
     BatchJob j;
-    if ((r = batch_plan(c, pats, pat_off, P, true, j))) return r;
+    if ((r = batch_plan(c, pats, pat_off, P, WS_LONG, j))) return r;
     if ((r = check_ws(j, d_work, work_bytes))) return r;
     return batch_count_enqueue(j, (uint8_t *)d_work, nullptr, d_counts, nullptr, false, (hipStream_t)stream);
 }
@@ -700,7 +750,7 @@ extern "C" int sm_batch_find_all_async(sm_corpus *c, const uint8_t *pats, const 
     if (!d_out_off) return err(SM_EINVAL, "d_out_off is NULL");
     if (!d_out && cap > 0) return err(SM_EINVAL, "d_out is NULL with cap > 0");
     BatchJob j;
-    if ((r = batch_plan(c, pats, pat_off, P, false, j))) return r;
+    if ((r = batch_plan(c, pats, pat_off, P, WS_NONE, j))) return r;
     if (!j.longp.empty())
         return err(SM_EINVAL, "asynchronous batched find_all takes patterns up to %d bytes (use sm_batch_find_all)",
                    BATCH_MAX_M);
@@ -721,7 +771,7 @@ extern "C" int sm_batch_count(sm_corpus *c, const uint8_t *pats, const uint64_t 
     if (P == 0) return SM_OK;
     if (!counts) return err(SM_EINVAL, "counts is NULL");
     BatchJob j;
-    if ((r = batch_plan(c, pats, pat_off, P, true, j))) return r;
+    if ((r = batch_plan(c, pats, pat_off, P, WS_LONG, j))) return r;
     DevFree ws;
     HIP_OK(hipMalloc(&ws.p, j.L.need));
     uint64_t *d_tot = (uint64_t *)((uint8_t *)ws.p + j.L.totals);
@@ -731,7 +781,7 @@ extern "C" int sm_batch_count(sm_corpus *c, const uint8_t *pats, const uint64_t 
 }
 
 namespace {
-constexpr uint64_t WAVE_DEFAULT = 16ull << 30;
+constexpr uint64_t WAVE_DEFAULT = 64ull << 30;
 uint64_t g_wave_bytes = WAVE_DEFAULT;  // output-wave budget of sm_batch_find_all
 }
 

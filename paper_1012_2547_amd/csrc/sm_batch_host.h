@@ -36,16 +36,26 @@ struct BatchJob {
     std::vector<uint8_t> mqwtab;
     uint32_t max_mqw = 0;             // filter write groups the layout has room for
     std::vector<uint32_t> longp;      // m > BATCH_MAX_M: searched one pattern at a time
+    // write plan: patterns of the window dense enough that the single-pattern
+    // pipeline (bitmap form, coalesced emit) beats a batch rescan; possible when the
+    // workspace holds single-pattern scratch for every m up to single_max_m
+    std::vector<uint32_t> singlep;
+    uint32_t single_max_m = 0;
     uint64_t patbytes = 0;
     uint32_t chunk_tiles = 1;
     uint64_t nchunks = 0, ntiles = 0;
     BatchLayout L{};
 };
 
-// Validates and plans P patterns against the corpus (host only). The workspace
-// reserves single-pattern scratch for the long patterns when long_ws is set.
-int batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P,
-               bool long_ws, BatchJob &j);
+// Single-pattern scratch reserved in a batch workspace: none (asynchronous
+// find_all), for the long patterns (counting), or also for the dense patterns of
+// the write waves (handle, synchronous find_all, server).
+enum BatchWs { WS_NONE = 0, WS_LONG = 1, WS_WRITE = 2 };
+
+// Validates and plans P patterns against the corpus (host only), with the
+// workspace scratch of kind ws (BatchWs).
+int batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint32_t P, int ws,
+               BatchJob &j);
 
 // Bytes of the host image uploaded by the count step (pattern table, groups and
 // pattern bytes), and its contents.
@@ -78,7 +88,8 @@ int batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64_t l
 
 // Write step: CSR entries [lo, hi) -> d_out[0 .. hi - lo). Needs the count
 // step's workspace (keep_chunk_off) and d_csr; h_csr (host copy of d_csr) is
-// needed only when the job has long patterns.
+// needed only when the job has long patterns or the plan routes patterns to the
+// single-pattern pipeline.
 int batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, const uint64_t *h_csr,
                         uint64_t *d_totals, int64_t *d_out, uint64_t lo, uint64_t hi,
                         hipStream_t st);

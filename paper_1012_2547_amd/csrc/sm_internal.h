@@ -153,6 +153,20 @@ constexpr int BATCH_MAX_M = 2048;        // longest pattern handled inside a bat
 constexpr int BATCH_TABLE_BYTES = 32768; // LDS for a group's tables
 constexpr int BATCH_GROUP_MAX = 32;      // patterns per group
 constexpr int BATCH_HBITS_MAX = 10;      // Hash-q table bits inside a batch (1 KB per pattern)
+// Batch write waves. Cost model (seconds, measured on MI355X at n = 2^32): a
+// single-pattern search costs one count pass over the text (about 1/6.1e12 s per
+// byte, launches included) and 2.7 ps per position for its coalesced emit; one
+// prefix-filter write pass of a group costs about 1/0.8e12 s per text byte; a
+// position written from a batch pass (the filter's sorted tile lists, or a
+// lane-direct store of a pattern's own scanner) costs 40 to 60 ps. So a pattern
+// of at most SINGLE_ROUTE_MAX_M bytes with at least one occurrence per
+// SINGLE_ROUTE_DENSITY text bytes takes the single-pattern pipeline (break-even
+// near one per 300 to 400 bytes).
+constexpr uint32_t SINGLE_ROUTE_MAX_M = 64;
+constexpr double SINGLE_ROUTE_DENSITY = 384.0;
+constexpr double SINGLE_COST_PER_BYTE = 1.0 / 6.1e12;
+constexpr double SINGLE_COST_PER_POS = 8.0 / 3.0e12;
+constexpr double FILTER_COST_PER_BYTE = 1.0 / 0.8e12;
 
 // Multi-pattern prefix filter of the batched count pass. The patterns of one
 // q-class (q = min(m, MQ_QMAX)) are cut into groups of at most MQ_G. A group keeps

@@ -231,7 +231,7 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     }
     s.pats.resize(s.pats.size() + 16);
     s.job = BatchJob();
-    int r = batch_plan(c, s.pats.data(), s.pat_off.data(), P, true, s.job);
+    int r = batch_plan(c, s.pats.data(), s.pat_off.data(), P, WS_WRITE, s.job);
     if (r) return r;
     BatchJob &j = s.job;
     if ((r = grow_dev(&s.ws, &s.ws_cap, j.L.need))) return r;
@@ -281,7 +281,8 @@ int run_batch(sm_server *S, Slot &s, sm_corpus *c)
     for (uint64_t lo = 0; lo < total; lo += s.pool_pos, nw++) {
         const uint64_t hi = std::min(total, lo + s.pool_pos);
         if ((r = batch_write_plan(j, s.ws, s.h_csr, lo, hi, s.st, *s.stg))) return r;
-        r = enqueue_graph(S, s.st, s.write_exec, graphs, [&]() -> int {
+        // a wave with single-pattern searches launches directly, as long patterns do
+        r = enqueue_graph(S, s.st, s.write_exec, graphs && j.singlep.empty(), [&]() -> int {
             int rr = batch_write_enqueue(j, s.ws, d_csr, s.h_csr, d_tot, s.pool, lo, hi, s.st);
             if (rr) return rr;
             HIP_OK(hipMemcpyAsync(s.host_out + lo, s.pool, (hi - lo) * 8, hipMemcpyDeviceToHost, s.st));

@@ -86,6 +86,15 @@ def test_degenerate_sizes_return_zero_without_device(L):
     assert L.sm_count_dev(t, 3, p, 4, ctypes.byref(c), None) == SM_OK and c.value == 0
 
 
+def test_batch_write_policy_range(L):
+    from paper_1012_2547_amd._native import SM_EINVAL, SM_OK
+    for v in (0, 1, 2, 3):
+        assert L.sm_batch_set_write_policy(v) == SM_OK
+    assert L.sm_batch_set_write_policy(4) == SM_EINVAL
+    assert L.sm_batch_set_write_policy(-1) == SM_EINVAL
+    assert L.sm_batch_set_write_policy(0) == SM_OK
+
+
 def test_invalid_options(L):
     import paper_1012_2547_amd as sm
     with pytest.raises(sm.SmError):

@@ -52,7 +52,7 @@ def check_csr(sm, t_np, pats, pos, off, cap=None):
     assert np.array_equal(pos, flat[:lim])
 
 
-@pytest.fixture(params=[0, 1, 2], ids=["auto", "own", "shared"])
+@pytest.fixture(params=[0, 1, 2, 3], ids=["auto", "own", "shared", "single"])
 def policy(sm, request):
     sm.batch_set_write_policy(request.param)
     yield request.param

@@ -48,7 +48,11 @@ def query_mix(texts, count, seed):
     return out
 
 
-def test_batch_windows_match_whole_output(sm):
+@pytest.mark.parametrize("policy", [0, 1, 3])
+def test_batch_windows_match_whole_output(sm, policy):
+    """Windows cut inside the slices of dense patterns, which the automatic write plan
+    (0) and policy 3 search with the single-pattern pipeline, one window at a time."""
+    sm.batch_set_write_policy(policy)
     t_np = dg.uniform_text(400_000, 4, seed=3)
     t_np[:50_000] = np.tile(t_np[:7], 50_000 // 7 + 1)[:50_000]  # period 7: long patterns recur
     pats = [dg.substring_pattern(t_np, int(m), seed=4, idx=i)[0]
@@ -77,6 +81,7 @@ def test_batch_windows_match_whole_output(sm):
         b.write_async(0, b.total + 1, d)
     b.close()
     c.close()
+    sm.batch_set_write_policy(0)
 
 
 def test_batch_find_all_in_small_waves(sm):
