@@ -89,8 +89,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--batched-n-log2", type=int, default=32)
     ap.add_argument("--batched-patterns", type=int, default=4096)
-    ap.add_argument("--batched-find-all", action="store_true",
-                    help="also list every position of the batched workload in 64 GiB output waves")
+    ap.add_argument("--no-batched-find-all", action="store_true",
+                    help="skip listing every position of the batched workload (64 GiB output waves)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-shift", type=int, default=0,
                     help="log2 scale of the serving corpora (0: 8, 2 and 4 GiB)")
@@ -270,7 +270,7 @@ def main():
         batched = batched_section(args, dev, stream)
 
     batched_waves = None
-    if args.batched_find_all:
+    if not args.no_batched_find_all:
         torch.cuda.empty_cache()
         batched_waves = batched_find_all_section(args, dev)
 
