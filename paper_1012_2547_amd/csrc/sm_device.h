@@ -217,9 +217,11 @@ struct takes_masks<BitAcc<NW>> {
 };
 
 // Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
-// hit checks (requires m - 1 + CHECK <= bits of W).
-template <typename W, int CHECK, bool WRITE, class E>
-__device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *mask, int m, int li0,
+// hit checks (requires m - 1 + CHECK <= bits of W). MT = mask table entry: W, or
+// a byte when m <= 8 (the masks' bits >= m are clear), so that the table index is
+// the text byte itself, with no scaling.
+template <typename W, int CHECK, bool WRITE, class E, typename MT = W>
+__device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const MT *mask, int m, int li0,
                                                   int lo, int hi, E &o)
 {
     const int e_lo = lo + m - 1, e_hi = hi + m - 1;  // relative ends owned by this lane
@@ -235,7 +237,7 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const W *ma
             for (int b = 0; b < CHECK; b++) {
                 const int k = g * CHECK + b;
                 const uint32_t c = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                D = (D << 1) | mask[c];
+                D = (D << 1) | (W)mask[c];
             }
             // relative end of the last byte consumed
             const int e_last = 16 * u + g * CHECK + CHECK - 1 - li0;

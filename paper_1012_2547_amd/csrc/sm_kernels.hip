@@ -138,6 +138,8 @@ __device__ __forceinline__ void tables_commit(uint4 r, uint64_t *s_mask, uint8_t
         if (tid < ((1u << hbits) >> 4)) reinterpret_cast<uint4 *>(s_shift)[tid] = r;
     } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
         reinterpret_cast<uint32_t *>(s_mask)[tid] = r.x;
+    } else if (ALGO == ALGO_SHIFT_AND && VAR == 4) {  // m <= 8: the masks fit a byte
+        reinterpret_cast<uint8_t *>(s_mask)[tid] = (uint8_t)r.x;
     } else {
         s_mask[tid] = ((uint64_t)r.y << 32) | r.x;
     }
@@ -207,6 +209,9 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
 {
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if constexpr (ALGO == ALGO_SHIFT_AND) {
+        if (VAR == 4)
+            return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint8_t *>(S.mask), m,
+                                                       li0, lo, hi, o);
         if (VAR == 0)
             return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
                                                        m, li0, lo, hi, o);
@@ -1032,6 +1037,9 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
     switch (p.algo) {
     case ALGO_SHIFT_AND: {
         const int m = (int)p.m;
+        // variants: 4 = 32-bit state, byte masks (m <= 8); 0 = 32-bit state and masks;
+        // 1, 2, 3 = 64-bit state, hits checked every 16, 4 or 1 bytes
+        if (m <= 8) return launch_l<ALGO_SHIFT_AND, 4, KIND>(p, a, grid, st);
         if (m <= 17) return launch_l<ALGO_SHIFT_AND, 0, KIND>(p, a, grid, st);
         if (m <= 49) return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
         if (m <= 61) return launch_l<ALGO_SHIFT_AND, 2, KIND>(p, a, grid, st);
