@@ -149,7 +149,7 @@ def main():
     corpora = {s: sm.Corpus(dev_texts[s]) for s in SIGMAS}
     sigma_eff = {s: round(corpora[s].stats()[2], 2) for s in SIGMAS}
     calls = [(s, m, p) for s in SIGMAS for m in MS for p in pats[(s, m)]]
-    work = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
+    work = torch.empty(sm.workspace_size_upto(n, 1024), dtype=torch.uint8,
                        device=dev)
     counts_dev = torch.zeros(len(calls), dtype=torch.int64, device=dev)
     # exact counts (sizes the output buffer; checked after every step)
@@ -338,7 +338,7 @@ def batched_section(args, dev, stream):
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3 / reps
     # plain: one single-pattern count per pattern
-    w1 = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
+    w1 = torch.empty(sm.workspace_size_upto(n, 1024), dtype=torch.uint8,
                      device=dev)
     d_p = torch.zeros(P, dtype=torch.int64, device=dev)
     for i in range(min(P, 64)):  # warm-up
@@ -432,7 +432,7 @@ def batched_find_all_section(args, dev):
     # each into a buffer of its own count (every position written, as above)
     counts = off[1:] - off[:-1]
     out = torch.empty(max(int(counts.max()), 1), dtype=torch.int64, device=dev)
-    work = torch.empty(max(sm.workspace_size(n, m_) for m_ in (1, 1024)), dtype=torch.uint8, device=dev)
+    work = torch.empty(sm.workspace_size_upto(n, 1024), dtype=torch.uint8, device=dev)
     dc = torch.zeros(1, dtype=torch.int64, device=dev)
     for p in pats[:64]:  # warm-up
         corpus.find_all_async(p, out, dc, work, None, stream)

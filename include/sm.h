@@ -134,11 +134,16 @@ int sm_count_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t
  * pass keeps their hits as a bitmap of starts. count
  * runs the first kernel only; its workspace may be smaller.
  *
- * The size depends on m: for m <= 64 it holds that bitmap (n bits), and fewer
- * tiles are needed as m grows. A workspace shared by patterns of lengths 1..M
- * under the same options needs the larger of the sizes at m = 1 and m = M.
+ * The size depends on m: for m <= 64 it holds that bitmap (n bits), fewer tiles
+ * are needed as m grows, and the lane width (hence the tile count) the planner
+ * may pick differs between lengths. sm_workspace_size_upto(n, M, opts) is the
+ * size of a workspace that serves every pattern length 1..M under the same
+ * options (the maximum of sm_workspace_size over those lengths, or a bound
+ * above it for M > 4097, where the planner's lanes no longer depend on m under
+ * the built-in table).
  */
 uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts);
+uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_opts *opts);
 int sm_find_all_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
                       int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
                       uint64_t work_bytes, const sm_opts *opts, void *stream);

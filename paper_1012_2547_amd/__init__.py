@@ -21,7 +21,7 @@ from ._native import (ALGO_AUTO, ALGO_BLOCK, ALGO_BNDM, ALGO_BRUTE, ALGO_HASHQ, 
 __all__ = ["pack_patterns", "find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
            "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_BLOCK", "ALGO_BRUTE", "ALGO_NAMES", "version",
-           "Batch", "Server", "batch_set_wave_bytes", "batch_set_write_policy", "now_ns"]
+           "Batch", "Server", "batch_set_wave_bytes", "batch_set_write_policy", "now_ns", "workspace_size_upto"]
 
 
 def version() -> str:
@@ -61,6 +61,11 @@ def _stream_ptr(stream):
 
 def workspace_size(n: int, m: int, o: Opts | None = None) -> int:
     return int(load().sm_workspace_size(n, m, ctypes.byref(o) if o is not None else None))
+
+
+def workspace_size_upto(n: int, m_max: int, o: Opts | None = None) -> int:
+    """Bytes of a workspace that serves every pattern length 1..m_max under o."""
+    return int(load().sm_workspace_size_upto(n, m_max, ctypes.byref(o) if o is not None else None))
 
 
 def plan_query(pat, o: Opts | None = None) -> dict:

@@ -87,6 +87,7 @@ PROTOTYPES = {
     "sm_find_all_dev": (_i32, [_vp, _u64, _vp, _u64, _vp, _u64, _pu64, _vp]),
     "sm_count_dev": (_i32, [_vp, _u64, _vp, _u64, _pu64, _vp]),
     "sm_workspace_size": (_u64, [_u64, _u64, ctypes.POINTER(Opts)]),
+    "sm_workspace_size_upto": (_u64, [_u64, _u64, ctypes.POINTER(Opts)]),
     "sm_find_all_async": (_i32, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
                                  ctypes.POINTER(Opts), _vp]),
     "sm_count_async": (_i32, [_vp, _u64, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(Opts), _vp]),

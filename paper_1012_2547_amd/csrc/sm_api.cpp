@@ -345,6 +345,31 @@ extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opt
     return ws_layout(n, m, tile_starts(p)).need;
 }
 
+extern "C" uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_opts *opts)
+{
+    // every length up to the block filter's range, one by one
+    const uint64_t lim = std::min<uint64_t>(m_max, (uint64_t)BF_MAX_M + 1);
+    uint64_t best = 0;
+    for (uint64_t m = 1; m <= lim; m++) best = std::max(best, sm_workspace_size(n, m, opts));
+    if (m_max <= lim) return best;
+    // above it: the tile part only shrinks as m grows and the pattern copy grows,
+    // so the narrowest lane any entry covering (lim, m_max] may pick, at m = lim + 1,
+    // with the pattern copy of m_max bounds every size
+    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : AUTO_MIN_LANE;
+    if (!(opts && opts->lane_bytes)) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        const sm_tune_entry *e = g_tune_custom ? g_tune.data() : k_builtin_tune;
+        const size_t ne = g_tune_custom ? g_tune.size() : sizeof(k_builtin_tune) / sizeof(k_builtin_tune[0]) - 1;
+        for (size_t k = 0; k < ne; k++)
+            if (e[k].m_hi > lim && e[k].m_lo <= m_max && e[k].lane_bytes && e[k].lane_bytes < lb)
+                lb = e[k].lane_bytes;
+    }
+    Plan p;
+    p.lane_bytes = lb;
+    const WsLayout w = ws_layout(n, lim + 1, tile_starts(p));
+    return std::max(best, w.need + align_up(m_max + 64, 256) - align_up(lim + 1 + 64, 256));
+}
+
 static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
                      int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
                      uint64_t work_bytes, const sm_opts *opts, hipStream_t st, bool write,

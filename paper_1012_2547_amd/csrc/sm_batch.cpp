@@ -365,13 +365,11 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         j.nchunks = (j.ntiles + ct - 1) / ct;
     }
     if (ws == WS_WRITE && !j.bpats.empty()) {
-        // single-pattern scratch for every m up to single_max_m: the size over that
-        // range is at most its value at m = 1 or at the top
+        // single-pattern scratch for every m up to single_max_m
         uint32_t top = 0;
         for (const auto &bp : j.bpats) top = std::max(top, bp.m);
         j.single_max_m = std::min<uint32_t>(top, SINGLE_ROUTE_MAX_M);
-        single = std::max({single, sm_workspace_size(c->n, 1, nullptr),
-                           sm_workspace_size(c->n, j.single_max_m, nullptr)});
+        single = std::max(single, sm_workspace_size_upto(c->n, j.single_max_m, nullptr));
     }
     j.L = layout_of(j, ws == WS_NONE ? 0 : single);
     return SM_OK;

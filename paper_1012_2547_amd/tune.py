@@ -11,7 +11,8 @@ quantities; this measures that map on MI355X.
 
     python -m paper_1012_2547_amd.tune --out tune_out --n-log2 30   # on a GPU
 writes tune.json (entries + timings) and tune_table.inc (C initialisers for
-csrc/tune_table.inc).
+csrc/tune_table.inc). With --sigmas / --ms only those cells are measured again
+and the others are taken from --base (a tune.json of the same grid).
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ import time
 
 SIGMAS = (2, 4, 16, 64, 256)
 SIGMA_RANGES = {2: (1, 2), 4: (3, 7), 16: (8, 31), 64: (32, 127), 256: (128, 256)}
-M_GRID = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 65, 96, 128, 192, 256, 384, 512, 768, 1024)
+M_GRID = (1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 32, 48, 64, 65, 96, 128, 192, 256, 384, 512, 768, 1024)
 QS = (2, 3, 4, 5, 6, 8, 10, 12, 16)
 
 
@@ -64,7 +65,24 @@ def main():
     ap.add_argument("--n-log2", type=int, default=30)
     ap.add_argument("--patterns", type=int, default=6)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--sigmas", type=str, default="", help="comma-separated subset of the alphabet buckets")
+    ap.add_argument("--ms", type=str, default="", help="comma-separated subset of the pattern-length grid")
+    ap.add_argument("--base", type=str, default="", help="tune.json holding the cells not measured")
     args = ap.parse_args()
+    sigmas = tuple(int(x) for x in args.sigmas.split(",")) if args.sigmas else SIGMAS
+    grid = tuple(int(x) for x in args.ms.split(",")) if args.ms else M_GRID
+    if not set(sigmas) <= set(SIGMAS) or not set(grid) <= set(M_GRID):
+        raise SystemExit("--sigmas / --ms must be taken from the grid")
+    base = {}
+    if args.base:
+        with open(args.base) as f:
+            for c in json.load(f)["cells"]:
+                base[(c["sigma"], c["m"])] = c
+    if (sigmas, grid) != (SIGMAS, M_GRID):
+        missing = [(sg, m) for sg in SIGMAS for m in M_GRID
+                   if (sg not in sigmas or m not in grid) and (sg, m) not in base]
+        if missing:
+            raise SystemExit("a subset needs --base with the other cells (missing %s)" % (missing[:3],))
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
@@ -78,15 +96,15 @@ def main():
     dev = torch.device("cuda:0")
     n = 1 << args.n_log2
     stream = torch.cuda.current_stream()
-    work = torch.empty(max(sm.workspace_size(n, m_, sm.opts(lane_bytes=32)) for m_ in (1, 1024)), dtype=torch.uint8,
+    work = torch.empty(sm.workspace_size_upto(n, 1024, sm.opts(lane_bytes=32)), dtype=torch.uint8,
                        device=dev)
     dc = torch.zeros(1, dtype=torch.int64, device=dev)
     results = []
     t_start = time.time()
-    for sigma in SIGMAS:
+    for sigma in sigmas:
         h = dg.uniform_text(n, sigma, seed=2)
         text = torch.from_numpy(h).to(dev)
-        for m in M_GRID:
+        for m in grid:
             pats = [dg.substring_pattern(h, m, seed=3, idx=j)[0] for j in range(args.patterns)]
             counts = []
             for p in pats:
@@ -123,6 +141,9 @@ def main():
         del text
         torch.cuda.empty_cache()
 
+    measured = {(r["sigma"], r["m"]) for r in results}
+    results += [c for k, c in base.items() if k not in measured]
+    results.sort(key=lambda r: (SIGMAS.index(r["sigma"]), M_GRID.index(r["m"])))
     entries = []
     for r in results:
         i = M_GRID.index(r["m"])

@@ -134,6 +134,36 @@ def test_workspace_size_monotone(L):
     assert sm.workspace_size(10, 20) > 0
 
 
+def test_workspace_size_upto_covers_every_length(L):
+    """A shared workspace: at least the size of every length up to M, with the planner's
+    lanes from the built-in table and from a table whose narrowest lane sits at an
+    interior length (and, past the block filter's range, at long lengths)."""
+    import paper_1012_2547_amd as sm
+    tables = [None,
+              [dict(sigma_lo=1, sigma_hi=256, m_lo=1, m_hi=8, algo=1, lane_bytes=128),
+               dict(sigma_lo=1, sigma_hi=256, m_lo=9, m_hi=11, algo=3, lane_bytes=16),
+               dict(sigma_lo=1, sigma_hi=256, m_lo=12, m_hi=6000, algo=4, lane_bytes=128),
+               dict(sigma_lo=1, sigma_hi=256, m_lo=6001, m_hi=7000, algo=4, lane_bytes=32),
+               dict(sigma_lo=1, sigma_hi=256, m_lo=7001, m_hi=0xFFFFFFFF, algo=4, lane_bytes=128)]]
+    try:
+        for tab in tables:
+            if tab is not None:
+                sm.tune_set(tab)
+            for n in (5000, 1 << 20):
+                for M in (1, 9, 64, 300, 4097, 9000):
+                    got = sm.workspace_size_upto(n, M)
+                    each = max(sm.workspace_size(n, m) for m in range(1, M + 1))
+                    assert got >= each, (n, M)
+                    if M <= 4097:
+                        assert got == each, (n, M)
+            o = sm.opts(lane_bytes=64)
+            assert sm.workspace_size_upto(1 << 20, 100, o) == max(
+                sm.workspace_size(1 << 20, m, o) for m in range(1, 101))
+    finally:
+        sm.tune_set([])
+    assert sm.workspace_size_upto(1 << 20, 0) == 0
+
+
 def test_tuning_table_roundtrip(L):
     import paper_1012_2547_amd as sm
     base = sm.tune_get()
