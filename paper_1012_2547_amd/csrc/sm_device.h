@@ -830,16 +830,16 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t per = 0;
-        for (uint32_t d = 1; d <= PERIOD_MAX && d < m; d++)
-            if (!s_bad[d]) {
-                per = d;
-                break;
-            }
+    if (tid < 64) {  // wave 0: lane d - 1 tests period d; the smallest is the first set bit
+        static_assert(PERIOD_MAX == 64, "one lane per candidate period");
+        const uint32_t d = tid + 1;
+        const uint64_t ok = __ballot(d < m && !s_bad[d]);
+        uint32_t per = ok ? (uint32_t)__builtin_ctzll(ok) + 1u : 0u;
         if (per == 0 && m <= PERIOD_MAX + 1) per = m;
-        P->period = per;
-        P->period_lb = per ? per : PERIOD_MAX + 1;
+        if (tid == 0) {
+            P->period = per;
+            P->period_lb = per ? per : PERIOD_MAX + 1;
+        }
     }
 }
 
