@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 METRIC = "text GB/s scanned (and % of HBM peak); batched patterns×GB/s; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
+PROF_EVERY = 8  # sweep calls per call whose kernels are timed with HIP events
 
 # The paper's own timings, as context only (other hardware, other text sizes): mean
 # search time of the best algorithm per pattern length on its uniform 4-symbol text
@@ -173,7 +174,9 @@ def main():
     assert np.array_equal(got, expect), "find_all totals differ from count totals"
 
     sm.prof_collect()  # clear
-    sm.prof_enable(True)
+    # kernel times from HIP events on every PROF_EVERY-th call (each event costs the
+    # stream a few microseconds, about 10 % of a call if every call carried four)
+    sm.prof_enable(True, every=PROF_EVERY)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
@@ -218,18 +221,20 @@ def main():
         "%.2f ms/step" % (gbs, count_gbs, 100 * count_gbs / HBM_PEAK_GBS,
                           roofline["avg_emit_us"], ms_per_step))
 
-    # per-cell rates (mean over the cell's patterns), from one extra timed pass
-    cells = {}
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+    # per-cell rates from one extra timed pass: events at cell boundaries only, so a
+    # cell's rate is its patterns' bytes over their back-to-back calls
+    keys = ["s%d_m%d" % (s, m) for s in SIGMAS for m in MS]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(keys) + 1)]
     ev[0].record(stream)
-    for k, (s, m, p) in enumerate(calls):
-        corpora[s].find_all_async(p, out, counts_dev[k:k + 1], work, None, stream)
-        ev[k + 1].record(stream)
+    k = 0
+    for ci, (s, m) in enumerate((s, m) for s in SIGMAS for m in MS):
+        for p in pats[(s, m)]:
+            corpora[s].find_all_async(p, out, counts_dev[k:k + 1], work, None, stream)
+            k += 1
+        ev[ci + 1].record(stream)
     torch.cuda.synchronize()
-    for k, (s, m, p) in enumerate(calls):
-        dt = ev[k].elapsed_time(ev[k + 1]) / 1e3
-        cells.setdefault("s%d_m%d" % (s, m), []).append(n / dt / 1e9)
-    cell_gbs = {c: round(float(np.median(v)), 1) for c, v in cells.items()}
+    cell_gbs = {c: round(n * args.per_cell / (ev[ci].elapsed_time(ev[ci + 1]) / 1e3) / 1e9, 1)
+                for ci, c in enumerate(keys)}
 
     # ---- CPU baseline: the oracle on host cores, plus full-size parity --------
     cpu = None
@@ -292,7 +297,7 @@ def main():
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "cells_median_gbs": cell_gbs,
+        "cells_gbs": cell_gbs,
         "sigma_eff": sigma_eff,
         "batched": batched,
         "serving": serving,

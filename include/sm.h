@@ -342,9 +342,13 @@ int sm_corpus_count_async(sm_corpus *corpus, const uint8_t *pat, uint64_t m, uin
 int sm_corpus_text(const sm_corpus *corpus, const uint8_t **d_text, uint64_t *n);
 
 /*
- * Kernel timing (profiling aid). While enabled, every *_async/_dev call records
- * HIP events on its stream around its kernels. sm_prof_collect waits for the
- * recorded events, returns the accumulated times and clears them.
+ * Kernel timing (profiling aid). sm_prof_enable(k), k >= 1: every k-th
+ * *_async/_dev call from now on (the first, then every k-th after it, in issue
+ * order) records HIP events on its stream around its kernels (each event costs
+ * the stream a few microseconds, so a stride keeps timed loops close to their
+ * unprofiled speed); 0 turns recording off, a negative k is SM_EINVAL.
+ * sm_prof_collect waits for the recorded events, returns the accumulated times
+ * of the recorded calls and clears them.
  */
 typedef struct sm_prof {
     uint64_t calls;        /* calls recorded */
@@ -355,7 +359,7 @@ typedef struct sm_prof {
     uint64_t sampled_calls;   /* of the calls, those whose count pass is the block filter, */
     double sampled_count_ms;  /* which reads one 16-byte block per m - 15 bytes, and its time */
 } sm_prof;
-int sm_prof_enable(int on);
+int sm_prof_enable(int every);
 int sm_prof_collect(sm_prof *out);
 
 #ifdef __cplusplus

@@ -431,8 +431,9 @@ def tune_set(entries: list[dict]) -> None:
     check(load().sm_tune_set(arr, len(entries)))
 
 
-def prof_enable(on: bool = True) -> None:
-    check(load().sm_prof_enable(1 if on else 0))
+def prof_enable(on: bool = True, every: int = 1) -> None:
+    """Record kernel times of every `every`-th call from now on (off when on is False)."""
+    check(load().sm_prof_enable(every if on else 0))
 
 
 def prof_collect() -> dict:

@@ -276,14 +276,17 @@ struct ProfRec {
     bool sampled;  // block filter: the count pass reads sampled blocks only
 };
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+uint32_t g_prof_every = 0;  // 0: off; k: every k-th call is recorded
+uint64_t g_prof_seen = 0;   // calls since enabling
 std::vector<ProfRec> g_prof;
 }  // namespace
 
-extern "C" int sm_prof_enable(int on)
+extern "C" int sm_prof_enable(int every)
 {
+    if (every < 0) return fail(SM_EINVAL, "profiling stride must be >= 0");
     std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof_on = on != 0;
+    g_prof_every = (uint32_t)every;
+    g_prof_seen = 0;
     return SM_OK;
 }
 
@@ -408,7 +411,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     ProfRec rec{};
     {
         std::lock_guard<std::mutex> g(g_prof_mu);
-        prof = g_prof_on;
+        prof = g_prof_every && g_prof_seen++ % g_prof_every == 0;
     }
     if (prof) {
         HIP_TRY(hipEventCreate(&rec.e0));

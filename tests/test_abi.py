@@ -86,6 +86,13 @@ def test_degenerate_sizes_return_zero_without_device(L):
     assert L.sm_count_dev(t, 3, p, 4, ctypes.byref(c), None) == SM_OK and c.value == 0
 
 
+def test_prof_enable_stride(L):
+    from paper_1012_2547_amd._native import SM_EINVAL, SM_OK
+    assert L.sm_prof_enable(-1) == SM_EINVAL
+    for k in (0, 1, 8, 0):
+        assert L.sm_prof_enable(k) == SM_OK
+
+
 def test_batch_write_policy_range(L):
     from paper_1012_2547_amd._native import SM_EINVAL, SM_OK
     for v in (0, 1, 2, 3):

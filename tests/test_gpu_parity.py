@@ -421,6 +421,32 @@ def test_workspace_reuse_across_calls(sm):
         assert np.array_equal(out[:want.size].cpu().numpy(), want), (i, n, m, algo)
 
 
+@pytest.mark.parametrize("sigma", [4, 256])
+def test_shared_workspace_upto(sm, sigma):
+    """One workspace of exactly workspace_size_upto(n, M) bytes serves every length 1..M
+    with the planner's own choices (which differ in lane width from length to length),
+    as a corpus (measured sigma) and as a plain text (sigma estimated from the pattern)."""
+    t_np = dg.uniform_text(200_003, sigma, seed=31)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    M = 160
+    need = sm.workspace_size_upto(t_np.size, M)
+    assert need >= max(sm.workspace_size(t_np.size, m) for m in range(1, M + 1))
+    work = torch.empty(need, dtype=torch.uint8, device=DEV)
+    c = sm.Corpus(t_dev)
+    dc = torch.zeros(1, dtype=torch.int64, device=DEV)
+    for m in range(1, M + 1):
+        p, _ = dg.substring_pattern(t_np, m, seed=5, idx=m)
+        want = oracle.find_all(t_np, p)
+        out = torch.empty(max(want.size, 1), dtype=torch.int64, device=DEV)
+        c.find_all_async(p, out[:want.size], dc, work)
+        assert int(dc.item()) == want.size, m
+        assert np.array_equal(out[:want.size].cpu().numpy(), want), m
+        sm.find_all_async(t_dev, p, out[:want.size], dc, work)
+        assert int(dc.item()) == want.size, m
+        assert np.array_equal(out[:want.size].cpu().numpy(), want), m
+    c.close()
+
+
 def test_corpus_async_paths(sm):
     """Corpus queries planned with the measured sigma_eff (zipf and uniform texts)."""
     for t_np in (dg.zipf_text(300_000, 64, 1.0, seed=3), dg.uniform_text(300_000, 2, seed=3)):
