@@ -103,11 +103,14 @@ def test_batch_find_all_in_small_waves(sm):
     c.close()
 
 
-@pytest.mark.parametrize("slots,max_batch,pool,host,graphs", [(2, 64, 0, 0, True), (2, 64, 0, 0, False),
-                                                              (1, 7, 1 << 16, 1 << 16, True),
-                                                              (3, 256, 8 * 5000 * 3, 1 << 20, True)])
-def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host, graphs):
-    sm.batch_set_write_policy(2 if slots == 3 else 0)
+@pytest.mark.parametrize("slots,max_batch,pool,host,graphs,policy", [(2, 64, 0, 0, True, 0), (2, 64, 0, 0, False, 0),
+                                                                     (1, 7, 1 << 16, 1 << 16, True, 0),
+                                                                     (3, 256, 8 * 5000 * 3, 1 << 20, True, 2),
+                                                                     (2, 32, 8 * 10000 * 2, 1 << 20, True, 3)])
+def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host, graphs, policy):
+    """Policy 3 sends every pattern of at most 64 bytes through the single-pattern
+    pipeline in each write wave (waves launched directly, the others from graphs)."""
+    sm.batch_set_write_policy(policy)
     texts = corpora_small()
     srv = sm.Server(pool_bytes=pool, host_bytes=host, max_batch=max_batch, slots=slots, graphs=graphs)
     cs = [sm.Corpus(t) for t in texts]
