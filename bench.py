@@ -87,6 +87,9 @@ def main():
                     help="comma-separated subset of the sweep's alphabet sizes (profiling runs)")
     ap.add_argument("--ms", type=str, default="",
                     help="comma-separated subset of the sweep's pattern lengths (profiling runs)")
+    ap.add_argument("--no-skewed", action="store_true",
+                    help="skip the skewed (Zipf) and adversarial (a^n) texts")
+    ap.add_argument("--skewed-n-log2", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--batched-n-log2", type=int, default=32)
     ap.add_argument("--batched-patterns", type=int, default=4096)
@@ -268,6 +271,10 @@ def main():
         if mismatches:
             raise SystemExit("full-size parity failed on %d patterns" % mismatches)
 
+    skewed = None
+    if not args.no_skewed:
+        skewed = skewed_section(args, dev, stream)
+
     batched = None
     if not args.no_batched:
         del corpora
@@ -299,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "cells_gbs": cell_gbs,
         "sigma_eff": sigma_eff,
+        "skewed": skewed,
         "batched": batched,
         "serving": serving,
         "paper_context": PAPER_CONTEXT,
@@ -306,6 +314,109 @@ def main():
     if batched_waves is not None:
         res["batched_find_all"] = batched_waves
     print(json.dumps(res), flush=True)
+
+
+def skewed_section(args, dev, stream):
+    """Skewed and adversarial texts at n = 2^30, m in {4, 16, 64, 256}:
+    (a) order-0 Zipf(s=1.0) over 64 symbols (text seed 1), 20 substring patterns per m
+        (pattern seed 2): text GB/s per m, find_all totals equal to count-pass totals;
+    (b) t = a^n with b at every index = 4095 mod 4096, p = a^(m-1) b: exactly 2^18 hits, at
+        4096 k + 4096 - m;
+    (c) t = a^n, p = a^m: n - m + 1 hits (8 GiB of positions), at 0 .. n - m.
+    (b) and (c) are checked against their closed forms on the device; each is timed over 3
+    calls after one warm-up, and reports text GB/s and (n + 8 occ)/t."""
+    import numpy as np
+    import torch
+
+    import datagen as dg
+    import paper_1012_2547_amd as sm
+
+    n = 1 << args.skewed_n_log2
+    ms = (4, 16, 64, 256)
+    work = torch.empty(sm.workspace_size_upto(n, max(ms)), dtype=torch.uint8, device=dev)
+    dc = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def timed(corpus, pats, out, reps=1):
+        for p in pats[:2]:
+            corpus.find_all_async(p, out, dc, work, None, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            for p in pats:
+                corpus.find_all_async(p, out, dc, work, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    res = {}
+    # (a) Zipf
+    h = dg.zipf_text(n, 64, 1.0, seed=TEXT_SEED)
+    text = torch.from_numpy(h).to(dev)
+    c = sm.Corpus(text)
+    sig = c.stats()[2]
+    cells = {}
+    for m in ms:
+        pats = [dg.substring_pattern(h, m, seed=PAT_SEED, idx=j)[0] for j in range(args.per_cell)]
+        cnt = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+        for k, p in enumerate(pats):
+            c.count_async(p, cnt[k:k + 1], work, None, stream)
+        torch.cuda.synchronize()
+        counts = cnt.cpu().numpy()
+        out = torch.empty(max(int(counts.max()), 1), dtype=torch.int64, device=dev)
+        fcnt = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+        for k, p in enumerate(pats):
+            c.find_all_async(p, out, fcnt[k:k + 1], work, None, stream)
+        torch.cuda.synchronize()
+        if not np.array_equal(fcnt.cpu().numpy(), counts):
+            raise SystemExit("zipf text: find_all totals differ from count totals at m = %d" % m)
+        dt = timed(c, pats, out)
+        cells["m%d" % m] = {"gbs": round(n * len(pats) / dt / 1e9, 1),
+                            "mean_occ": int(counts.mean()),
+                            "algo": sm.plan_query(pats[0], sm.opts(sigma_hint=int(round(sig))))["algo"]}
+        del out
+    c.close()
+    del text, h
+    res["zipf64_s1"] = {"sigma_eff": round(sig, 2), "cells": cells}
+    # (b) and (c): one resident text of 'a' bytes, then b every 4096 bytes
+    text = torch.full((n,), 0x61, dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+
+    def check(cnt_want, first, step):
+        got = int(dc.item())
+        if got != cnt_want:
+            return False
+        chunk = 1 << 27
+        for a in range(0, got, chunk):
+            b = min(got, a + chunk)
+            want = torch.arange(a, b, dtype=torch.int64, device=dev) * step + first
+            if not torch.equal(out[a:b], want):
+                return False
+        return True
+
+    for name, periodic in (("a_n", False), ("a_n_with_b_every_4096", True)):
+        if periodic:
+            text[4095::4096] = 0x62
+        c = sm.Corpus(text)
+        cells = {}
+        for m in ms:
+            p = b"a" * (m - 1) + b"b" if periodic else b"a" * m
+            occ = n // 4096 if periodic else n - m + 1
+            dt = timed(c, [p], out[:occ], reps=3)
+            c.find_all_async(p, out[:occ], dc, work, None, stream)
+            torch.cuda.synchronize()
+            ok = check(occ, 4096 - m, 4096) if periodic else check(occ, 0, 1)
+            if not ok:
+                raise SystemExit("%s: positions differ from the closed form at m = %d" % (name, m))
+            cells["m%d" % m] = {"gbs": round(n / dt / 1e9, 1), "occ": occ,
+                                "algorithmic_gbs": round((n + 8 * occ) / dt / 1e9, 1)}
+        c.close()
+        res[name] = {"closed_form_parity": True, "cells": cells}
+    del text, out
+    log("skewed: zipf %s; a^n with b: %s; a^n: %s" % (
+        {k: v["gbs"] for k, v in res["zipf64_s1"]["cells"].items()},
+        {k: v["gbs"] for k, v in res["a_n_with_b_every_4096"]["cells"].items()},
+        {k: v["algorithmic_gbs"] for k, v in res["a_n"]["cells"].items()}))
+    return res
 
 
 def batched_section(args, dev, stream):

@@ -54,7 +54,11 @@ typedef struct sm_corpus sm_corpus;
 /* Scan algorithms (paper, Figs. 1 and 3). SM_ALGO_AUTO lets the planner choose. */
 enum sm_algo {
     SM_ALGO_AUTO = 0,
-    SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel, m <= 64 (Fig. 3) */
+    SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel (Fig. 3), one step per text byte;
+                              for m > 64 the pattern's last 64 bytes are scanned and the first
+                              m - 64 verified (a start one period, <= 64, after an occurrence
+                              without reading): linear on texts of one symbol, where the
+                              planner takes it for every m */
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */
     SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
     SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
@@ -67,8 +71,8 @@ enum sm_algo {
 
 /*
  * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
- * Options change speed only, never results. Invalid combinations (a bit-parallel
- * algorithm with m > 64, the block filter with m outside [144, 4096], brute force with
+ * Options change speed only, never results. Invalid combinations (BNDM or SBNDM
+ * with m > 64, the block filter with m outside [144, 4096], brute force with
  * m > 8, q > m or
  * q > 16, lane_bytes not in {16,32,64,128}, hbits outside [8,12]) are SM_EINVAL.
  * lane_bytes, q and hbits do not apply to the block filter (its tile is the

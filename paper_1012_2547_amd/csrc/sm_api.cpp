@@ -205,9 +205,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     if (o->algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M))
         return fail(SM_EINVAL, "the block filter needs %d <= m <= %d (m = %llu)", BF_MIN_M, BF_MAX_M,
                     (unsigned long long)m);
-    if (o->algo != ALGO_AUTO && o->algo != ALGO_HASHQ && o->algo != ALGO_BLOCK && m > BP_MAX_M)
-        return fail(SM_EINVAL, "bit-parallel algorithms need m <= %d (m = %llu)", BP_MAX_M,
-                    (unsigned long long)m);
+    if ((o->algo == ALGO_BNDM || o->algo == ALGO_SBNDM) && m > BP_MAX_M)
+        return fail(SM_EINVAL, "BNDM and SBNDM need m <= %d (m = %llu)", BP_MAX_M, (unsigned long long)m);
     if (o->q && (uint64_t)o->q > m)
         return fail(SM_EINVAL, "q = %d exceeds m = %llu", o->q, (unsigned long long)m);
 
@@ -226,7 +225,15 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     if (have && te.algo == ALGO_HASHQ && te.q && (uint64_t)te.q > m) algo = 0;
     // the block filter expects varied 16-byte blocks: not on a text of (nearly) one symbol
     if (algo == ALGO_BLOCK && sigma < 2) algo = 0;
-    const bool use_entry = algo != 0 && (o->algo == ALGO_AUTO || o->algo == algo);
+    // on such a text every window of a skip algorithm can match up to m - 1 bytes before
+    // it shifts by one (O(nm), the adversarial case of the paper's window-based families);
+    // Shift-And takes one step per byte whatever the text (for m > 64 on the pattern's
+    // last 64 bytes, the first m - 64 verified, once per period on a periodic run)
+    bool use_entry = algo != 0 && (o->algo == ALGO_AUTO || o->algo == algo);
+    if (sigma < 2 && o->algo == ALGO_AUTO && algo != ALGO_SHIFT_AND) {
+        algo = ALGO_SHIFT_AND;
+        use_entry = false;
+    }
     if (o->algo != ALGO_AUTO) algo = o->algo;
     if (algo == 0) {  // heuristic when no table entry applies
         if (m <= 12) algo = ALGO_SHIFT_AND;

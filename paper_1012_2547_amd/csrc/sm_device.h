@@ -406,6 +406,41 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
     return true;
 }
 
+// Shift-And for m > 64 (its suffix form): the scan finds the pattern's last 64
+// bytes; each such start g is an occurrence when the first m - 64 bytes match too,
+// read from global memory. A start exactly one period (<= 64) after the lane's
+// previous occurrence needs no reading: bytes [0, m - period) repeat that
+// occurrence shifted by the period, and the rest lie inside the 64-byte suffix
+// (the memory idea of Apostolico-Giancarlo and Turbo-BM, Fig. 1). Starts come in
+// ascending order; they are passed on to the emitter o.
+template <class E>
+struct SuffixVerify {
+    E &o;
+    const uint8_t *text0, *pat;
+    uint32_t m, period;    // period: the smallest when <= 64, else 0
+    uint64_t s;            // tile start (global start of tile-relative start 0)
+    uint64_t last = ~0ull; // this lane's last occurrence
+    uint32_t n = 0;
+    __device__ __forceinline__ void put(int rel)
+    {
+        const uint64_t g = s + (uint64_t)rel;
+        bool ok = period != 0 && last != ~0ull && g - last == period;
+        if (!ok) {
+            ok = true;
+            const uint32_t len = m - (uint32_t)BP_MAX_M;
+            for (uint32_t off = 0; off < len && ok; off += 16)
+                ok = verify_lane16(text0, g, pat, m, off, len - off < 16 ? len - off : 16);
+        }
+        if (ok) {
+            o.put(rel);
+            last = g;
+            n++;
+        }
+    }
+    __device__ __forceinline__ bool saturated() const { return false; }
+    __device__ __forceinline__ void add(uint32_t) {}
+};
+
 // Brute force (Fig. 1, BF) over packed bytes, m <= BRUTE_MAX_M. For the four
 // starts of a text word, word k of the text shifted by k bytes is compared with
 // p[k] replicated in all four bytes (pw[k]); a start matches when its byte is
@@ -768,11 +803,14 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
 {
     const int tid = threadIdx.x;
     if (algo == ALGO_SHIFT_AND) {
-        // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear
+        // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear. A
+        // pattern longer than 64 bytes is scanned for its last 64 bytes.
         const uint32_t c = tid;
+        const uint32_t ms = m < (uint32_t)BP_MAX_M ? m : (uint32_t)BP_MAX_M;
+        const uint8_t *ps = pp + (m - ms);
         uint64_t w = 0;
-        for (uint32_t j = 0; j < m; j++)
-            if (pp[j] != c) w |= 1ull << j;
+        for (uint32_t j = 0; j < ms; j++)
+            if (ps[j] != c) w |= 1ull << j;
         P->mask[c] = w;
     } else if (algo == ALGO_BNDM || algo == ALGO_SBNDM) {
         const uint32_t c = tid;

@@ -105,7 +105,7 @@ def test_batch_write_policy_range(L):
 def test_invalid_options(L):
     import paper_1012_2547_amd as sm
     with pytest.raises(sm.SmError):
-        sm.plan_query(b"a" * 65, sm.opts(algo=sm.ALGO_SHIFT_AND))   # bit-parallel needs m <= 64
+        sm.plan_query(b"a" * 65, sm.opts(algo=sm.ALGO_BNDM))        # BNDM needs m <= 64
     with pytest.raises(sm.SmError):
         sm.plan_query(b"abc", sm.opts(algo=sm.ALGO_HASHQ, q=4))       # q > m
     with pytest.raises(sm.SmError):
@@ -131,6 +131,21 @@ def test_planner_choices(L):
     assert sm.plan_query(bytes(range(4)) * 25)["algo"] != "block"  # m = 100 < 144
     f = sm.plan_query(b"x" * 30, sm.opts(algo=sm.ALGO_BNDM, lane_bytes=32))
     assert f["algo"] == "bndm" and f["lane_bytes"] == 32
+
+
+def test_one_symbol_texts_plan_shift_and(L):
+    """On a text of (nearly) one symbol (sigma 1) the planner takes Shift-And (for m > 64 its
+    suffix form), whatever the table says for sigma <= 2: skip algorithms degrade to O(nm)
+    there."""
+    import paper_1012_2547_amd as sm
+    for p in (b"a" * 63 + b"b", b"a" * 40, b"ab" * 16):
+        assert sm.plan_query(p, sm.opts(sigma_hint=1))["algo"] == "shift_and", p[:4]
+        assert sm.plan_query(p, sm.opts(sigma_hint=2))["algo"] != "shift_and" or len(p) < 32
+    assert sm.plan_query(b"a" * 64)["algo"] == "shift_and"      # sigma estimated from the pattern: 1
+    assert sm.plan_query(b"a" * 200, sm.opts(sigma_hint=1))["algo"] == "shift_and"  # suffix form
+    assert sm.plan_query(b"ab" * 100, sm.opts(sigma_hint=2))["algo"] != "shift_and"
+    f = sm.plan_query(b"a" * 50, sm.opts(algo=sm.ALGO_BNDM, sigma_hint=1))
+    assert f["algo"] == "bndm"                                   # explicit choices are kept
 
 
 def test_workspace_size_monotone(L):
@@ -186,7 +201,7 @@ def test_tuning_table_roundtrip(L):
     try:
         assert sm.plan_query(b"abcdefgh")["algo"] == "sbndm"
         assert sm.plan_query(b"abcdefgh")["lane_bytes"] == 32
-        assert sm.plan_query(b"x" * 100)["algo"] == "hashq"  # no entry: heuristic
+        assert sm.plan_query(bytes(range(100)))["algo"] == "hashq"  # no entry: heuristic
     finally:
         sm.tune_set([])
     assert sm.tune_get() == base

@@ -422,6 +422,75 @@ def test_workspace_reuse_across_calls(sm):
 
 
 @pytest.mark.parametrize("sigma", [4, 256])
+def _suffix_check(sm, t_np, pats, lanes=(16, 64, 128), tpws=(1, 2)):
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    for p in pats:
+        want = oracle.find_all(t_np, p)
+        for lane in lanes:
+            for tpw in tpws:
+                got, total = gpu_find(sm, t_dev, p, algo=1, lane=lane, tpw=tpw)
+                assert total == want.size, (len(p), lane, tpw)
+                assert np.array_equal(got, want), (len(p), lane, tpw)
+        # truncated output: the sorted prefix
+        if want.size > 3:
+            got, total = gpu_find(sm, t_dev, p, algo=1, cap=want.size // 2)
+            assert total == want.size and np.array_equal(got, want[:want.size // 2])
+
+
+@pytest.mark.parametrize("sigma", [2, 4, 256])
+def test_shift_and_suffix_form_random(sm, sigma):
+    """Shift-And with m > 64 (the last 64 bytes scanned, the first m - 64 verified), forced,
+    on i.i.d. texts: substring and random patterns, ragged tails."""
+    t_np = dg.uniform_text(300_007, sigma, seed=41 + sigma)
+    pats = [dg.substring_pattern(t_np, m, seed=6, idx=m)[0] for m in (65, 66, 80, 127, 128, 200, 1000, 3000)]
+    pats += [dg.random_pattern(m, sigma, seed=6, idx=m) for m in (65, 300)]
+    pats.append(bytes(t_np[-150:]))                               # occurrence ending at the text end
+    pats.append(bytes(t_np[:70]))                                 # occurrence at 0
+    _suffix_check(sm, t_np, pats)
+
+
+def test_shift_and_suffix_form_periodic(sm):
+    """The period rule (a start one period <= 64 after an occurrence is accepted without
+    reading) on periodic texts and patterns, and its absence for a period > 64."""
+    n = 200_003
+    a_n = np.full(n, ord("a"), dtype=np.uint8)
+    _suffix_check(sm, a_n, [b"a" * m for m in (65, 100, 500)] + [b"a" * 99 + b"b", b"b" + b"a" * 99])
+    gaps = a_n.copy()
+    gaps[96::97] = ord("b")                                        # b every 97 bytes
+    _suffix_check(sm, gaps, [b"a" * 96 + b"b" + b"a" * 40, b"a" * 96 + b"b" + b"a" * 96 + b"b",
+                             b"a" * 70, b"a" * 5 + b"b" + b"a" * 96 + b"b" + b"a" * 3,
+                             b"a" * 30 + b"b" + b"a" * 60], lanes=(16, 64), tpws=(1,))
+    ab = np.frombuffer(b"ab" * (n // 2), dtype=np.uint8).copy()
+    _suffix_check(sm, ab, [b"ab" * 50, b"ab" * 50 + b"a", b"ba" * 60, b"ab" * 40 + b"b"], lanes=(64,), tpws=(1, 2))
+    unit = dg.random_pattern(70, 4, seed=8, idx=0)                 # period 70 > 64: no shortcut
+    per = np.frombuffer(unit * (n // 70 + 1), dtype=np.uint8)[:n].copy()
+    _suffix_check(sm, per, [unit * 3, unit * 2 + unit[:10], unit[5:] + unit * 2], lanes=(64,), tpws=(1,))
+    # m = n, and a pattern longer than the text
+    _suffix_check(sm, ab[:300], [bytes(ab[:300]), bytes(ab[:299]) + b"b"], lanes=(16,), tpws=(1,))
+    t_dev = torch.from_numpy(ab[:100]).to(DEV)
+    assert gpu_find(sm, t_dev, b"ab" * 60, algo=1)[1] == 0
+
+
+def test_one_symbol_texts_planned(sm):
+    """The planner's own choice on corpora of one symbol (sigma_eff 1): every m, closed forms."""
+    n = 1 << 20
+    t_np = np.full(n, ord("a"), dtype=np.uint8)
+    t_np[4095::4096] = ord("b")
+    c = sm.Corpus(t_np)
+    for m in (4, 16, 64, 65, 256, 1000):
+        p = b"a" * (m - 1) + b"b"
+        pos = c.find_all(p)
+        assert np.array_equal(pos, np.arange(n // 4096, dtype=np.int64) * 4096 + 4096 - m), m
+    c.close()
+    c = sm.Corpus(np.full(n, ord("a"), dtype=np.uint8))
+    for m in (64, 65, 256, 1000):
+        assert c.count(b"a" * m) == n - m + 1
+        pos = c.find_all(b"a" * m)
+        assert pos.size == n - m + 1 and pos[0] == 0 and pos[-1] == n - m and np.all(np.diff(pos) == 1)
+    c.close()
+
+
+@pytest.mark.parametrize("sigma", [4, 256])
 def test_shared_workspace_upto(sm, sigma):
     """One workspace of exactly workspace_size_upto(n, M) bytes serves every length 1..M
     with the planner's own choices (which differ in lane width from length to length),
