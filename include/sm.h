@@ -55,8 +55,8 @@ typedef struct sm_corpus sm_corpus;
 enum sm_algo {
     SM_ALGO_AUTO = 0,
     SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel (Fig. 3), one step per text byte;
-                              for m > 64 the pattern's last 64 bytes are scanned and the first
-                              m - 64 verified (a start one period, <= 64, after an occurrence
+                              for m > 49 the pattern's last 49 bytes are scanned and the first
+                              m - 49 verified (a start one period, <= 49, after an occurrence
                               without reading): linear on texts of one symbol, where the
                               planner takes it for every m */
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */

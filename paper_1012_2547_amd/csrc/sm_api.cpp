@@ -228,7 +228,7 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     // on such a text every window of a skip algorithm can match up to m - 1 bytes before
     // it shifts by one (O(nm), the adversarial case of the paper's window-based families);
     // Shift-And takes one step per byte whatever the text (for m > 64 on the pattern's
-    // last 64 bytes, the first m - 64 verified, once per period on a periodic run)
+    // last 49 bytes, the rest verified, once per period on a periodic run)
     bool use_entry = algo != 0 && (o->algo == ALGO_AUTO || o->algo == algo);
     if (sigma < 2 && o->algo == ALGO_AUTO && algo != ALGO_SHIFT_AND) {
         algo = ALGO_SHIFT_AND;
@@ -260,6 +260,9 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     // a tile of 256 * L starts expects 256 * L * sigma^-m hits on an i.i.d. text: at
     // most the stash (256) when sigma^m >= L; denser tiles go to the emit pass anyway
     p.slots = (double)m * std::log((double)sigma) >= std::log((double)p.lane_bytes) ? 1 : 0;
+    // the suffix form of Shift-And (m > 49) verifies each hit from global memory: lanes
+    // keep their first hits so that tiles with few hits are not scanned twice
+    if (algo == ALGO_SHIFT_AND && m > (uint64_t)SA_SUFFIX) p.slots = 1;
     return SM_OK;
 }
 

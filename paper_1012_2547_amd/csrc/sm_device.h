@@ -406,33 +406,44 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
     return true;
 }
 
-// Shift-And for m > 64 (its suffix form): the scan finds the pattern's last 64
-// bytes; each such start g is an occurrence when the first m - 64 bytes match too,
-// read from global memory. A start exactly one period (<= 64) after the lane's
-// previous occurrence needs no reading: bytes [0, m - period) repeat that
-// occurrence shifted by the period, and the rest lie inside the 64-byte suffix
+// Shift-And for m > SA_SUFFIX (its suffix form): the scan finds the pattern's last
+// SA_SUFFIX bytes; each such start g is an occurrence when the first m - SA_SUFFIX
+// bytes match too, read from global memory. A start exactly one period (<=
+// SA_SUFFIX) after the lane's previous occurrence needs no reading: bytes [0, m -
+// period) repeat that occurrence shifted by the period, and the rest lie inside the suffix
 // (the memory idea of Apostolico-Giancarlo and Turbo-BM, Fig. 1). Starts come in
 // ascending order; they are passed on to the emitter o.
 template <class E>
 struct SuffixVerify {
     E &o;
     const uint8_t *text0, *pat;
-    uint32_t m, period;    // period: the smallest when <= 64, else 0
+    uint32_t m, period;    // period: the smallest when <= SA_SUFFIX, else 0
     uint64_t s;            // tile start (global start of tile-relative start 0)
+    int lo;                // the lane's first tile-relative start (bitmap emitters)
     uint64_t last = ~0ull; // this lane's last occurrence
     uint32_t n = 0;
     __device__ __forceinline__ void put(int rel)
     {
         const uint64_t g = s + (uint64_t)rel;
         bool ok = period != 0 && last != ~0ull && g - last == period;
-        if (!ok) {
+        if (!ok) {  // 64 bytes per round trip: four independent 16-byte loads of each
             ok = true;
-            const uint32_t len = m - (uint32_t)BP_MAX_M;
-            for (uint32_t off = 0; off < len && ok; off += 16)
-                ok = verify_lane16(text0, g, pat, m, off, len - off < 16 ? len - off : 16);
+            const uint32_t len = m - (uint32_t)SA_SUFFIX;
+            const uint8_t *tl = text0 + g + m - 1, *pl = pat + m + 15;
+            for (uint32_t off = 0; off < len && ok; off += 64) {
+                uint32_t d = 0;
+#pragma unroll
+                for (uint32_t k = 0; k < 4; k++) {
+                    const uint32_t o2 = off + 16 * k;
+                    if (o2 < len)
+                        d |= diff16(load16(text0 + g + o2, tl), load16(pat + o2, pl), len - o2 < 16 ? len - o2 : 16);
+                }
+                ok = d == 0;
+            }
         }
         if (ok) {
-            o.put(rel);
+            if constexpr (takes_masks<E>::value) o.put_mask(rel - lo, 1u);
+            else o.put(rel);
             last = g;
             n++;
         }
@@ -803,10 +814,11 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
 {
     const int tid = threadIdx.x;
     if (algo == ALGO_SHIFT_AND) {
-        // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear. A
-        // pattern longer than 64 bytes is scanned for its last 64 bytes.
+        // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear. With
+        // q_ = SA_SUFFIX (single-pattern suffix form, m > SA_SUFFIX) the masks are those
+        // of the pattern's last SA_SUFFIX bytes.
         const uint32_t c = tid;
-        const uint32_t ms = m < (uint32_t)BP_MAX_M ? m : (uint32_t)BP_MAX_M;
+        const uint32_t ms = (q_ == (uint32_t)SA_SUFFIX && m > q_) ? q_ : m;
         const uint8_t *ps = pp + (m - ms);
         uint64_t w = 0;
         for (uint32_t j = 0; j < ms; j++)

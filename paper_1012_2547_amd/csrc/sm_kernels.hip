@@ -66,9 +66,9 @@ struct ScanArgs {
     uint32_t *bits;       // find, bitmap form: hit bitmaps of the dense tiles (T / 32 words per tile)
     int64_t *out;         // emit: hit number k of the pattern goes to out[k - lo]
     uint64_t lo, cap;     // emit: window [lo, lo + cap) of hit numbers
-    // Shift-And for m > 64: text/n above are the text shifted by m - 64 and m above is
-    // 64 (the scan finds the pattern's last 64 bytes); text0 and m_full are the
-    // originals, for the verification of the first m - 64 bytes
+    // Shift-And for m > SA_SUFFIX: text/n above are the text shifted by m - SA_SUFFIX and m
+    // above is SA_SUFFIX (the scan finds the pattern's last SA_SUFFIX bytes); text0 and
+    // m_full are the originals, for the verification of the first m - SA_SUFFIX bytes
     const uint8_t *text0;
     uint32_t m_full;
 };
@@ -214,10 +214,11 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
 {
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if constexpr (ALGO == ALGO_SHIFT_AND) {
-        if constexpr (VAR == 5) {  // m > 64: the last 64 bytes, then the first m - 64 verified
+        if constexpr (VAR == 5) {  // m > SA_SUFFIX: the last SA_SUFFIX bytes, then the rest verified
+            static_assert(SA_SUFFIX - 1 + 16 <= 64, "hits checked every 16 bytes");
             SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full,
-                               period > 0 && period <= BP_MAX_M ? (uint32_t)period : 0u, s};
-            lane_shift_and<uint64_t, 1, true>(S.text, S.mask, m, li0, lo, hi, sv);
+                               period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u, s, lo};
+            lane_shift_and<uint64_t, 16, true>(S.text, S.mask, m, li0, lo, hi, sv);
             return sv.n;
         }
         if (VAR == 4)
@@ -1005,8 +1006,8 @@ hipError_t launch_t(const ScanArgs &a, uint32_t grid, hipStream_t st)
         else hipLaunchKernelGGL((count_kernel<ALGO, L, VAR, CM_COUNT, false>), dim3(grid), dim3(BLOCK), 0, st, a);
     } else if (KIND == K_FIND_COUNT) {
         // Shift-And: hit bitmaps, else (16-byte lanes) the lanes' first hits when sparse
-        // tiles are expected; the suffix form (m > 64) has no bitmap region
-        if constexpr (mask_hits(ALGO) && !(ALGO == ALGO_SHIFT_AND && VAR == 5)) {
+        // tiles are expected (the workspace has no bitmap region for m > 64)
+        if constexpr (mask_hits(ALGO)) {
             if (L >= 32 && a.bits) {
                 constexpr int LB = L >= 32 ? L : 32;
                 if (pf) hipLaunchKernelGGL((count_kernel<ALGO, LB, VAR, CM_BITS, true>), dim3(grid), dim3(BLOCK), 0, st, a);
@@ -1049,14 +1050,14 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
     case ALGO_SHIFT_AND: {
         const int m = (int)p.m;
         // variants: 4 = 32-bit state, byte masks (m <= 8); 0 = 32-bit state and masks;
-        // 1, 2, 3 = 64-bit state, hits checked every 16, 4 or 1 bytes; 5 = m > 64, the
-        // last 64 bytes scanned, the rest verified
-        if (m > BP_MAX_M) return launch_l<ALGO_SHIFT_AND, 5, KIND>(p, a, grid, st);
+        // 1 = 64-bit state, hits checked every 16 bytes (m <= 49); 5 = m > 49: the last
+        // SA_SUFFIX bytes scanned as variant 1 does, the rest verified (faster than
+        // checking hits every 4 or every byte, which m = 50..64 would need)
+        static_assert(SA_SUFFIX == 49, "variant 1 covers m <= 49");
+        if (m > SA_SUFFIX) return launch_l<ALGO_SHIFT_AND, 5, KIND>(p, a, grid, st);
         if (m <= 8) return launch_l<ALGO_SHIFT_AND, 4, KIND>(p, a, grid, st);
         if (m <= 17) return launch_l<ALGO_SHIFT_AND, 0, KIND>(p, a, grid, st);
-        if (m <= 49) return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
-        if (m <= 61) return launch_l<ALGO_SHIFT_AND, 2, KIND>(p, a, grid, st);
-        return launch_l<ALGO_SHIFT_AND, 3, KIND>(p, a, grid, st);
+        return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
     }
     case ALGO_BNDM: return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
     case ALGO_BRUTE: return launch_l<ALGO_BRUTE, 0, KIND>(p, a, grid, st);
@@ -1092,13 +1093,13 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
     a.slots = (uint32_t)plan.slots;
     a.bs = plan.algo == ALGO_BLOCK ? (uint32_t)plan.lane_bytes : 0u;
     a.ntiles = ntiles;
-    if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)BP_MAX_M) {  // suffix form (n >= m)
-        const uint64_t sh = plan.m - BP_MAX_M;
+    if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)SA_SUFFIX) {  // suffix form (n >= m)
+        const uint64_t sh = plan.m - SA_SUFFIX;
         a.text0 = d_text;
         a.m_full = (uint32_t)plan.m;
         a.text = d_text + sh;
         a.n = n - sh;
-        a.m = BP_MAX_M;
+        a.m = SA_SUFFIX;
     }
     return a;
 }
@@ -1123,6 +1124,7 @@ hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_para
     a.m = (uint32_t)plan.m;
     a.algo = (uint32_t)plan.algo;
     a.q = (uint32_t)plan.q;
+    if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)SA_SUFFIX) a.q = SA_SUFFIX;  // suffix masks
     a.hbits = (uint32_t)plan.hbits;
     if (plan.m <= PREP_INLINE) {
         a.inline_len = (uint32_t)plan.m;
@@ -1190,7 +1192,8 @@ hipError_t launch_find(const Plan &plan, const uint8_t *d_text, uint64_t n, cons
     a.out = d_out;
     a.lo = first;
     a.cap = cap;
-    // bitmap form for the mask-producing scans with lanes of >= 32 starts
+    // bitmap form for the mask-producing scans with lanes of >= 32 starts (the
+    // workspace holds the bitmap region for m <= 64 only)
     if ((plan.algo == ALGO_SHIFT_AND || plan.algo == ALGO_BRUTE) && plan.lane_bytes >= 32) a.bits = w.bits;
     const uint32_t g = count_grid(a);
     if (!g) return hipErrorInvalidValue;

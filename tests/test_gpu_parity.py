@@ -439,7 +439,7 @@ def _suffix_check(sm, t_np, pats, lanes=(16, 64, 128), tpws=(1, 2)):
 
 @pytest.mark.parametrize("sigma", [2, 4, 256])
 def test_shift_and_suffix_form_random(sm, sigma):
-    """Shift-And with m > 64 (the last 64 bytes scanned, the first m - 64 verified), forced,
+    """Shift-And with m > 64 (the last 49 bytes scanned, the first m - 49 verified), forced,
     on i.i.d. texts: substring and random patterns, ragged tails."""
     t_np = dg.uniform_text(300_007, sigma, seed=41 + sigma)
     pats = [dg.substring_pattern(t_np, m, seed=6, idx=m)[0] for m in (65, 66, 80, 127, 128, 200, 1000, 3000)]
@@ -450,8 +450,8 @@ def test_shift_and_suffix_form_random(sm, sigma):
 
 
 def test_shift_and_suffix_form_periodic(sm):
-    """The period rule (a start one period <= 64 after an occurrence is accepted without
-    reading) on periodic texts and patterns, and its absence for a period > 64."""
+    """The period rule (a start one period <= 49 after an occurrence is accepted without
+    reading) on periodic texts and patterns, and its absence for longer periods."""
     n = 200_003
     a_n = np.full(n, ord("a"), dtype=np.uint8)
     _suffix_check(sm, a_n, [b"a" * m for m in (65, 100, 500)] + [b"a" * 99 + b"b", b"b" + b"a" * 99])
@@ -462,9 +462,10 @@ def test_shift_and_suffix_form_periodic(sm):
                              b"a" * 30 + b"b" + b"a" * 60], lanes=(16, 64), tpws=(1,))
     ab = np.frombuffer(b"ab" * (n // 2), dtype=np.uint8).copy()
     _suffix_check(sm, ab, [b"ab" * 50, b"ab" * 50 + b"a", b"ba" * 60, b"ab" * 40 + b"b"], lanes=(64,), tpws=(1, 2))
-    unit = dg.random_pattern(70, 4, seed=8, idx=0)                 # period 70 > 64: no shortcut
-    per = np.frombuffer(unit * (n // 70 + 1), dtype=np.uint8)[:n].copy()
-    _suffix_check(sm, per, [unit * 3, unit * 2 + unit[:10], unit[5:] + unit * 2], lanes=(64,), tpws=(1,))
+    for u in (49, 60, 70):                                         # the shortcut up to 49 only
+        unit = dg.random_pattern(u, 4, seed=8, idx=u)
+        per = np.frombuffer(unit * (n // u + 1), dtype=np.uint8)[:n].copy()
+        _suffix_check(sm, per, [unit * 3, unit * 2 + unit[:10], unit[5:] + unit * 2], lanes=(64,), tpws=(1,))
     # m = n, and a pattern longer than the text
     _suffix_check(sm, ab[:300], [bytes(ab[:300]), bytes(ab[:299]) + b"b"], lanes=(16,), tpws=(1,))
     t_dev = torch.from_numpy(ab[:100]).to(DEV)
