@@ -4,7 +4,7 @@ Workload (the headline configuration): for each alphabet size sigma in
 {2, 4, 16, 64, 256} a text of n = 2^30 i.i.d. uniform bytes over {0..sigma-1}
 (text seed 1), and for each m in {2, 4, ..., 1024} 20 patterns copied from
 random offsets of that text (pattern seed 2) -- the shape of the paper's
-Section 3 experiments at 2^30 bytes instead of 5 MB. One step = the whole sweep:
+Section 2 experiments at 2^30 bytes instead of 5 MB. One step = the whole sweep:
 1000 find_all calls (device text, device output; count -> tile scan -> emit), texts
 resident in HBM before timing starts.
 
@@ -30,8 +30,8 @@ PROF_EVERY = 8  # sweep calls per call whose kernels are timed with HIP events
 
 # The paper's own timings, as context only (other hardware, other text sizes): mean
 # search time of the best algorithm per pattern length on its uniform 4-symbol text
-# of 5e6 bytes, one core of an Intel Core2 at 1.66 GHz (Section 3; the Rand4 table of
-# Section 4), converted to GB/s = 5e6 / t.
+# of 5e6 bytes, one core of an Intel Core2 at 1.66 GHz (Section 2; its Rand4 table,
+# Section 2.2), converted to GB/s = 5e6 / t.
 PAPER_CONTEXT = {
     "hardware": "one core of an Intel Core2 at 1.66 GHz",
     "text": "uniform, 4 symbols, 5e6 bytes",

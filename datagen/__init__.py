@@ -10,7 +10,7 @@ Random numbers: a counter-based SplitMix64 stream. For a (seed, stream) pair,
 (multi-threaded, used for 2^30-byte texts); the numpy functions suffixed
 ``_np`` are its twin and are checked equal to it in the tests.
 
-Workload shapes follow the paper's experimental set-up (Section 3): i.i.d.
+Workload shapes follow the paper's experimental set-up (Section 2): i.i.d.
 uniform "Rand sigma" texts, patterns drawn as random substrings of the text, and
 pattern lengths m in {2, 4, ..., 1024}. The natural-language and biological
 files the paper uses are not available; order-0 Zipf texts and uniform texts

@@ -224,7 +224,7 @@ int sm_batch_set_write_policy(int policy);
 
 /*
  * Server: continuous batching of single-pattern queries over resident corpora
- * (the paper's workload, Section 3, one pattern per query, served many at a
+ * (the paper's workload, Section 2, one pattern per query, served many at a
  * time). Queries are queued per corpus; a scheduler thread batches the queued
  * queries of one corpus (oldest first, at most max_batch) through the batched
  * search on one of `slots` pipeline slots (own HIP stream, workspace and
@@ -318,7 +318,7 @@ int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_i
 
 /*
  * Corpus: a device-resident text reused across queries (the paper's fixed text
- * buffers, Section 3). sm_corpus_open copies a host text to the device
+ * buffers, Section 2). sm_corpus_open copies a host text to the device
  * (text_on_device = 0) or borrows a device pointer (text_on_device = 1; the
  * caller keeps it alive until close), and probes its byte histogram once; the
  * planner then uses the measured alphabet size. A corpus is immutable after

@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -30,19 +31,24 @@ def sources():
 def build(verbose: bool = False, asm: bool = False) -> str:
     bdir = os.path.join(ROOT, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in sources():
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append(cmd)
         objs.append(obj)
         if asm and src.endswith(".hip"):
             s = os.path.join(bdir, os.path.basename(src) + ".gfx950.s")
-            subprocess.check_call([HIPCC] + HIP_FLAGS + ["--cuda-device-only", "-S", src, "-o", s])
+            cmds.append([HIPCC] + HIP_FLAGS + ["--cuda-device-only", "-S", src, "-o", s])
+    # one compiler process per translation unit, at most JOBS at a time
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        list(ex.map(subprocess.check_call, cmds))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -1,6 +1,6 @@
 // Batched multi-pattern search: P patterns against one resident text.
 //
-// The paper's experiments search one pattern at a time (Section 3); serving many
+// The paper's experiments search one pattern at a time (Section 2); serving many
 // patterns over the same text on a GPU wants the text read once for many
 // patterns instead. Patterns are sorted by kernel variant (algorithm, state width
 // or q-gram words) and length, and cut into groups whose tables fit a fixed LDS

@@ -1,7 +1,7 @@
 // Serving layer: continuous batching of single-pattern queries over resident
 // corpora.
 //
-// The paper times one pattern against a text already in memory (Section 3); a
+// The paper times one pattern against a text already in memory (Section 2); a
 // server sees a stream of such queries against a few large resident texts. The
 // scheduler thread groups the queued queries of one corpus into a batch (the
 // corpus whose oldest query arrived first goes next) and runs it through the

@@ -6,7 +6,7 @@ BNDM, SBNDM, Hash-q with its gram length q, the block filter, brute force), star
 and tiles per workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
 benchmark's seed 1) with substring patterns, as whole find_all calls. The
 fastest configuration of each cell becomes a table entry. The paper's own
-summary (Section 4) says the best algorithm depends on exactly these two
+summary (Section 3) says the best algorithm depends on exactly these two
 quantities; this measures that map on MI355X.
 
     python -m paper_1012_2547_amd.tune --out tune_out --n-log2 30   # on a GPU
