@@ -156,6 +156,31 @@ int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64
                    void *stream);
 
 /*
+ * sm_find_all_noalloc -- for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same search as sm_find_all_async, with the workspace taken from a static device
+ * array of SM_NOALLOC_SCRATCH_BYTES held by the library on every device it runs on
+ * until the process ends. The call makes no hipMalloc, hipFree, pinned-memory or
+ * other allocating call; it only enqueues kernels on `stream`.
+ *   d_text[n]: device bytes.  pat[m]: HOST bytes, m <= 3072 (captured into kernel
+ *   arguments, so the host buffer may be reused at once).  d_out[cap]: device
+ *   int64, the first min(cap, total) positions.  *d_count: device uint64, the
+ *   total, written in stream order.  opts: as sm_find_all_async (NULL = planner).
+ * Errors: the arguments of sm_find_all_async; m > 3072, or an (n, m, lanes) whose
+ * workspace (sm_workspace_size) exceeds SM_NOALLOC_SCRATCH_BYTES, is SM_EINVAL
+ * before any device work (at the planner's lanes, n up to 2^30 fits every m).
+ * Every call on one device shares that device's array and leaves its contents
+ * behind (the next call needs none of them): two calls that may overlap in time
+ * on the same device -- different streams, threads or graph replays running
+ * concurrently -- race on it and give wrong results. Serialize them (one stream,
+ * or events between them).
+ */
+#define SM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int sm_find_all_noalloc(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                        int64_t *d_out, uint64_t cap, uint64_t *d_count, const sm_opts *opts,
+                        void *stream);
+
+/*
  * Batched search: P patterns against one corpus, the text streamed once per
  * group of patterns instead of once per pattern (kernels and grouping in the
  * package's csrc/sm_batch.*). Patterns are concatenated in pats; pattern i is

@@ -18,7 +18,7 @@ from ._native import (ALGO_AUTO, ALGO_BLOCK, ALGO_BNDM, ALGO_BRUTE, ALGO_HASHQ, 
                       ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError,
                       TuneEntry, check, last_error, load)
 
-__all__ = ["pack_patterns", "find_all", "count", "find_all_async", "count_async", "workspace_size", "plan_query",
+__all__ = ["pack_patterns", "find_all", "count", "find_all_async", "find_all_noalloc", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
            "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_BLOCK", "ALGO_BRUTE", "ALGO_NAMES", "version",
            "Batch", "Server", "batch_set_wave_bytes", "batch_set_write_policy", "now_ns", "workspace_size_upto"]
@@ -85,6 +85,17 @@ def find_all_async(text, pat, out, d_count, work, o: Opts | None = None, stream=
         ctypes.c_void_p(out.data_ptr() if out is not None and out.numel() else 0),
         out.numel() if out is not None else 0, ctypes.c_void_p(d_count.data_ptr()),
         ctypes.c_void_p(work.data_ptr()), work.numel(),
+        ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
+
+
+def find_all_noalloc(text, pat, out, d_count, o: Opts | None = None, stream=None) -> int:
+    """As find_all_async, with the library's static device scratch as workspace (no
+    allocation; calls on one device must not overlap in time)."""
+    b, m = _pat(pat)
+    return check(load().sm_find_all_noalloc(
+        ctypes.c_void_p(text.data_ptr()), text.numel(), _pat_ptr(b), m,
+        ctypes.c_void_p(out.data_ptr() if out is not None and out.numel() else 0),
+        out.numel() if out is not None else 0, ctypes.c_void_p(d_count.data_ptr()),
         ctypes.byref(o) if o is not None else None, _stream_ptr(stream)))
 
 

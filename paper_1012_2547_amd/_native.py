@@ -91,6 +91,7 @@ PROTOTYPES = {
     "sm_find_all_async": (_i32, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _vp, _u64,
                                  ctypes.POINTER(Opts), _vp]),
     "sm_count_async": (_i32, [_vp, _u64, _vp, _u64, _vp, _vp, _u64, ctypes.POINTER(Opts), _vp]),
+    "sm_find_all_noalloc": (_i32, [_vp, _u64, _vp, _u64, _vp, _u64, _vp, ctypes.POINTER(Opts), _vp]),
     "sm_plan_query": (_i32, [_vp, _u64, ctypes.POINTER(Opts), ctypes.POINTER(PlanInfo)]),
     "sm_corpus_open": (_i32, [_vp, _u64, _i32, ctypes.POINTER(_vp)]),
     "sm_corpus_close": (_i32, [_vp]),

@@ -386,7 +386,7 @@ extern "C" uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_
 static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
                      int64_t *d_out, uint64_t cap, uint64_t *d_count, void *d_work,
                      uint64_t work_bytes, const sm_opts *opts, hipStream_t st, bool write,
-                     int sigma_known, uint64_t first = 0)
+                     int sigma_known, uint64_t first = 0, bool may_profile = true)
 {
     int r = validate_common(d_text, n, pat, m);
     if (r) return r;
@@ -421,7 +421,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
     ProfRec rec{};
     {
         std::lock_guard<std::mutex> g(g_prof_mu);
-        prof = g_prof_every && g_prof_seen++ % g_prof_every == 0;
+        prof = may_profile && g_prof_every && g_prof_seen++ % g_prof_every == 0;
     }
     if (prof) {
         HIP_TRY(hipEventCreate(&rec.e0));
@@ -462,6 +462,70 @@ extern "C" int sm_count_async(const uint8_t *d_text, uint64_t n, const uint8_t *
 {
     return run_async(d_text, n, pat, m, nullptr, 0, d_count, d_work, work_bytes, opts,
                      (hipStream_t)stream, false, 0);
+}
+
+// ---------------------------------------------------------------------------
+// find_all without allocation: the workspace is a static device array
+// ---------------------------------------------------------------------------
+// Every device the library runs on holds its own copy of this array (code-object
+// memory) until the process ends. In host code its name is only a host-side stand-in:
+// kernels take the per-device address from hipGetSymbolAddress instead.
+static __device__ __align__(256) uint8_t scratch[SM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];  // per device: device address of `scratch`, once looked up
+
+// Device address of the current device's scratch array (looked up once per device,
+// with that device current).
+int static_scratch(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(SM_EDEVICE, "device %d: the static scratch is tracked for devices 0..%d only", dev,
+                    kScratchDevices - 1);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SM_EDEVICE, "hipGetSymbolAddress returned NULL for the static scratch");
+        if (((uintptr_t)p & 255) != 0) return fail(SM_EDEVICE, "static scratch is not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SM_OK;
+}
+}  // namespace
+
+extern "C" int sm_find_all_noalloc(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint64_t m,
+                                   int64_t *d_out, uint64_t cap, uint64_t *d_count,
+                                   const sm_opts *opts, void *stream)
+{
+    int r = validate_common(d_text, n, pat, m);
+    if (r) return r;
+    if (!d_count) return fail(SM_EINVAL, "d_count is NULL");
+    if (!d_out && cap > 0) return fail(SM_EINVAL, "output is NULL with cap > 0");
+    if (m > (uint64_t)PREP_INLINE)
+        return fail(SM_EINVAL, "sm_find_all_noalloc takes patterns of at most %d bytes (m = %llu)",
+                    PREP_INLINE, (unsigned long long)m);
+    Plan plan;
+    if ((r = make_plan(pat, m, opts, 0, plan))) return r;
+    if (n > 0 && m <= n) {
+        const uint64_t need = ws_layout(n, m, tile_starts(plan)).need;
+        if (need > (uint64_t)SM_NOALLOC_SCRATCH_BYTES)
+            return fail(SM_EINVAL,
+                        "sm_find_all_noalloc: n = %llu, m = %llu needs %llu bytes of workspace, more than "
+                        "the %llu bytes of static scratch; use sm_find_all_async with a caller workspace",
+                        (unsigned long long)n, (unsigned long long)m, (unsigned long long)need,
+                        (unsigned long long)SM_NOALLOC_SCRATCH_BYTES);
+    }
+    if ((r = check_device())) return r;
+    void *ws = nullptr;
+    if ((r = static_scratch(&ws))) return r;
+    return run_async(d_text, n, pat, m, d_out, cap, d_count, ws, (uint64_t)SM_NOALLOC_SCRATCH_BYTES, opts,
+                     (hipStream_t)stream, true, 0, 0, false);
 }
 
 extern "C" int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts, sm_plan_info *info)
