@@ -99,7 +99,9 @@ def main():
     ap.add_argument("--serve-shift", type=int, default=0,
                     help="log2 scale of the serving corpora (0: 8, 2 and 4 GiB)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="trace length per arrival rate: min(20000, rate x seconds) queries")
+                    help="trace length per arrival rate: min(20000, max(2000, rate x seconds)) queries")
+    ap.add_argument("--serve-min-queries", type=int, default=2000,
+                    help="queries per arrival rate at least (so that p99 and p999 rest on many samples)")
     ap.add_argument("--serve-rates", type=str, default="250,1000,4000,16000")
     ap.add_argument("--plain-queries", type=int, default=1000,
                     help="queries of each trace (its prefix) replayed through the plain path")
@@ -592,7 +594,7 @@ def _pct(v, p):
 def serving_section(args, dev):
     """Open-loop serving: three resident corpora (uniform sigma=4 of 8 GiB seed 11,
     uniform sigma=20 of 2 GiB seed 12 (protein-like), Zipf(s=1.1) over 256 symbols
-    of 4 GiB seed 13); per arrival rate a Poisson trace of min(20000, rate x T)
+    of 4 GiB seed 13); per arrival rate a Poisson trace of min(20000, max(2000, rate x T))
     queries (seed 14 + rate index), corpus uniform, m log-uniform in [4, 256], even
     queries substrings of their corpus and odd ones i.i.d. random over its
     alphabet. Latency = arrival -> positions in host memory. The prefix of each
@@ -621,7 +623,7 @@ def serving_section(args, dev):
     rates = [float(x) for x in args.serve_rates.split(",") if x]
     traces = []
     for k, lam in enumerate(rates):
-        N = int(min(20000, max(1, round(lam * args.serve_seconds))))
+        N = int(min(20000, max(args.serve_min_queries, round(lam * args.serve_seconds))))
         seed = 14 + k
         arr = dg.poisson_arrivals(N, lam, seed)
         cs = dg.choices(N, len(corpora), seed)
@@ -719,7 +721,10 @@ def serving_section(args, dev):
             "pattern_GBps": round(st["text_bytes"] / span_s / 1e9, 1),
             "out_GBps": round(st["out_bytes"] / span_s / 1e9, 2),
             "batches": st["batches"], "mean_batch": round(float(bsz.mean()), 1),
-            "write_waves": st["write_waves"], "overflow_allocs": st["overflow_allocs"],
+            "write_waves": st["write_waves"], "deferred": st["deferred"], "evicted": st["evicted"],
+            "rejected": st["rejected"], "mem_waits": st["mem_waits"],
+            "host_peak_GiB": round(st["host_peak_bytes"] / 2**30, 3),
+            "host_arena_GiB": round(st["host_arena_bytes"] / 2**30, 3),
             "graph_launches": st["graph_launches"], "graph_builds": st["graph_builds"],
             "prefix": {"queries": K,
                        "server_p50_ms": round(_pct(lat[:K], 50) / 1e6, 3),

@@ -251,13 +251,23 @@ int sm_batch_set_write_policy(int policy);
  * Server: continuous batching of single-pattern queries over resident corpora
  * (the paper's workload, Section 2, one pattern per query, served many at a
  * time). Queries are queued per corpus; a scheduler thread batches the queued
- * queries of one corpus (oldest first, at most max_batch) through the batched
- * search on one of `slots` pipeline slots (own HIP stream, workspace and
- * pool_bytes / slots of device output staging), so the count pass of one batch
- * overlaps the writes and copies of the previous one. The exact output size
- * from the count step admits each batch: host result space comes from a pinned
- * arena of host_bytes (a dedicated pinned buffer when it does not fit) and the
- * positions are written in waves of at most the slot's staging size.
+ * queries of one corpus (oldest first, at most max_batch) onto any free one of
+ * `slots` pipeline slots (own HIP stream, workspace and pool_bytes / slots of
+ * device output staging) and starts the batch's count step; the next batch can be
+ * formed and counted while earlier ones are written and copied.
+ *
+ * Admission by memory: the count step gives every query's exact number of
+ * positions. Results live in one pinned host arena of host_bytes, the only
+ * pinned memory results ever take. Batches are admitted in dispatch order: the
+ * longest prefix of the batch whose positions fit the arena is written (in waves
+ * of at most the slot's staging size), the rest goes back to the front of its
+ * queue and is counted again later (`deferred`). When not even the first query
+ * fits, completed results that no caller has received yet are moved from the
+ * arena to pageable memory (`evicted`), oldest first; if that is not enough,
+ * admission waits until results are freed or batches complete. A query whose
+ * positions alone exceed host_bytes fails with SM_ENOMEM (`rejected`). A result
+ * returned by wait/poll stays where it is until sm_result_free; a caller that
+ * frees each result before waiting for the next never stalls admission for good.
  *
  * sm_server_create: zero fields take defaults (pool 16 GiB, host arena 2 GiB,
  *   max_batch 256, 2 slots, max_pending 2^20 queued queries, HIP graphs on); the
@@ -271,12 +281,14 @@ int sm_batch_set_write_policy(int policy);
  *   arrival time on sm_now_ns's clock (<= 0: now) and latency is measured from
  *   it. SM_EBUSY when max_pending queries are queued. Thread-safe.
  * sm_server_wait: waits up to timeout_us (< 0: forever) for the query; SM_OK
- *   with *res filled, SM_EBUSY if it is still running, or the query's error.
+ *   with *res filled, SM_EBUSY if it is still running, or the query's error
+ *   (SM_ENOMEM: its positions exceed the arena).
  *   res->positions (res->count entries, ascending) is library-owned host memory,
  *   valid until sm_result_free(ticket). sm_server_poll = wait with timeout 0.
  * sm_server_stats: latency percentiles (arrival to positions on the host) of
- *   the queries completed since the last reset, and throughput.
- * sm_server_destroy: drops queued queries, finishes dispatched ones, frees all.
+ *   the queries completed since the last reset, throughput and memory counters.
+ * sm_server_destroy: drops queued queries, finishes dispatched ones (a batch still
+ *   waiting for arena memory fails with SM_EBUSY), frees all.
  */
 typedef struct sm_server sm_server;
 typedef struct sm_server_config {
@@ -299,15 +311,22 @@ typedef struct sm_result {
 } sm_result;
 typedef struct sm_server_metrics {
     uint64_t completed, pending, batches, batched_queries;
-    uint64_t text_bytes;        /* sum over completed batches of n x queries (pattern-bytes) */
+    uint64_t text_bytes;        /* sum over admitted batches of n x queries (pattern-bytes) */
     uint64_t out_bytes;         /* positions written, bytes */
-    uint64_t write_waves, overflow_allocs;
+    uint64_t write_waves;
+    uint64_t deferred;          /* queries sent back to their queue: their positions did not fit the arena */
     int64_t p50_ns, p99_ns, p999_ns, max_ns;
     double mean_ns;
     int64_t span_ns;            /* first arrival to last completion */
     double qps;                 /* completed / span */
     uint64_t graph_launches;    /* graph launches (count steps and write waves) */
     uint64_t graph_builds;      /* of which needed a new executable (shape changed) */
+    uint64_t evicted;           /* results moved from the arena to pageable memory */
+    uint64_t evicted_bytes;
+    uint64_t rejected;          /* queries failed with SM_ENOMEM (positions alone exceed the arena) */
+    uint64_t mem_waits;         /* times admission waited for arena memory */
+    uint64_t host_peak_bytes;   /* most arena bytes held at once since the last reset */
+    uint64_t host_arena_bytes;  /* the arena's size (host_bytes) */
 } sm_server_metrics;
 int64_t sm_now_ns(void);
 int sm_server_create(const sm_server_config *cfg, sm_server **server);

@@ -68,12 +68,15 @@ class ServerMetrics(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("pending", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("batched_queries", ctypes.c_uint64),
                 ("text_bytes", ctypes.c_uint64), ("out_bytes", ctypes.c_uint64),
-                ("write_waves", ctypes.c_uint64), ("overflow_allocs", ctypes.c_uint64),
+                ("write_waves", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                 ("p50_ns", ctypes.c_int64), ("p99_ns", ctypes.c_int64),
                 ("p999_ns", ctypes.c_int64), ("max_ns", ctypes.c_int64),
                 ("mean_ns", ctypes.c_double), ("span_ns", ctypes.c_int64),
                 ("qps", ctypes.c_double), ("graph_launches", ctypes.c_uint64),
-                ("graph_builds", ctypes.c_uint64)]
+                ("graph_builds", ctypes.c_uint64), ("evicted", ctypes.c_uint64),
+                ("evicted_bytes", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("mem_waits", ctypes.c_uint64), ("host_peak_bytes", ctypes.c_uint64),
+                ("host_arena_bytes", ctypes.c_uint64)]
 
 
 # every exported symbol and its prototype: (restype, argtypes)

@@ -50,7 +50,9 @@ def build(verbose: bool = False, asm: bool = False) -> str:
                 print(" ".join(cmd), flush=True)
         list(ex.map(subprocess.check_call, cmds))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # roctx: named host ranges for rocprofv3 --marker-trace
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -14,6 +14,7 @@
 
 #include "../../include/sm.h"
 #include "sm_internal.h"
+#include "sm_trace.h"
 
 using namespace sm;
 
@@ -346,6 +347,22 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
     return SM_OK;
 }
 
+// Whether a plan for a pattern of length m under opts may keep hit bitmaps beyond
+// m <= 64: Shift-And's suffix form does, which the planner takes on texts of one
+// dominant symbol (sigma < 2) or when it is forced.
+static bool may_keep_bitmap(uint64_t m, const sm_opts *o)
+{
+    if (m <= (uint64_t)BP_MAX_M) return true;
+    if (o && o->algo) return o->algo == ALGO_SHIFT_AND;
+    if (o && o->sigma_hint > 0) return o->sigma_hint < 2;
+    return true;
+}
+
+static bool plan_keeps_bitmap(const Plan &p)
+{
+    return p.m <= (uint64_t)BP_MAX_M || p.algo == ALGO_SHIFT_AND;
+}
+
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
     // explicit lanes, else the smallest the planner could pick for this m (the
@@ -355,7 +372,7 @@ extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opt
         lb = (int)(m - 15);
     Plan p;
     p.lane_bytes = lb;
-    return ws_layout(n, m, tile_starts(p)).need;
+    return ws_layout(n, m, tile_starts(p), may_keep_bitmap(m, opts)).need;
 }
 
 extern "C" uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_opts *opts)
@@ -379,7 +396,7 @@ extern "C" uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_
     }
     Plan p;
     p.lane_bytes = lb;
-    const WsLayout w = ws_layout(n, lim + 1, tile_starts(p));
+    const WsLayout w = ws_layout(n, lim + 1, tile_starts(p), may_keep_bitmap(lim + 1, opts));
     return std::max(best, w.need + align_up(m_max + 64, 256) - align_up(lim + 1 + 64, 256));
 }
 
@@ -388,6 +405,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
                      uint64_t work_bytes, const sm_opts *opts, hipStream_t st, bool write,
                      int sigma_known, uint64_t first = 0, bool may_profile = true)
 {
+    TraceRange tr(write ? "sm.find_all.enqueue" : "sm.count.enqueue");
     int r = validate_common(d_text, n, pat, m);
     if (r) return r;
     if (!d_count) return fail(SM_EINVAL, "d_count is NULL");
@@ -400,7 +418,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         HIP_TRY(launch_set_u64(d_count, 0, st));
         return SM_OK;
     }
-    const WsLayout w = ws_layout(n, m, tile_starts(plan));
+    const WsLayout w = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan));
     const uint64_t need = write ? w.need : w.need_count;
     if (!d_work || work_bytes < need)
         return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)need);
@@ -513,7 +531,7 @@ extern "C" int sm_find_all_noalloc(const uint8_t *d_text, uint64_t n, const uint
     Plan plan;
     if ((r = make_plan(pat, m, opts, 0, plan))) return r;
     if (n > 0 && m <= n) {
-        const uint64_t need = ws_layout(n, m, tile_starts(plan)).need;
+        const uint64_t need = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan)).need;
         if (need > (uint64_t)SM_NOALLOC_SCRATCH_BYTES)
             return fail(SM_EINVAL,
                         "sm_find_all_noalloc: n = %llu, m = %llu needs %llu bytes of workspace, more than "
@@ -588,6 +606,7 @@ static int run_sync_dev(const uint8_t *d_text, uint64_t n, const uint8_t *pat, u
                         int64_t *d_out, uint64_t cap, uint64_t *count, hipStream_t st, bool write,
                         int sigma_known)
 {
+    TraceRange tr(write ? "sm.find_all" : "sm.count");
     int r = validate_common(d_text, n, pat, m);
     if (r) return r;
     if (!count) return fail(SM_EINVAL, "count is NULL");

@@ -15,6 +15,7 @@
 
 #include "../../include/sm.h"
 #include "sm_batch_host.h"
+#include "sm_trace.h"
 
 using namespace sm;
 
@@ -263,7 +264,10 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         if (m > c->n) continue;  // no occurrence
         if (m > (uint64_t)BATCH_MAX_M) {
             j.longp.push_back(i);
-            single = std::max(single, sm_workspace_size(c->n, m, nullptr));
+            sm_opts o;
+            memset(&o, 0, sizeof o);
+            o.sigma_hint = sigma;  // planned with the corpus's alphabet, as the search will be
+            single = std::max(single, sm_workspace_size(c->n, m, &o));
             continue;
         }
         Plan p;
@@ -655,6 +659,7 @@ extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *
 {
     if (!out) return err(SM_EINVAL, "batch is NULL");
     *out = nullptr;
+    TraceRange tr("batch.count");
     int r = check_corpus(c);
     if (r) return r;
     if (!pats || !pat_off) return err(SM_EINVAL, "patterns or offsets are NULL");
@@ -696,6 +701,7 @@ extern "C" int sm_batch_write_async(sm_batch *b, uint64_t lo, uint64_t hi, int64
     int r = check_corpus(b->j.c);
     if (r) return r;
     if (hi == lo) return SM_OK;
+    TraceRange tr("batch.write.enqueue");
     // the write plan of this window: only the patterns whose slices meet it
     if ((r = batch_write_plan(b->j, b->ws, b->csr.data(), lo, hi, (hipStream_t)stream, b->stg))) return r;
     return batch_write_enqueue(b->j, b->ws, (const uint64_t *)(b->ws + b->j.L.csr), b->csr.data(),
@@ -816,6 +822,7 @@ extern "C" int sm_batch_find_all(sm_corpus *c, const uint8_t *pats, const uint64
     DevFree dbuf;
     if (dcap) HIP_OK(hipMalloc(&dbuf.p, wave * 8));
     for (uint64_t lo = 0; lo < dcap; lo += wave) {
+        TraceRange tw("batch.wave (write + copy to host)");
         const uint64_t hi = std::min(dcap, lo + wave);
         if ((r = sm_batch_write_async(b, lo, hi, (int64_t *)dbuf.p, nullptr))) return r;
         HIP_OK(hipMemcpy(out + lo, dbuf.p, (hi - lo) * 8, hipMemcpyDeviceToHost));

@@ -215,6 +215,14 @@ template <int NW>
 struct takes_masks<BitAcc<NW>> {
     static constexpr bool value = true;
 };
+template <class E>
+struct is_no_emit {
+    static constexpr bool value = false;
+};
+template <>
+struct is_no_emit<NoEmit> {
+    static constexpr bool value = true;
+};
 
 // Shift-And, complemented (Shift-Or) form. W = state word; CHECK = bytes between
 // hit checks (requires m - 1 + CHECK <= bits of W). MT = mask table entry: W, or
@@ -451,6 +459,63 @@ struct SuffixVerify {
     __device__ __forceinline__ bool saturated() const { return false; }
     __device__ __forceinline__ void add(uint32_t) {}
 };
+
+// The suffix form's candidates, settled after the scan: ba holds the lane's starts
+// whose last SA_SUFFIX bytes match (bit i <-> start g0 + i) and keeps those that are
+// occurrences. In ascending order, a start exactly one period (<= SA_SUFFIX, else
+// period = 0) after the lane's previous occurrence is one without reading (as in
+// SuffixVerify); any other compares its first m - SA_SUFFIX bytes with the pattern,
+// 64 bytes per round trip. Outside the scan loop, the verification's registers do
+// not weigh on the scan.
+template <int NW>
+__device__ __forceinline__ uint32_t suffix_resolve(BitAcc<NW> &ba, const uint8_t *text0, uint64_t g0,
+                                                   const uint8_t *pat, uint32_t m, uint32_t period)
+{
+    const uint32_t len = m - (uint32_t)SA_SUFFIX;
+    const uint8_t *pl = pat + m + 15;
+    uint32_t cnt = 0;
+    int last = -(1 << 20);  // lane-relative start of the lane's last occurrence
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+        uint64_t x = ba.w[k], keep = 0;
+        // a whole word one period after an occurrence, every start a candidate: all
+        // occurrences (a text of one symbol and p = a^m)
+        if (period == 1 && x == ~0ull && last == 64 * k - 1) {
+            keep = x;
+            cnt += 64;
+            last = 64 * k + 63;
+            x = 0;
+        }
+        while (x) {
+            const int b = __builtin_ctzll(x);
+            x &= x - 1;
+            const int r = 64 * k + b;
+            bool ok = period != 0 && r - last == (int)period;
+            if (!ok) {
+                const uint64_t g = g0 + (uint64_t)r;
+                const uint8_t *tl = text0 + g + m - 1;
+                ok = true;
+                for (uint32_t off = 0; off < len && ok; off += 64) {
+                    uint32_t d = 0;
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; q++) {
+                        const uint32_t o2 = off + 16 * q;
+                        if (o2 < len)
+                            d |= diff16(load16(text0 + g + o2, tl), load16(pat + o2, pl), len - o2 < 16 ? len - o2 : 16);
+                    }
+                    ok = d == 0;
+                }
+            }
+            if (ok) {
+                keep |= 1ull << b;
+                last = r;
+                cnt++;
+            }
+        }
+        ba.w[k] = keep;
+    }
+    return cnt;
+}
 
 // Brute force (Fig. 1, BF) over packed bytes, m <= BRUTE_MAX_M. For the four
 // starts of a text word, word k of the text shifted by k bytes is compared with

@@ -84,7 +84,8 @@ static_assert(sizeof(TileEntry) == 16, "one 16-byte load per entry");
 
 // Workspace layout (offsets in bytes from the workspace base):
 // [Params][pattern][tile_cnt u32][super u64 per 64 tiles][list TileEntry][nlist u64]
-// [stash u16 x STASH_K per tile][bits: one bit per start, m <= BP_MAX_M only]
+// [stash u16 x STASH_K per tile][bits: one bit per start, when the plan keeps hit
+// bitmaps: m <= BP_MAX_M, or Shift-And's suffix form]
 struct WsLayout {
     uint64_t params, pat, tile_cnt, super, list, nlist, stash, bits;
     uint64_t need;        // minimum workspace size for find_all
@@ -104,7 +105,7 @@ inline uint64_t num_tiles(uint64_t n, uint64_t m, uint64_t tile)
 
 inline uint64_t num_super(uint64_t ntiles) { return (ntiles + (1ull << SUPER_SHIFT) - 1) >> SUPER_SHIFT; }
 
-inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
+inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile, bool bitmap)
 {
     WsLayout w;
     w.ntiles = num_tiles(n, m, tile);
@@ -127,7 +128,7 @@ inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile)
     // hit bitmaps of dense Shift-And tiles: tile t at bit t * tile; whatever the
     // tile (at most BLOCK * 128 starts), the last one ends before bit n + BLOCK * 128
     w.bits = 0;
-    if (m <= (uint64_t)BP_MAX_M && w.ntiles) {
+    if ((bitmap || m <= (uint64_t)BP_MAX_M) && w.ntiles) {
         w.bits = o;
         o = align_up(o + (n + (uint64_t)BLOCK * 128) / 8 + 8, 256);
     }

@@ -216,10 +216,23 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
     if constexpr (ALGO == ALGO_SHIFT_AND) {
         if constexpr (VAR == 5) {  // m > SA_SUFFIX: the last SA_SUFFIX bytes, then the rest verified
             static_assert(SA_SUFFIX - 1 + 16 <= 64, "hits checked every 16 bytes");
-            SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full,
-                               period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u, s, lo};
-            lane_shift_and<uint64_t, 16, true>(S.text, S.mask, m, li0, lo, hi, sv);
-            return sv.n;
+            const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
+            if constexpr (takes_masks<E>::value || is_no_emit<E>::value) {
+                // candidates as a bitmap first, settled after the scan
+                constexpr int NW = L > 64 ? L / 64 : 1;
+                BitAcc<NW> cand;
+                lane_shift_and<uint64_t, 16, false>(S.text, S.mask, m, li0, lo, hi, cand);
+                const uint32_t c = suffix_resolve(cand, a.text0, s + (uint64_t)lo, a.pat, a.m_full, per);
+                if constexpr (takes_masks<E>::value) {
+#pragma unroll
+                    for (int k = 0; k < NW; k++) o.w[k] |= cand.w[k];
+                }
+                return c;
+            } else {  // hits one by one: checked as they come
+                SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full, per, s, lo};
+                lane_shift_and<uint64_t, 16, true>(S.text, S.mask, m, li0, lo, hi, sv);
+                return sv.n;
+            }
         }
         if (VAR == 4)
             return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint8_t *>(S.mask), m,

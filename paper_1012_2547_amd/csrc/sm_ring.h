@@ -21,6 +21,19 @@ struct Ring {
     uint64_t cap = 0, head = 0, used = 0;
     std::deque<std::shared_ptr<RingRegion>> live;  // allocation order
 
+    // Whether alloc(bytes) would succeed now (always for 0 bytes, which need no region).
+    bool fits(uint64_t bytes) const
+    {
+        bytes = (bytes + 255) & ~255ull;
+        if (bytes == 0) return true;
+        if (bytes > cap) return false;
+        const uint64_t pad = head + bytes > cap ? cap - head : 0;
+        return used + pad + bytes <= cap;
+    }
+
+    // Whether a region of `bytes` fits the ring at all (when nothing else is held).
+    bool ever_fits(uint64_t bytes) const { return ((bytes + 255) & ~255ull) <= cap; }
+
     // A region of at least `bytes` (rounded up to 256), or null if it does not fit now.
     std::shared_ptr<RingRegion> alloc(uint64_t bytes)
     {

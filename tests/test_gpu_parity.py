@@ -471,6 +471,31 @@ def test_shift_and_suffix_form_periodic(sm):
     assert gpu_find(sm, t_dev, b"ab" * 60, algo=1)[1] == 0
 
 
+def test_shift_and_suffix_form_bitmap(sm):
+    """The suffix form (m > 49) keeps its candidates as lane bitmaps and settles them after
+    the scan; dense tiles leave their occurrence bitmaps to the emit pass. m = 50..64 and
+    longer, every lane width (BitAcc of one and of two words), on a^n, (ab)^n and a text of
+    dense, sparse and empty regions, with truncation."""
+    n = 150_001
+    a_n = np.full(n, ord("a"), dtype=np.uint8)
+    ab = np.frombuffer(b"ab" * (n // 2 + 1), dtype=np.uint8)[:n].copy()
+    parts = [np.zeros(9001, np.uint8), dg.uniform_text(30_003, 2, seed=35),
+             np.zeros(15_013, np.uint8), np.full(7_777, 200, np.uint8), np.zeros(21_011, np.uint8),
+             dg.uniform_text(11_999, 2, seed=36)]
+    mixed = np.concatenate(parts)
+    for t_np, pats in ((a_n, [b"a" * m for m in (50, 57, 64, 65, 130)]),
+                       (ab, [b"ab" * 25, b"ba" * 28 + b"b", b"ab" * 32, b"ab" * 40 + b"a"]),
+                       (mixed, [bytes(m) for m in (50, 57, 64, 90, 300)])):
+        _suffix_check(sm, t_np, pats, lanes=(32, 64, 128, 16), tpws=(1, 2))
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        for p in pats:
+            want = oracle.find_all(t_np, p)
+            for cap in (1, want.size // 3, want.size - 1):
+                if 0 < cap < want.size:
+                    got, tot = gpu_find(sm, t_dev, p, algo=1, lane=128, cap=cap)
+                    assert tot == want.size and np.array_equal(got, want[:cap]), (len(p), cap)
+
+
 def test_one_symbol_texts_planned(sm):
     """The planner's own choice on corpora of one symbol (sigma_eff 1): every m, closed forms."""
     n = 1 << 20

@@ -118,25 +118,74 @@ def test_server_alone_vs_in_mix(sm, slots, max_batch, pool, host, graphs, policy
     qs = query_mix(texts, 150, seed=14)
     qs += [(0, b"\x00\x01"), (1, b"\x05"), (2, bytes(texts[2][:2100])), (0, bytes(texts[0][:300_001]))]
     tickets = [srv.submit(ids[c], p) for c, p in qs]
+    refused = 0
     for (c, p), tk in zip(qs, tickets):
-        cnt, pos, info = srv.wait(tk)
         want = oracle.find_all(texts[c], p)
+        if host and (want.size * 8 + 255) // 256 * 256 > host:
+            # positions alone larger than the host result arena: refused, not allocated
+            with pytest.raises(sm.SmError, match="ENOMEM"):
+                srv.wait(tk)
+            refused += 1
+            srv.free(tk)
+            continue
+        cnt, pos, info = srv.wait(tk)
         assert cnt == want.size, (c, len(p))
         assert np.array_equal(pos, want), (c, len(p))
         assert info["corpus"] == c and info["done_ns"] >= info["start_ns"] >= info["arrival_ns"] > 0
         srv.free(tk)
     st = srv.stats()
-    assert st["completed"] == len(qs) and st["pending"] == 0
-    assert st["batched_queries"] == len(qs)
+    assert st["completed"] == len(qs) - refused and st["pending"] == 0
+    assert st["rejected"] == refused
+    assert st["host_peak_bytes"] <= st["host_arena_bytes"]
     assert 0 < st["p50_ns"] <= st["p99_ns"] <= st["p999_ns"] <= st["max_ns"]
-    if pool:
-        assert st["write_waves"] > st["batches"]  # outputs larger than a slot's pool share
+    if pool:  # no wave holds more than a slot's pool share
+        assert st["write_waves"] * (pool // slots) >= st["out_bytes"]
+    if host and host < (1 << 20):  # the 64 KiB arena cannot hold the densest queries
+        assert refused > 0
     if not graphs:
         assert st["graph_launches"] == 0
     srv.close()
     sm.batch_set_write_policy(0)
     for c in cs:
         c.close()
+
+
+@pytest.mark.parametrize("slots", [1, 2, 3])
+def test_server_defers_on_memory(sm, slots):
+    """A host result arena far smaller than a batch's positions: batches are cut to the
+    prefix that fits, the rest deferred and counted again, completed results evicted to
+    pageable memory when a deferred query needs the room; pinned memory never exceeds
+    the arena and every result equals the oracle's for the pattern alone."""
+    t_np = dg.uniform_text(300_001, 4, seed=31)
+    c = sm.Corpus(t_np)
+    host = 64 << 10
+    srv = sm.Server(host_bytes=host, max_batch=64, slots=slots)
+    cid = srv.add_corpus(c)
+    pats = [dg.substring_pattern(t_np, 3 + i % 4, seed=32, idx=i)[0] for i in range(160)]
+    want = [oracle.find_all(t_np, p) for p in pats]
+    assert sum(w.size for w in want) * 8 > 20 * host
+    tks = [srv.submit(cid, p) for p in pats]
+    for k, tk in enumerate(tks):
+        cnt, pos, _ = srv.wait(tk)
+        assert cnt == want[k].size and np.array_equal(pos, want[k]), k
+        srv.free(tk)
+    st = srv.stats()
+    assert st["completed"] == len(pats) and st["rejected"] == 0
+    assert st["deferred"] > 0
+    assert 0 < st["host_peak_bytes"] <= host == st["host_arena_bytes"]
+    # results held by the caller while more queries arrive: the others wait or are
+    # evicted around them; freeing them lets everything finish
+    held = [srv.submit(cid, pats[i]) for i in range(4)]
+    for k, tk in enumerate(held):
+        cnt, pos, _ = srv.wait(tk)
+        assert np.array_equal(pos, want[k])
+    more = [srv.submit(cid, p) for p in pats[4:40]]
+    for tk in held:
+        srv.free(tk)
+    for k, tk in enumerate(more):
+        assert np.array_equal(srv.result(tk), want[4 + k]), k
+    srv.close()
+    c.close()
 
 
 def test_server_matches_single_path_and_reuses_memory(sm):
