@@ -460,60 +460,200 @@ struct SuffixVerify {
     __device__ __forceinline__ void add(uint32_t) {}
 };
 
-// The suffix form's candidates, settled after the scan: ba holds the lane's starts
-// whose last SA_SUFFIX bytes match (bit i <-> start g0 + i) and keeps those that are
-// occurrences. In ascending order, a start exactly one period (<= SA_SUFFIX, else
-// period = 0) after the lane's previous occurrence is one without reading (as in
-// SuffixVerify); any other compares its first m - SA_SUFFIX bytes with the pattern,
-// 64 bytes per round trip. Outside the scan loop, the verification's registers do
-// not weigh on the scan.
-template <int NW>
-__device__ __forceinline__ uint32_t suffix_resolve(BitAcc<NW> &ba, const uint8_t *text0, uint64_t g0,
-                                                   const uint8_t *pat, uint32_t m, uint32_t period)
+// 16 bytes at byte index idx of an LDS tile in the swizzled chunk layout (the
+// chunk holding idx and the next one must be staged).
+__device__ __forceinline__ uint4 lds_bytes16(const uint4 *lds, uint32_t idx)
 {
-    const uint32_t len = m - (uint32_t)SA_SUFFIX;
-    const uint8_t *pl = pat + m + 15;
+    const uint32_t u = idx >> 4, r = idx & 15;
+    const uint4 c0 = lds[swz(u)], c1 = lds[swz(u + 1)];
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    const uint32_t q = r >> 2, sh = r & 3;
+    uint32_t v[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++)
+        v[k] = q == 0 ? w[k] : (q == 1 ? w[k + 1] : (q == 2 ? w[k + 2] : w[k + 3]));
+    uint4 o;
+    o.x = alignbyte(v[1], v[0], sh);
+    o.y = alignbyte(v[2], v[1], sh);
+    o.z = alignbyte(v[3], v[2], sh);
+    o.w = alignbyte(v[4], v[3], sh);
+    return o;
+}
+
+__device__ __forceinline__ uint4 readlane4(uint4 v, int k)
+{
+    uint4 r;
+    r.x = (uint32_t)__builtin_amdgcn_readlane((int)v.x, k);
+    r.y = (uint32_t)__builtin_amdgcn_readlane((int)v.y, k);
+    r.z = (uint32_t)__builtin_amdgcn_readlane((int)v.z, k);
+    r.w = (uint32_t)__builtin_amdgcn_readlane((int)v.w, k);
+    return r;
+}
+
+// Where the suffix form reads a candidate's first m - SA_SUFFIX bytes: the LDS tile
+// holds the (shifted) text from tile-relative position -li0 on, so a candidate at
+// tile-relative start rel has them in LDS from byte index li0 + rel - (m - SA_SUFFIX)
+// when that is >= 0; the pattern's first 1024 bytes sit in registers, 16 per lane
+// (lane k: bytes [16 k, 16 k + 16)).
+struct SuffixCtx {
+    const uint8_t *text0, *pat;  // original text, pattern copy (zero padded)
+    const uint4 *lds;            // the staged tile
+    int li0;                     // LDS byte index of tile-relative start 0 (shifted text)
+    uint64_t s;                  // global start of tile-relative start 0
+    uint32_t m, period;          // period: the smallest when <= SA_SUFFIX, else 0
+    uint4 ppre;                  // pattern bytes [16 lane, 16 lane + 16)
+};
+
+// Is the candidate at tile-relative start rel an occurrence? Wave-cooperative: all
+// lanes call it with the same rel.
+__device__ __forceinline__ bool suffix_check_wave(const SuffixCtx &c, int rel)
+{
+    const uint32_t len = c.m - (uint32_t)SA_SUFFIX;
+    const int b0 = c.li0 + rel - (int)len;  // LDS index of the candidate's first byte
+    const uint32_t lane = threadIdx.x & 63;
+    if (b0 < 0 || len > 1024) return verify_wave(c.text0, c.s + (uint64_t)rel, c.pat, c.m, 0, len);
+    const uint32_t o = 16 * lane;
+    uint32_t d = 0;
+    if (o < len) d = diff16(lds_bytes16(c.lds, (uint32_t)b0 + o), c.ppre, len - o < 16 ? len - o : 16);
+    return __ballot(d != 0) == 0;
+}
+
+// The same check by one lane for its own candidate (uniform loop bounds).
+__device__ __forceinline__ bool suffix_check_lane(const SuffixCtx &c, int rel, bool active)
+{
+    const uint32_t len = c.m - (uint32_t)SA_SUFFIX;
+    const int b0 = c.li0 + rel - (int)len;
+    bool ok = true;
+    if (active && b0 >= 0 && len <= 1024) {
+        uint32_t d = 0;
+        for (uint32_t o = 0; o < len; o += 16)  // the pattern's 16 bytes from lane o / 16
+            d |= diff16(lds_bytes16(c.lds, (uint32_t)b0 + o), readlane4(c.ppre, (int)(o >> 4)),
+                        len - o < 16 ? len - o : 16);
+        ok = d == 0;
+    } else if (active) {
+        const uint64_t g = c.s + (uint64_t)rel;
+        const uint8_t *tl = c.text0 + g + c.m - 1, *pl = c.pat + c.m + 15;
+        for (uint32_t off = 0; off < len && ok; off += 64) {
+            uint32_t d = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t o2 = off + 16 * q;
+                if (o2 < len)
+                    d |= diff16(load16(c.text0 + g + o2, tl), load16(c.pat + o2, pl), len - o2 < 16 ? len - o2 : 16);
+            }
+            ok = d == 0;
+        }
+    }
+    return ok;
+}
+
+// The suffix form's candidates, settled after the scan: ba holds the lane's starts
+// whose last SA_SUFFIX bytes match (bit i <-> tile-relative start lo + i) and keeps
+// those that are occurrences. Each lane walks its candidates in ascending order; a
+// start exactly one period (<= SA_SUFFIX) after the lane's previous occurrence is
+// one without reading (as in SuffixVerify). The others compare their first
+// m - SA_SUFFIX bytes with the pattern, from the LDS tile where it holds them:
+// when few lanes of the wave have such a candidate at once the whole wave checks
+// each of them, 16 bytes per lane; when many do (a text of one symbol: every lane's
+// first candidate), each lane checks its own. Wave-cooperative: all 64 lanes call
+// it (lanes without starts pass an empty ba). Outside the scan loop, the
+// verification's registers do not weigh on the scan.
+template <int L, int NW>
+__device__ __forceinline__ uint32_t suffix_resolve(BitAcc<NW> &ba, const SuffixCtx &c, int lo)
+{
+    static_assert(NW <= 2 && L <= 64 * NW, "at most 128 starts per lane");
+    constexpr uint64_t FULL0 = L >= 64 ? ~0ull : ((1ull << (L & 63)) - 1ull);  // the lane's bits of word 0
+    constexpr uint32_t COOP_MAX = 8;  // lanes checked one after another by the whole wave
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t period = c.period;
+    uint64_t x0 = ba.w[0], x1 = NW > 1 ? ba.w[NW > 1 ? 1 : 0] : 0ull;  // candidates left
+    uint64_t k0 = 0, k1 = 0;                                        // occurrences
     uint32_t cnt = 0;
     int last = -(1 << 20);  // lane-relative start of the lane's last occurrence
-#pragma unroll
-    for (int k = 0; k < NW; k++) {
-        uint64_t x = ba.w[k], keep = 0;
-        // a whole word one period after an occurrence, every start a candidate: all
-        // occurrences (a text of one symbol and p = a^m)
-        if (period == 1 && x == ~0ull && last == 64 * k - 1) {
-            keep = x;
-            cnt += 64;
-            last = 64 * k + 63;
-            x = 0;
-        }
-        while (x) {
-            const int b = __builtin_ctzll(x);
-            x &= x - 1;
-            const int r = 64 * k + b;
-            bool ok = period != 0 && r - last == (int)period;
-            if (!ok) {
-                const uint64_t g = g0 + (uint64_t)r;
-                const uint8_t *tl = text0 + g + m - 1;
-                ok = true;
-                for (uint32_t off = 0; off < len && ok; off += 64) {
-                    uint32_t d = 0;
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; q++) {
-                        const uint32_t o2 = off + 16 * q;
-                        if (o2 < len)
-                            d |= diff16(load16(text0 + g + o2, tl), load16(pat + o2, pl), len - o2 < 16 ? len - o2 : 16);
-                    }
-                    ok = d == 0;
+    if (period == 1) {
+        // Every start of a lane a candidate (a text of one symbol): the lane's starts are
+        // one period apart, so they are all occurrences when its first one is; and when
+        // the previous lane is full too, that first start is one period after the previous
+        // lane's last. So only the first lane of each run of full lanes is checked.
+        const bool full = x0 == FULL0 && (NW == 1 || x1 == ~0ull);
+        const uint64_t F = __ballot(full);
+        const bool head = full && !(lane > 0 && ((F >> (lane - 1)) & 1ull));
+        const uint64_t H = __ballot(head);
+        if (F && (uint32_t)__builtin_popcountll(H) <= COOP_MAX) {
+            uint64_t p = H, bad = 0;
+            while (p) {
+                const int kl = __builtin_ctzll(p);
+                p &= p - 1;
+                if (!suffix_check_wave(c, __shfl(lo, kl, 64))) bad |= 1ull << kl;
+            }
+            if (!bad) {  // uniform: every full lane holds occurrences only
+                if (full) {
+                    k0 = x0;
+                    k1 = x1;
+                    cnt = L;
+                    last = L - 1;
+                    x0 = x1 = 0;
                 }
             }
-            if (ok) {
-                keep |= 1ull << b;
-                last = r;
-                cnt++;
-            }
         }
-        ba.w[k] = keep;
     }
+    for (;;) {
+        // 1. accept what the period rule settles; stop at a candidate that needs reading
+        int r = -1;
+        while (x0 | x1) {
+            const bool lo_word = x0 != 0;
+            const int b = __builtin_ctzll(lo_word ? x0 : x1);
+            if (lo_word) x0 &= x0 - 1;
+            else x1 &= x1 - 1;
+            const int rr = (lo_word ? 0 : 64) + b;
+            if (period != 0 && rr - last == (int)period) {
+                if (lo_word) k0 |= 1ull << b;
+                else k1 |= 1ull << b;
+                last = rr;
+                cnt++;
+                // a run of consecutive starts one period apart (period 1: a text of one symbol)
+                if (period == 1 && b < 63) {
+                    if (lo_word && x0 != 0 && x0 == (FULL0 & (~0ull << (b + 1)))) {
+                        k0 |= x0;
+                        cnt += (uint32_t)__builtin_popcountll(x0);
+                        last = 63 - __builtin_clzll(x0 | 1ull);
+                        x0 = 0;
+                    } else if (!lo_word && x1 == ~0ull << (b + 1)) {
+                        k1 |= x1;
+                        cnt += (uint32_t)__builtin_popcountll(x1);
+                        last = 127;
+                        x1 = 0;
+                    }
+                }
+                continue;
+            }
+            r = rr;
+            break;
+        }
+        const uint64_t pend = __ballot(r >= 0);
+        if (!pend) break;
+        // 2. check the pending candidates
+        bool ok = false;
+        if ((uint32_t)__builtin_popcountll(pend) <= COOP_MAX) {
+            uint64_t p = pend;
+            while (p) {
+                const int kl = __builtin_ctzll(p);
+                p &= p - 1;
+                const bool v = suffix_check_wave(c, __shfl(lo + r, kl, 64));
+                if (lane == kl) ok = v;
+            }
+        } else {
+            ok = suffix_check_lane(c, lo + r, r >= 0);
+        }
+        if (r >= 0 && ok) {
+            if (r < 64) k0 |= 1ull << r;
+            else k1 |= 1ull << (r - 64);
+            last = r;
+            cnt++;
+        }
+    }
+    ba.w[0] = k0;
+    if (NW > 1) ba.w[NW > 1 ? 1 : 0] = k1;
     return cnt;
 }
 

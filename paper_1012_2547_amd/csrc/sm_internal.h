@@ -26,6 +26,7 @@ constexpr int BRUTE_MAX_M = 8;
 constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
 constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register
 constexpr int SA_SUFFIX = 49;      // Shift-And for m > SA_SUFFIX scans the pattern's last 49 bytes
+constexpr int SA_STAGE_MAX = 1024 + SA_SUFFIX;  // its tiles stage whole windows up to this m
 constexpr int Q_MAX = 16;          // longest hashed q-gram
 constexpr int H_MIN = 8;           // hash table bits range
 constexpr int H_MAX = 12;

@@ -66,18 +66,22 @@ struct ScanArgs {
     uint32_t *bits;       // find, bitmap form: hit bitmaps of the dense tiles (T / 32 words per tile)
     int64_t *out;         // emit: hit number k of the pattern goes to out[k - lo]
     uint64_t lo, cap;     // emit: window [lo, lo + cap) of hit numbers
-    // Shift-And for m > SA_SUFFIX: text/n above are the text shifted by m - SA_SUFFIX and m
-    // above is SA_SUFFIX (the scan finds the pattern's last SA_SUFFIX bytes); text0 and
-    // m_full are the originals, for the verification of the first m - SA_SUFFIX bytes
+    // Shift-And for m > SA_SUFFIX (the scan finds the pattern's last SA_SUFFIX bytes; text0
+    // and m_full are the original text and m, for the check of the first m - SA_SUFFIX
+    // bytes). Up to SA_STAGE_MAX, text/n/m above are the originals too and the tiles
+    // stage whole windows: the scan reads them from sfx_off = m - SA_SUFFIX bytes on.
+    // Longer patterns: text/n above are the text shifted by m - SA_SUFFIX, m above is
+    // SA_SUFFIX and sfx_off is 0.
     const uint8_t *text0;
-    uint32_t m_full;
+    uint32_t m_full, sfx_off;
 };
 
 template <int ALGO, int L>
 struct Geometry {
     static constexpr int T = BLOCK * L;
     // halo bytes beyond the tile, plus 16 for misalignment and 16 for word reads
-    static constexpr int HALO = (ALGO == ALGO_HASHQ) ? (Q_MAX + 32) : (BP_MAX_M + 32);
+    static constexpr int HALO = (ALGO == ALGO_HASHQ) ? (Q_MAX + 32)
+                                : (ALGO == ALGO_SHIFT_AND ? (SA_STAGE_MAX + 32) : (BP_MAX_M + 32));
     // whole groups of 8 chunks: the swizzle permutes chunks inside such groups
     static constexpr int CHUNKS = (((T + HALO + 15) / 16 + 1) + 7) & ~7;
     static constexpr int PER = (CHUNKS + BLOCK - 1) / BLOCK;  // chunk loads per thread
@@ -210,27 +214,33 @@ __device__ __forceinline__ BruteWords brute_words(const Params *prm)
 template <int ALGO, int L, int VAR, bool WRITE, class E>
 __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanArgs &a, int m,
                                              int sh1, int period, int period_lb, uint64_t s,
-                                             int li0, int lo, int hi, E &o, const BruteWords &bw)
+                                             int li0, int lo, int hi, E &o, const BruteWords &bw,
+                                             uint4 ppre = uint4{0u, 0u, 0u, 0u})
 {
+    if constexpr (ALGO == ALGO_SHIFT_AND && VAR == 5 && (takes_masks<E>::value || is_no_emit<E>::value)) {
+        // m > SA_SUFFIX: candidates (the last SA_SUFFIX bytes match) as a bitmap first,
+        // settled after the scan by the whole wave (every lane takes part)
+        static_assert(SA_SUFFIX - 1 + 16 <= 64, "hits checked every 16 bytes");
+        const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
+        constexpr int NW = L > 64 ? L / 64 : 1;
+        BitAcc<NW> cand;
+        const int sli0 = li0 + (int)a.sfx_off;  // LDS index of the suffix of start 0
+        if (lo <= hi) lane_shift_and<uint64_t, 16, false>(S.text, S.mask, SA_SUFFIX, sli0, lo, hi, cand);
+        const SuffixCtx sc{a.text0, a.pat, S.text, sli0, s, a.m_full, per, ppre};
+        const uint32_t c = suffix_resolve<L>(cand, sc, lo);
+        if constexpr (takes_masks<E>::value) {
+#pragma unroll
+            for (int k = 0; k < NW; k++) o.w[k] |= cand.w[k];
+        }
+        return c;
+    }
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if constexpr (ALGO == ALGO_SHIFT_AND) {
         if constexpr (VAR == 5) {  // m > SA_SUFFIX: the last SA_SUFFIX bytes, then the rest verified
-            static_assert(SA_SUFFIX - 1 + 16 <= 64, "hits checked every 16 bytes");
             const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
-            if constexpr (takes_masks<E>::value || is_no_emit<E>::value) {
-                // candidates as a bitmap first, settled after the scan
-                constexpr int NW = L > 64 ? L / 64 : 1;
-                BitAcc<NW> cand;
-                lane_shift_and<uint64_t, 16, false>(S.text, S.mask, m, li0, lo, hi, cand);
-                const uint32_t c = suffix_resolve(cand, a.text0, s + (uint64_t)lo, a.pat, a.m_full, per);
-                if constexpr (takes_masks<E>::value) {
-#pragma unroll
-                    for (int k = 0; k < NW; k++) o.w[k] |= cand.w[k];
-                }
-                return c;
-            } else {  // hits one by one: checked as they come
+            {  // hits one by one: checked as they come
                 SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full, per, s, lo};
-                lane_shift_and<uint64_t, 16, true>(S.text, S.mask, m, li0, lo, hi, sv);
+                lane_shift_and<uint64_t, 16, true>(S.text, S.mask, SA_SUFFIX, li0 + (int)a.sfx_off, lo, hi, sv);
                 return sv.n;
             }
         }
@@ -321,6 +331,12 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
     const BruteWords bw = brute_words<ALGO>(a.prm);
     tables_commit<ALGO, VAR>(tb, S.mask, S.shift, a.hbits);
     uint64_t sup_i = ~0ull, sup_v = 0;  // this workgroup's pending super-chunk total (thread 0)
+    // suffix form: the pattern's first 1024 bytes, 16 per lane, for the candidates' checks
+    uint4 ppre = {0u, 0u, 0u, 0u};
+    if constexpr (ALGO == ALGO_SHIFT_AND && VAR == 5) {
+        const uint32_t lane = threadIdx.x & 63;
+        if (16 * lane < a.m_full - (uint32_t)SA_SUFFIX) ppre = reinterpret_cast<const uint4 *>(a.pat)[lane];
+    }
 
     for (uint64_t t = t_begin; t < t_end; t++) {
         if (!PREFETCH && t != t_begin) {
@@ -343,13 +359,13 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(ScanArgs a)
         [[maybe_unused]] CapEmit ce;
         [[maybe_unused]] BitAcc<NW> ba;
         if constexpr (MODE == CM_BITS) {
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba, bw);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba, bw, ppre);
         } else if constexpr (MODE == CM_CAP) {
             run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce, bw);
             c = ce.n;
         } else {
             NoEmit ne;
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne, bw);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne, bw, ppre);
         }
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
@@ -1110,9 +1126,13 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
         const uint64_t sh = plan.m - SA_SUFFIX;
         a.text0 = d_text;
         a.m_full = (uint32_t)plan.m;
-        a.text = d_text + sh;
-        a.n = n - sh;
-        a.m = SA_SUFFIX;
+        if (plan.m <= (uint64_t)SA_STAGE_MAX) {  // whole windows in LDS
+            a.sfx_off = (uint32_t)sh;
+        } else {
+            a.text = d_text + sh;
+            a.n = n - sh;
+            a.m = SA_SUFFIX;
+        }
     }
     return a;
 }
