@@ -237,14 +237,16 @@ int sm_batch_set_wave_bytes(uint64_t bytes);
 /* How the write pass of sm_batch_open, sm_batch_find_all and the server finds the
  * positions of each pattern with occurrences (speed only, never results):
  * 0 = automatic (from the counts of the window: the single-pattern pipeline for
- * patterns of at most 64 bytes with at least one occurrence per 384 text bytes, a
- * shared prefix-filter pass for q-classes whose patterns would otherwise rescan
- * most of the text, each pattern's own scanner for the rest), 1 = every
- * pattern's own scanner, 2 = the shared pass for every pattern sparse enough for
- * it (at most 16 occurrences per 4096 text bytes) in q-classes of at least 3 such
- * patterns, 3 = the single-pattern pipeline for every pattern of at most 64
- * bytes. Patterns longer than 2048 bytes always take the single-pattern
- * pipeline. Process-wide; SM_EINVAL outside 0..3. */
+ * patterns of at most 64 bytes with at least one occurrence per 384 text bytes; the
+ * shared prefix-filter pass of the pattern's count group -- which copies out the
+ * hits the count step kept, up to 2048 per text chunk and group, and scans the
+ * other chunks again -- when the group kept every chunk's hits or its patterns would
+ * otherwise rescan most of the text; each pattern's own scanner for the rest),
+ * 1 = every pattern's own scanner, 2 = the shared pass for every pattern of a
+ * filter group sparse enough for it (at most 16 occurrences per 4096 text bytes),
+ * 3 = the single-pattern pipeline for every pattern of at most 64 bytes. Patterns
+ * longer than 2048 bytes always take the single-pattern pipeline. Process-wide;
+ * SM_EINVAL outside 0..3. */
 int sm_batch_set_write_policy(int policy);
 
 /*

@@ -150,6 +150,8 @@ BatchLayout layout_of(const BatchJob &j, uint64_t single)
     o = align_up(o + j.mq.size() * sizeof(MqGroup), 256);
     L.mqtabs = o;
     o = align_up(o + j.mqtab.size(), 256);
+    L.mqwtabs = o;
+    o = align_up(o + j.mqwtab.size(), 256);
     L.params = o;
     o = align_up(o + np * sizeof(Params), 256);
     L.patbytes = o;
@@ -163,11 +165,20 @@ BatchLayout layout_of(const BatchJob &j, uint64_t single)
     L.csr = o;
     o = align_up(o + ((uint64_t)j.P + 1) * 8, 256);
     L.wgroups = o;
-    o = align_up(o + np * sizeof(BatchGroup), 256);
-    L.mqwgroups = o;
-    o = align_up(o + (uint64_t)j.max_mqw * sizeof(MqGroup), 256);
-    L.mqwtabs = o;
-    o = align_up(o + (uint64_t)j.max_mqw * MQ_TAB_BYTES, 256);
+    o = align_up(o + np * sizeof(BatchGroup), 16);
+    L.wroute = o;
+    o = align_up(o + np, 16);
+    L.mqwlist = o;
+    o = align_up(o + j.mq.size() * 4, 256);
+    L.hqgroups = o;
+    o = align_up(o + (uint64_t)j.max_hq * sizeof(MqGroup), 256);
+    L.hqtabs = o;
+    o = align_up(o + (uint64_t)j.max_hq * MQ_TAB_BYTES, 256);
+    const uint64_t items = j.stash ? j.nchunks * j.mq.size() : 0;
+    L.mqstash = o;
+    o = align_up(o + items * MQ_STASH * 4, 256);
+    L.mqstash_n = o;
+    o = align_up(o + items * 4, 256);
     L.single = o;
     o = align_up(o + single, 256);
     L.need = o;
@@ -204,7 +215,12 @@ BatchLaunch launch_of(const BatchJob &j, uint8_t *ws)
     B.mqgroups = reinterpret_cast<const MqGroup *>(ws + j.L.mqgroups);
     B.host_mq = j.mq.data();
     B.mqtabs = ws + j.L.mqtabs;
+    B.mqwtabs = ws + j.L.mqwtabs;
     B.nmq = (uint32_t)j.mq.size();
+    if (j.stash && j.nchunks && !j.mq.empty()) {
+        B.mqstash = reinterpret_cast<uint32_t *>(ws + j.L.mqstash);
+        B.mqstash_n = reinterpret_cast<uint32_t *>(ws + j.L.mqstash_n);
+    }
     B.mq_max_m = j.mq_max_m;
     B.params = reinterpret_cast<const Params *>(ws + j.L.params);
     B.patbytes = ws + j.L.patbytes;
@@ -303,6 +319,7 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         off += pat_region(bp.m);
     }
     j.patbytes = off;
+    j.mq_of.assign(j.bpats.size(), -1);
     // q-classes (q = min(m, MQ_QMAX)) with at least MQ_MIN patterns are counted by
     // the prefix filter; the others by their own scanners
     std::vector<uint32_t> qcount(MQ_QMAX + 1, 0);
@@ -355,10 +372,14 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
             j.mq.push_back(g);
             j.mqtab.resize(j.mqtab.size() + MQ_TAB_BYTES, 0);
             j.mq.back().flat = build_mq_table(j, mem.data() + b, g.count, q, j.mqtab.data() + g.tab_off, true) ? 1u : 0u;
+            j.mqwtab.resize(j.mqtab.size(), 0);
+            build_mq_table(j, mem.data() + b, g.count, q, j.mqwtab.data() + g.tab_off, false);
+            for (size_t e2 = b; e2 < e; e2++) j.mq_of[mem[e2]] = (int32_t)(j.mq.size() - 1);
         }
     }
     if (j.patbytes >= (1ull << 32)) return err(SM_EINVAL, "batch patterns exceed 4 GiB");
-    j.max_mqw = (uint32_t)(j.bpats.size() / MQ_G + MQ_QMAX);
+    j.stash = ws == WS_WRITE;
+    j.max_hq = (uint32_t)(j.bpats.size() / MQ_G + MQ_QMAX);
     if (!j.bpats.empty()) {
         j.ntiles = (c->n - min_m + 1 + BT - 1) / BT;
         // aim for several thousand (chunk, group) items in the count pass
@@ -382,6 +403,8 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
 
 uint64_t sm::batch_image_bytes(const BatchJob &j) { return j.L.cnt; }
 
+uint64_t sm::batch_stash_items(const BatchJob &j) { return j.stash ? j.nchunks * j.mq.size() : 0; }
+
 void sm::batch_fill_image(const BatchJob &j, uint8_t *h)
 {
     memset(h, 0, j.L.cnt);
@@ -390,6 +413,7 @@ void sm::batch_fill_image(const BatchJob &j, uint8_t *h)
     memcpy(h + j.L.cgroups, j.cgroups.data(), j.cgroups.size() * sizeof(BatchGroup));
     memcpy(h + j.L.mqgroups, j.mq.data(), j.mq.size() * sizeof(MqGroup));
     memcpy(h + j.L.mqtabs, j.mqtab.data(), j.mqtab.size());
+    memcpy(h + j.L.mqwtabs, j.mqwtab.data(), j.mqwtab.size());
     for (const auto &bp : j.bpats) memcpy(h + j.L.patbytes + bp.pat_off, j.pats + j.pat_off[bp.index], bp.m);
 }
 
@@ -457,26 +481,40 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
     const int policy = g_write_policy;
     j.wplan = true;
     j.wgroups.clear();
-    j.mqw.clear();
-    j.mqwtab.clear();
+    j.mqwlist.clear();
+    j.hq.clear();
+    j.hqtab.clear();
     j.singlep.clear();
+    j.wroute.assign(j.bpats.size(), 0);
     if (j.bpats.empty()) return SM_OK;
-    // A pattern may share a filter write pass when its own scanner would rescan at
-    // least 1/16 of the text (the chunks holding its hits; estimated from its
-    // count) and its hits are sparse enough to be sorted in LDS (at most 16 per
-    // 4096 starts on average). A q-class shares a pass when the rescans it replaces
-    // exceed 2.5 texts: one shared pass runs at about 2/5 of a per-pattern rescan's
-    // rate. A pattern with at least one occurrence per SINGLE_ROUTE_DENSITY text
-    // bytes in the window goes to the single-pattern pipeline instead: one text
-    // read plus a coalesced emit, against 40 to 60 ps per position written from a
-    // batch pass.
+    // A pattern may share its count group's filter write pass when its hits are
+    // sparse enough to be sorted in LDS (at most 16 per 4096 starts on average). That
+    // pass copies out the hits the count step kept -- those of a pattern with at most
+    // MQ_CAP hits in a chunk, in the chunks whose item did not overflow -- and scans
+    // the other chunks again at about 2/5 of a per-pattern rescan's rate. So a
+    // pattern whose hits are mostly kept (on average at most MQ_CAP / 2 per chunk, in
+    // a group that kept most items) shares the pass; a heavier one does when the
+    // rescans of all such patterns of its group exceed 2.5 texts. A pattern with at
+    // least one occurrence per SINGLE_ROUTE_DENSITY text bytes in the window goes to
+    // the single-pattern pipeline instead: one text read plus a coalesced emit,
+    // against 40 to 60 ps per position written from a batch pass.
     const double n = (double)j.c->n, nch = (double)j.nchunks;
     const double chunk_bytes = (double)j.chunk_tiles * BT;
+    const size_t nmq = j.mq.size();
+    // per filter group: the fraction of chunks whose item overflowed (1: unknown)
+    std::vector<double> ovf(nmq, 1.0);
+    if (j.stash && j.h_stash_n && j.nchunks) {
+        for (size_t g = 0; g < nmq; g++) {
+            uint64_t k = 0;
+            for (uint64_t c = 0; c < j.nchunks; c++) k += j.h_stash_n[c * nmq + g] > MQ_STASH;
+            ovf[g] = (double)k / nch;
+        }
+    }
     // 0: none, 1: own scanner, 2: filter, 3: single-pattern pipeline
-    std::vector<uint8_t> route(j.bpats.size(), 0);
+    std::vector<uint8_t> &route = j.wroute;
     std::vector<double> wcount(j.bpats.size(), 0.0);  // occurrences inside the window
-    std::vector<double> qcover(MQ_QMAX + 1, 0.0);
-    std::vector<uint32_t> qn(MQ_QMAX + 1, 0);
+    std::vector<uint8_t> heavy(j.bpats.size(), 0);    // routed to the filter, hits mostly not kept
+    std::vector<double> gcover(nmq, 0.0);
     for (size_t k = 0; k < j.bpats.size(); k++) {
         const uint32_t i = j.bpats[k].index;
         // occurrences of this pattern inside the window [lo, hi)
@@ -490,37 +528,41 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
             j.singlep.push_back(i);
             continue;
         }
-        const double cover = nch * (1.0 - std::exp(-c / nch)) * chunk_bytes;
+        const int32_t g = j.mq_of[k];
         const bool sparse = c * 4096.0 / n <= 16.0;
-        const bool filt = policy == 2 ? sparse : (policy == 0 && sparse && cover * 16 >= n);
-        route[k] = filt ? 2 : 1;
-        if (filt) {
-            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
-            qcover[qc] += cover;
-            qn[qc]++;
+        route[k] = 1;
+        if (g < 0 || !sparse || policy == 1) continue;
+        const double total = (double)(h_csr[i + 1] - h_csr[i]);
+        const bool kept = ovf[g] <= 0.25 && total <= nch * (MQ_CAP / 2);
+        const double cover = nch * (1.0 - std::exp(-c / nch)) * chunk_bytes;
+        if (kept) {
+            route[k] = 2;
+        } else if (policy == 2 || cover * 16 >= n) {
+            route[k] = 4;
+            heavy[k] = 1;
+            gcover[g] += cover;
         }
     }
-    for (size_t k = 0; k < j.bpats.size(); k++) {
-        const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
-        if (route[k] == 2 && (qn[qc] < (uint32_t)MQ_MIN || (policy == 0 && qcover[qc] < 2.5 * n))) route[k] = 1;
+    if (policy == 0) {
+        for (size_t k = 0; k < j.bpats.size(); k++)
+            if (heavy[k] && gcover[j.mq_of[k]] < 2.5 * n) route[k] = 1;
     }
     if (policy == 0 && j.single_max_m) {
-        // A filter class costs one text pass per group of MQ_G patterns in every
-        // window; when the window holds few of its patterns, the single-pattern
-        // pipeline (about one text read each, plus the coalesced emit) is cheaper.
-        std::vector<double> alone(MQ_QMAX + 1, 0.0);
-        std::vector<uint8_t> can(MQ_QMAX + 1, 1);
+        // The heavy patterns of a group cost a text pass of the group's filter; when
+        // that exceeds searching them one by one (about one text read each, plus the
+        // coalesced emit), the single-pattern pipeline takes them.
+        std::vector<double> alone(nmq, 0.0);
+        std::vector<uint8_t> can(nmq, 1);
         for (size_t k = 0; k < j.bpats.size(); k++) {
-            if (route[k] != 2) continue;
-            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
-            if (j.bpats[k].m > j.single_max_m) can[qc] = 0;
-            alone[qc] += n * SINGLE_COST_PER_BYTE + wcount[k] * SINGLE_COST_PER_POS;
+            if (route[k] != 4) continue;
+            const int32_t g = j.mq_of[k];
+            if (j.bpats[k].m > j.single_max_m) can[g] = 0;
+            alone[g] += n * SINGLE_COST_PER_BYTE + wcount[k] * SINGLE_COST_PER_POS;
         }
         for (size_t k = 0; k < j.bpats.size(); k++) {
-            if (route[k] != 2) continue;
-            const uint32_t qc = std::min<uint32_t>(j.bpats[k].m, MQ_QMAX);
-            const double passes = (double)((qn[qc] + MQ_G - 1) / MQ_G);
-            if (can[qc] && alone[qc] < passes * n * FILTER_COST_PER_BYTE) {
+            if (route[k] != 4) continue;
+            const int32_t g = j.mq_of[k];
+            if (can[g] && alone[g] < n * FILTER_COST_PER_BYTE) {
                 route[k] = 3;
                 j.singlep.push_back(j.bpats[k].index);
             }
@@ -552,11 +594,19 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
         }
         j.wgroups.push_back(g);
     }
-    // filter write groups: each q-class by length, in groups of MQ_G
+    // count groups with patterns written from the kept hits (ascending: q order)
+    {
+        std::vector<uint8_t> used(nmq, 0);
+        for (size_t k = 0; k < j.bpats.size(); k++)
+            if (route[k] == 2) used[j.mq_of[k]] = 1;
+        for (size_t g = 0; g < nmq; g++)
+            if (used[g]) j.mqwlist.push_back((uint32_t)g);
+    }
+    // filter pass groups of the heavy patterns: each q-class by length, in groups of MQ_G
     for (uint32_t q = 1; q <= (uint32_t)MQ_QMAX; q++) {
         std::vector<uint32_t> mem;
         for (uint32_t k = 0; k < j.bpats.size(); k++)
-            if (route[k] == 2 && std::min<uint32_t>(j.bpats[k].m, MQ_QMAX) == q) mem.push_back(k);
+            if (route[k] == 4 && std::min<uint32_t>(j.bpats[k].m, MQ_QMAX) == q) mem.push_back(k);
         std::stable_sort(mem.begin(), mem.end(), [&](uint32_t x, uint32_t y) { return j.bpats[x].m < j.bpats[y].m; });
         for (size_t b = 0; b < mem.size(); b += MQ_G) {
             const size_t e = std::min(mem.size(), b + (size_t)MQ_G);
@@ -566,16 +616,16 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
             g.q = q;
             g.min_m = j.bpats[mem[b]].m;
             g.max_m = j.bpats[mem[e - 1]].m;
-            g.tab_off = (uint64_t)j.mqw.size() * MQ_TAB_BYTES;
-            j.mqw.push_back(g);
-            j.mqwtab.resize(j.mqwtab.size() + MQ_TAB_BYTES, 0);
-            build_mq_table(j, mem.data() + b, g.count, q, j.mqwtab.data() + g.tab_off, false);
+            g.tab_off = (uint64_t)j.hq.size() * MQ_TAB_BYTES;
+            j.hq.push_back(g);
+            j.hqtab.resize(j.hqtab.size() + MQ_TAB_BYTES, 0);
+            build_mq_table(j, mem.data() + b, g.count, q, j.hqtab.data() + g.tab_off, false);
         }
     }
-    if (j.mqw.size() > j.max_mqw) return err(SM_EDEVICE, "internal: write plan larger than its workspace");
-    // the plan into the workspace region [L.wgroups, L.mqwtabs + tables), one copy
-    // from pinned staging that no earlier upload still reads
-    const uint64_t bytes = j.L.mqwtabs + j.mqwtab.size() - j.L.wgroups;
+    if (j.hq.size() > j.max_hq) return err(SM_EDEVICE, "internal: write plan larger than its workspace");
+    // the plan into the workspace region [L.wgroups, L.mqwlist + list), one copy from
+    // pinned staging that no earlier upload still reads
+    const uint64_t bytes = j.L.hqtabs + j.hqtab.size() - j.L.wgroups;
     if (stg.pending) {
         HIP_OK(hipEventSynchronize(stg.ev));
         stg.pending = false;
@@ -590,8 +640,10 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
     }
     uint8_t *h = stg.host;
     memcpy(h, j.wgroups.data(), j.wgroups.size() * sizeof(BatchGroup));
-    memcpy(h + (j.L.mqwgroups - j.L.wgroups), j.mqw.data(), j.mqw.size() * sizeof(MqGroup));
-    memcpy(h + (j.L.mqwtabs - j.L.wgroups), j.mqwtab.data(), j.mqwtab.size());
+    memcpy(h + (j.L.wroute - j.L.wgroups), j.wroute.data(), j.wroute.size());
+    memcpy(h + (j.L.mqwlist - j.L.wgroups), j.mqwlist.data(), j.mqwlist.size() * 4);
+    memcpy(h + (j.L.hqgroups - j.L.wgroups), j.hq.data(), j.hq.size() * sizeof(MqGroup));
+    memcpy(h + (j.L.hqtabs - j.L.wgroups), j.hqtab.data(), j.hqtab.size());
     HIP_OK(hipMemcpyAsync(ws + j.L.wgroups, h, bytes, hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(stg.ev, st));
     stg.pending = true;
@@ -609,10 +661,14 @@ int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, con
             B.groups = reinterpret_cast<const BatchGroup *>(ws + j.L.wgroups);
             B.host_groups = j.wgroups.data();
             B.ngroups = (uint32_t)j.wgroups.size();
-            B.mqwgroups = reinterpret_cast<const MqGroup *>(ws + j.L.mqwgroups);
-            B.host_mqw = j.mqw.data();
-            B.mqwtabs = ws + j.L.mqwtabs;
-            B.nmqw = (uint32_t)j.mqw.size();
+            B.mqwlist = reinterpret_cast<const uint32_t *>(ws + j.L.mqwlist);
+            B.host_mqwlist = j.mqwlist.data();
+            B.nmqw = (uint32_t)j.mqwlist.size();
+            B.wroute = ws + j.L.wroute;
+            B.hqgroups = reinterpret_cast<const MqGroup *>(ws + j.L.hqgroups);
+            B.host_hq = j.hq.data();
+            B.hqtabs = ws + j.L.hqtabs;
+            B.nhq = (uint32_t)j.hq.size();
         }
         B.chunk_off = reinterpret_cast<const uint64_t *>(ws + j.L.chunk_off);
         B.csr = d_csr;
@@ -647,6 +703,7 @@ struct sm_batch {
     std::vector<uint8_t> pats;
     std::vector<uint64_t> pat_off;
     std::vector<uint64_t> csr;  // host copy, P + 1
+    std::vector<uint32_t> stash_n;  // host copy: hits of each (chunk, filter group) item
     uint8_t *ws = nullptr;
     ~sm_batch()
     {
@@ -679,6 +736,12 @@ extern "C" int sm_batch_open(sm_corpus *c, const uint8_t *pats, const uint64_t *
     if ((r = batch_count_enqueue(b->j, b->ws, nullptr, d_tot, d_csr, true, nullptr))) return r;
     b->csr.resize((uint64_t)P + 1);
     HIP_OK(hipMemcpy(b->csr.data(), d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost));
+    const uint64_t items = batch_stash_items(b->j);
+    if (items) {
+        b->stash_n.resize(items);
+        HIP_OK(hipMemcpy(b->stash_n.data(), b->ws + b->j.L.mqstash_n, items * 4, hipMemcpyDeviceToHost));
+        b->j.h_stash_n = b->stash_n.data();
+    }
     *out = b.release();
     return SM_OK;
 }

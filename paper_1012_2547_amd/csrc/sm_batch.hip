@@ -255,13 +255,29 @@ struct MqArgs {
     uint32_t ngroups, chunk_tiles;
     uint64_t nchunks, ntiles;
     uint32_t *cnt;             // [sorted pattern][chunk]
+    // count pass: the hits of each (chunk, group) item, group index group_base + the
+    // launch's group, nmq groups in all (null: not kept)
+    uint32_t *stash, *stash_n;
+    uint32_t group_base, nmq;
 };
+static_assert(256 * BT <= (1 << MQ_REL_BITS), "a chunk's relative starts fit MQ_REL_BITS");
+static_assert(MQ_G <= (1 << (32 - MQ_REL_BITS)), "counter ids fit above the relative start");
 
 struct MqShared {
     uint4 text[B_CHUNKS];
     uint4 tab[MQ_LDS_BYTES / 16];
     uint32_t acc[MQ_G];
+    uint32_t nst;  // hits of the item so far (the stash keeps the first MQ_STASH)
 };
+
+// k entries of this lane for the item's stash: the index of the first, or
+// MQ_STASH when the item already holds more than MQ_STASH (then it is not kept;
+// the count goes on only until then, so the counter stays small)
+__device__ __forceinline__ uint32_t mq_stash_take(MqShared &S, uint32_t k)
+{
+    if (k == 0 || *(volatile uint32_t *)&S.nst > MQ_STASH) return MQ_STASH;
+    return atomicAdd(&S.nst, k);
+}
 
 // Word k (bytes [4k, 4k + 4)) of the swizzled LDS tile.
 __device__ __forceinline__ uint32_t tile_word(const uint4 *text, uint32_t k)
@@ -369,11 +385,14 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
         const uint4 *src = reinterpret_cast<const uint4 *>(tab);
         for (uint32_t k = tid; k < MQ_LDS_BYTES / 16; k += BLOCK) S.tab[k] = src[k];
         for (uint32_t k = tid; k < g.count; k += BLOCK) S.acc[k] = 0;
+        if (tid == 0) S.nst = 0;
     }
     const uint32_t *poff = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_POFF);
     const uint32_t *bits = reinterpret_cast<const uint32_t *>(S.tab);
     const uint32_t q = g.q;
     const uint32_t mlo = byte_mask(q < 4 ? (int)q : 4), mhi = byte_mask(q > 4 ? (int)q - 4 : 0);
+    const uint64_t sitem = chunk * a.nmq + a.group_base + item % a.ngroups;
+    uint32_t *stash = a.stash ? a.stash + sitem * MQ_STASH : nullptr;
     const uint64_t t0 = chunk * a.chunk_tiles;
     uint64_t t1 = t0 + a.chunk_tiles;
     if (t1 > a.ntiles) t1 = a.ntiles;
@@ -426,14 +445,28 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                     const uint32_t below = wb[b] & ((1u << (hh[b] & 31)) - 1u);
                     kk[b] = ((cm >> b) & 1u) ? (uint32_t)rank[hh[b] >> 5] + (uint32_t)__builtin_popcount(below) : 0u;
                 }
+                uint32_t hm = 0;  // starts of this unit whose hit is kept
+                uint32_t rp[16];
 #pragma unroll
                 for (int b = 0; b < 16; b++) {
                     const int i = b >> 2, sh = b & 3;
                     const uint32_t klo = (sh ? alignbyte(W[i + 1], W[i], sh) : W[i]) & mlo;
                     const uint32_t khi = EXACT ? 0u : ((sh ? alignbyte(W[i + 2], W[i + 1], sh) : W[i + 1]) & mhi);
                     const uint2 p = spre[kk[b]];
-                    const uint32_t rep = srep[kk[b]];
-                    if (((cm >> b) & 1u) && !((p.x ^ klo) | (p.y ^ khi))) atomicAdd(&S.acc[rep], 1u);
+                    rp[b] = srep[kk[b]];
+                    if (((cm >> b) & 1u) && !((p.x ^ klo) | (p.y ^ khi))) {
+                        if (atomicAdd(&S.acc[rp[b]], 1u) < MQ_CAP) hm |= 1u << b;
+                    }
+                }
+                if (stash && hm) {
+                    uint32_t at = mq_stash_take(S, (uint32_t)__builtin_popcount(hm));
+                    const uint32_t rel0 = (uint32_t)(s - t0 * (uint64_t)BT) + (uint32_t)r0;
+#pragma unroll
+                    for (int b = 0; b < 16; b++)
+                        if ((hm >> b) & 1u) {
+                            if (at < MQ_STASH) stash[at] = (rp[b] << MQ_REL_BITS) | (rel0 + (uint32_t)b);
+                            at++;
+                        }
                 }
                 continue;
             }
@@ -447,9 +480,15 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                 const uint32_t x = (uint32_t)(16 * u + b);
                 uint32_t klo, khi, h;
                 mq_key_at<EXACT>(S.text, x, mlo, mhi, klo, khi, h);
+                const uint32_t rel = (uint32_t)(s - t0 * (uint64_t)BT) + (uint32_t)r;
+                auto rec = [&](uint32_t ctr) {
+                    if (atomicAdd(&S.acc[ctr], 1u) < MQ_CAP && stash) {
+                        const uint32_t at = mq_stash_take(S, 1u);
+                        if (at < MQ_STASH) stash[at] = (ctr << MQ_REL_BITS) | rel;
+                    }
+                };
                 mq_slots(S.text, reinterpret_cast<const uint8_t *>(S.tab), a, poff, h, bits[h >> 5], klo, khi,
-                         x, s + (uint64_t)r, q, [&](uint32_t rep) { atomicAdd(&S.acc[rep], 1u); },
-                         [&](uint32_t j) { atomicAdd(&S.acc[j], 1u); });
+                         x, s + (uint64_t)r, q, rec, rec);
             }
         }
     }
@@ -458,6 +497,7 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
     const uint16_t *cid = reinterpret_cast<const uint16_t *>(tab + MQ_OFF_CID);
     for (uint32_t j = tid; j < g.count; j += BLOCK)
         a.cnt[(uint64_t)spi[j] * a.nchunks + chunk] = S.acc[cid[j]];
+    if (stash && tid == 0) a.stash_n[sitem] = S.nst;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,6 +514,12 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
 constexpr int MQW_LIST = 4096;
 static_assert(BT / 4 <= MQW_LIST, "a quarter tile of one pattern must fit the write list");
 
+// Items are (chunk, listed group): group list[k] of f.groups / f.tabs (the group's
+// write table) for k < nlisted, or group k when list is null. Patterns take part
+// when route[sorted] == route_val: 2 for the count groups' patterns whose hits the
+// count pass kept (here only where it did not: an item that overflowed, or more
+// than MQ_CAP hits in the chunk; mq_stash_write_kernel writes the rest), 4 for the
+// window's heavy patterns (groups of their own, nothing kept).
 struct MqwArgs {
     MqArgs f;
     const BatchPat *pats;      // sorted
@@ -481,6 +527,12 @@ struct MqwArgs {
     const uint64_t *csr;       // [original index]
     int64_t *out;              // CSR entry k goes to out[k - lo]
     uint64_t lo, span;
+    const uint32_t *list;
+    uint32_t nlisted, nmq;
+    const uint8_t *route;
+    uint32_t route_val;
+    const uint32_t *stash, *stash_n;  // null: nothing kept
+    const uint8_t *ctabs;             // the count tables (counter ids)
 };
 
 struct MqwShared {
@@ -499,8 +551,12 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
     __shared__ MqwShared S;
     const MqArgs &a = w.f;
     const uint64_t item = blockIdx.x;
-    const uint64_t chunk = item / a.ngroups;
-    const MqGroup g = a.groups[item % a.ngroups];
+    const uint64_t chunk = item / w.nlisted;
+    const uint32_t gi = w.list ? w.list[item % w.nlisted] : (uint32_t)(item % w.nlisted);
+    // the count pass kept the item's entries: patterns with at most MQ_CAP hits in
+    // the chunk are written from them (mq_stash_write_kernel), the others here
+    const bool kept = w.stash_n && w.stash_n[chunk * w.nmq + gi] <= MQ_STASH;
+    const MqGroup g = a.groups[gi];
     const int tid = threadIdx.x;
     const uint8_t *tab = a.tabs + g.tab_off;
     const uint32_t *spi = reinterpret_cast<const uint32_t *>(tab + MQ_OFF_SPI);
@@ -511,7 +567,8 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
     __syncthreads();
     for (uint32_t j = tid; j < g.count; j += BLOCK) {
         const uint64_t sp = spi[j];
-        const uint32_t c = a.cnt[sp * a.nchunks + chunk];
+        uint32_t c = w.route[sp] == w.route_val ? a.cnt[sp * a.nchunks + chunk] : 0u;
+        if (kept && c <= MQ_CAP) c = 0;  // written from the stash
         const uint64_t r0 = c ? w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk] : 0;
         const bool on = c && r0 < wend && r0 + c > w.lo;
         S.act[j] = on ? 1 : 0;
@@ -650,6 +707,84 @@ __global__ __launch_bounds__(BLOCK) void mq_write_kernel(MqwArgs w)
                 break;
             }
             jlo = jhi;
+        }
+    }
+}
+
+// Write pass of the items whose hits the count pass kept: the item's entries
+// (counter << MQ_REL_BITS | start in the chunk) are sorted in LDS, so each
+// counter's hits come in ascending order; entry k of counter c is hit number
+// k - first(c) in the chunk of every taking-part pattern counted by c (duplicates
+// and the m == q patterns of a slot share one counter). Threads take consecutive
+// entries, so a pattern's positions are stored coalesced. The text is not read.
+__global__ __launch_bounds__(BLOCK) void mq_stash_write_kernel(MqwArgs w)
+{
+    __shared__ uint32_t s_e[MQ_STASH];
+    __shared__ uint32_t s_head[MQ_G];   // counter -> first taking-part pattern, or MQ_NONE
+    __shared__ uint32_t s_next[MQ_G];   // pattern -> next one on the same counter
+    __shared__ uint64_t s_base[MQ_G];   // pattern -> CSR entry of its first hit in the chunk
+    __shared__ int s_any;
+    const MqArgs &a = w.f;
+    const uint64_t chunk = blockIdx.x / w.nlisted;
+    const uint32_t gi = w.list[blockIdx.x % w.nlisted];
+    const uint64_t sitem = chunk * w.nmq + gi;
+    const uint32_t ne = w.stash_n[sitem];
+    if (ne == 0 || ne > MQ_STASH) return;  // uniform
+    const MqGroup g = a.groups[gi];
+    const uint8_t *ctab = w.ctabs + g.tab_off;
+    const uint32_t *spi = reinterpret_cast<const uint32_t *>(ctab + MQ_OFF_SPI);
+    const uint16_t *cid = reinterpret_cast<const uint16_t *>(ctab + MQ_OFF_CID);
+    const int tid = threadIdx.x;
+    const uint64_t wend = w.lo + w.span;
+    for (uint32_t k = tid; k < (uint32_t)MQ_G; k += BLOCK) s_head[k] = MQ_NONE;
+    if (tid == 0) s_any = 0;
+    uint32_t n2 = 64;
+    while (n2 < ne) n2 <<= 1;
+    const uint32_t *src = w.stash + sitem * MQ_STASH;
+    for (uint32_t k = tid; k < n2; k += BLOCK) s_e[k] = k < ne ? src[k] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t j = tid; j < g.count; j += BLOCK) {
+        const uint64_t sp = spi[j];
+        const uint32_t c = w.route[sp] == 2 ? a.cnt[sp * a.nchunks + chunk] : 0u;
+        if (!c || c > MQ_CAP) continue;  // counters above MQ_CAP were not kept
+        const uint64_t r0 = w.csr[w.pats[sp].index] + w.chunk_off[sp * a.nchunks + chunk];
+        if (!(r0 < wend && r0 + c > w.lo)) continue;
+        s_base[j] = r0;
+        s_next[j] = atomicExch(&s_head[cid[j]], j);
+        s_any = 1;
+    }
+    __syncthreads();
+    if (!s_any) return;  // uniform
+    // bitonic sort, ascending
+    for (uint32_t k = 2; k <= n2; k <<= 1)
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = tid; i < n2; i += BLOCK) {
+                const uint32_t ixj = i ^ jj;
+                if (ixj > i) {
+                    const uint32_t x = s_e[i], y = s_e[ixj];
+                    if ((x > y) == ((i & k) == 0)) {
+                        s_e[i] = y;
+                        s_e[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    const uint64_t s0 = chunk * (uint64_t)a.chunk_tiles * (uint64_t)BT;
+    constexpr uint32_t RMASK = (1u << MQ_REL_BITS) - 1u;
+    for (uint32_t k = tid; k < ne; k += BLOCK) {
+        const uint32_t e = s_e[k], c = e >> MQ_REL_BITS;
+        uint32_t j = s_head[c];
+        if (j == MQ_NONE) continue;
+        uint32_t b0 = 0, b1 = k;  // first entry of counter c
+        while (b0 < b1) {
+            const uint32_t mid = (b0 + b1) >> 1;
+            if ((s_e[mid] >> MQ_REL_BITS) < c) b0 = mid + 1; else b1 = mid;
+        }
+        const int64_t pos = (int64_t)(s0 + (e & RMASK));
+        for (; j != MQ_NONE; j = s_next[j]) {
+            const uint64_t idx = s_base[j] + (k - b0);
+            if (idx - w.lo < w.span) w.out[idx - w.lo] = pos;
         }
     }
 }
@@ -804,12 +939,11 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         if ((e = launch_batch_class(hg[g].algo, hg[g].var, a, L.write, st)) != hipSuccess) return e;
         g = h;
     }
-    if (L.write && L.nmqw) {
+    if (L.write && (L.nmqw || L.nhq)) {
         MqwArgs w;
         memset(&w, 0, sizeof w);
         w.f.text = L.text;
         w.f.n = L.n;
-        w.f.tabs = L.mqwtabs;
         w.f.patbytes = L.patbytes;
         w.f.chunk_tiles = L.chunk_tiles;
         w.f.nchunks = L.nchunks;
@@ -821,20 +955,64 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         w.out = L.out;
         w.lo = L.lo;
         w.span = L.span;
-        uint32_t nexact = 0;
-        while (nexact < L.nmqw && L.host_mqw[nexact].q <= 2) nexact++;
-        for (int pass = 0; pass < 2; pass++) {
-            const uint32_t g0 = pass ? nexact : 0, g1 = pass ? L.nmqw : nexact;
-            if (g1 == g0) continue;
-            w.f.groups = L.mqwgroups + g0;
-            w.f.ngroups = g1 - g0;
-            const uint64_t grid = L.nchunks * (g1 - g0);
+        w.nmq = L.nmq;
+        w.route = L.wroute;
+        // a filter pass over the text: groups[list[k]] (list null: groups[k]) for k < ng,
+        // the exact-key groups (q <= 2) and the hashed ones in launches of their own.
+        // list is the device copy (kernel argument), host_list the host one, host the
+        // host copy of the groups (both read here to split the launches).
+        auto rescan = [&](const uint32_t *list, const uint32_t *host_list, const MqGroup *host,
+                          uint32_t ng) -> hipError_t {
+            uint32_t nexact = 0;
+            while (nexact < ng && host[host_list ? host_list[nexact] : nexact].q <= 2) nexact++;
+            for (int pass = 0; pass < 2; pass++) {
+                const uint32_t g0 = pass ? nexact : 0, g1 = pass ? ng : nexact;
+                if (g1 == g0) continue;
+                if (list) {
+                    w.list = list + g0;
+                } else {
+                    w.list = nullptr;
+                    w.f.groups += g0;
+                }
+                w.nlisted = g1 - g0;
+                const uint64_t grid = L.nchunks * (g1 - g0);
+                if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+                if (pass == 0)
+                    hipLaunchKernelGGL(mq_write_kernel<true>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
+                else
+                    hipLaunchKernelGGL(mq_write_kernel<false>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
+                if (!list) w.f.groups -= g0;
+                hipError_t e2 = hipGetLastError();
+                if (e2 != hipSuccess) return e2;
+            }
+            return hipSuccess;
+        };
+        if (L.nmqw && L.mqstash) {
+            // the patterns whose hits the count pass kept: copied out, then the items
+            // where it did not keep them scanned again
+            w.f.groups = L.mqgroups;
+            w.f.tabs = L.mqwtabs;
+            w.f.ngroups = L.nmq;
+            w.route_val = 2;
+            w.stash = L.mqstash;
+            w.stash_n = L.mqstash_n;
+            w.ctabs = L.mqtabs;
+            w.list = L.mqwlist;
+            w.nlisted = L.nmqw;
+            const uint64_t grid = L.nchunks * L.nmqw;
             if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
-            if (pass == 0)
-                hipLaunchKernelGGL(mq_write_kernel<true>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
-            else
-                hipLaunchKernelGGL(mq_write_kernel<false>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
+            hipLaunchKernelGGL(mq_stash_write_kernel, dim3((uint32_t)grid), dim3(BLOCK), 0, st, w);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = rescan(L.mqwlist, L.host_mqwlist, L.host_mq, L.nmqw)) != hipSuccess) return e;
+        }
+        if (L.nhq) {  // the heavy patterns: one filter pass of their own groups
+            w.f.groups = L.hqgroups;
+            w.f.tabs = L.hqtabs;
+            w.f.ngroups = L.nhq;
+            w.route_val = 4;
+            w.stash = nullptr;
+            w.stash_n = nullptr;
+            if ((e = rescan(nullptr, nullptr, L.host_hq, L.nhq)) != hipSuccess) return e;
         }
     }
     if (!L.write && L.nmq) {
@@ -850,6 +1028,9 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         m.nchunks = L.nchunks;
         m.ntiles = L.ntiles;
         m.cnt = L.cnt;
+        m.stash = L.mqstash;
+        m.stash_n = L.mqstash_n;
+        m.nmq = L.nmq;
         // one launch for the exact-key groups (q <= 2), one for the hashed ones; the
         // groups are ordered by q, so each launch takes a contiguous range
         uint32_t nexact = 0;
@@ -859,6 +1040,7 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
             if (g1 == g0) continue;
             m.groups = L.mqgroups + g0;
             m.ngroups = g1 - g0;
+            m.group_base = g0;
             const uint64_t grid = L.nchunks * (g1 - g0);
             if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
             if (pass == 0)

@@ -13,8 +13,8 @@
 namespace sm {
 
 struct BatchLayout {  // byte offsets inside the batch workspace
-    uint64_t pats, groups, cgroups, mqgroups, mqtabs, params, patbytes, cnt, chunk_off, totals, csr,
-        wgroups, mqwgroups, mqwtabs, single, need;
+    uint64_t pats, groups, cgroups, mqgroups, mqtabs, mqwtabs, params, patbytes, cnt, chunk_off, totals,
+        csr, wgroups, wroute, mqwlist, hqgroups, hqtabs, mqstash, mqstash_n, single, need;
 };
 
 struct BatchJob {
@@ -27,14 +27,26 @@ struct BatchJob {
     std::vector<BatchGroup> cgroups;  // count pass: patterns outside the prefix filter
     std::vector<MqGroup> mq;          // count pass: prefix filter groups
     std::vector<uint8_t> mqtab;       // their tables (MQ_TAB_BYTES each)
+    std::vector<uint8_t> mqwtab;      // the same groups' write tables (every pattern with its slot)
+    std::vector<int32_t> mq_of;       // sorted pattern -> its filter group, or -1
     uint32_t mq_max_m = 0;
+    // the count pass keeps each (chunk, filter group) item's hits when they fit
+    // (MQ_STASH); after the count, h_stash_n (nchunks x mq.size(), host, set by the
+    // caller) tells which items kept them
+    bool stash = false;
+    const uint32_t *h_stash_n = nullptr;
     // write plan, built from the counts (batch_write_plan); without one the write
     // pass runs every pattern's own scanner (groups)
     bool wplan = false;
     std::vector<BatchGroup> wgroups;  // per-pattern write groups
-    std::vector<MqGroup> mqw;         // prefix filter write groups
-    std::vector<uint8_t> mqwtab;
-    uint32_t max_mqw = 0;             // filter write groups the layout has room for
+    // per sorted pattern: 2 = written from the filter's kept hits (a pass over its count
+    // group's items), 4 = by a filter pass over the text with the window's other such
+    // patterns (hq groups); 1 own scanner, 3 single-pattern pipeline
+    std::vector<uint8_t> wroute;
+    std::vector<uint32_t> mqwlist;    // count groups with route-2 patterns in the window
+    std::vector<MqGroup> hq;          // route-4 patterns of the window, by q-class and length
+    std::vector<uint8_t> hqtab;       // their tables
+    uint32_t max_hq = 0;              // hq groups the layout has room for
     std::vector<uint32_t> longp;      // m > BATCH_MAX_M: searched one pattern at a time
     // write plan: patterns of the window dense enough that the single-pattern
     // pipeline (bitmap form, coalesced emit) beats a batch rescan; possible when the
@@ -60,6 +72,9 @@ int batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, uint3
 // Bytes of the host image uploaded by the count step (pattern table, groups and
 // pattern bytes), and its contents.
 uint64_t batch_image_bytes(const BatchJob &j);
+// (chunk, filter group) items whose hit counts the count step leaves at L.mqstash_n
+// (u32 each) for the write plan; 0 when the job keeps no hits.
+uint64_t batch_stash_items(const BatchJob &j);
 void batch_fill_image(const BatchJob &j, uint8_t *dst);
 
 // Count step: uploads the image (h_image: batch_fill_image's output, pinned or

@@ -184,6 +184,15 @@ constexpr int MQ_G = 1024;                  // patterns per group
 constexpr int MQ_QMAX = 8;                  // longest prefix gram (two 32-bit words)
 constexpr int MQ_MIN = 3;                   // smallest q-class sent to the filter
 constexpr uint32_t MQ_NONE = 0xFFFF;
+// The filter's count pass keeps the hits of each (chunk, group) item -- counter id
+// << MQ_REL_BITS | start relative to the chunk -- of every counter with at most
+// MQ_CAP hits in the chunk, MQ_STASH entries per item at most, so that the write
+// pass copies them out instead of scanning the chunk again. A pattern is served
+// from the stash in a chunk when the item kept its entries (stash_n <= MQ_STASH)
+// and its count there is at most MQ_CAP.
+constexpr uint32_t MQ_STASH = 4096;
+constexpr uint32_t MQ_CAP = 64;
+constexpr int MQ_REL_BITS = 22;  // a chunk is at most 256 tiles of BLOCK * BATCH_LANE starts
 
 // Table of one group (byte offsets; the part below MQ_LDS_BYTES is staged in LDS).
 constexpr uint32_t MQ_OFF_BITS = 0;                                // u32[MQ_WORDS]
@@ -241,10 +250,21 @@ struct BatchLaunch {
     uint32_t ncgroups;
     const MqGroup *mqgroups;        // count pass, prefix filter (ordered by q)
     const MqGroup *host_mq;
-    const MqGroup *mqwgroups;       // write pass, prefix filter (ordered by q)
-    const MqGroup *host_mqw;
+    // write pass, prefix filter: the count groups listed in mqwlist (ascending, so
+    // the q <= 2 groups come first), with their write tables (every pattern listed
+    // with its slot), for the patterns with wroute[sorted] == 2
     const uint8_t *mqwtabs;
+    const uint32_t *mqwlist;
+    const uint32_t *host_mqwlist;
     uint32_t nmqw;
+    const uint8_t *wroute;
+    // write pass, filter pass over the text for the window's route-4 patterns
+    const MqGroup *hqgroups;
+    const MqGroup *host_hq;
+    const uint8_t *hqtabs;
+    uint32_t nhq;
+    uint32_t *mqstash;              // [chunk][group] MQ_STASH hits each (count pass writes)
+    uint32_t *mqstash_n;            // [chunk][group] hits (more than MQ_STASH: not kept)
     const uint8_t *mqtabs;
     uint32_t nmq, mq_max_m;
     const Params *params;

@@ -86,6 +86,8 @@ struct HipExec {
         uint64_t h_image_cap = 0;
         uint64_t *h_csr = nullptr;
         uint64_t h_csr_cap = 0;
+        uint32_t *h_stash_n = nullptr;  // hits kept per (chunk, filter group) item
+        uint64_t h_stash_n_cap = 0;
         std::vector<uint8_t> pats;
         std::vector<uint64_t> pat_off;
         BatchJob job;
@@ -167,6 +169,8 @@ struct HipExec {
         if ((r = grow_dev(&s.ws, &s.ws_cap, j.L.need))) return r;
         if ((r = grow_host(&s.h_image, &s.h_image_cap, std::max<uint64_t>(batch_image_bytes(j), 256)))) return r;
         if ((r = grow_host(&s.h_csr, &s.h_csr_cap, ((uint64_t)P + 1) * 8))) return r;
+        const uint64_t items = batch_stash_items(j);
+        if ((r = grow_host(&s.h_stash_n, &s.h_stash_n_cap, std::max<uint64_t>(items * 4, 256)))) return r;
         batch_fill_image(j, s.h_image);
         uint64_t *d_tot = (uint64_t *)(s.ws + j.L.totals), *d_csr = (uint64_t *)(s.ws + j.L.csr);
         // graphs for batches of patterns within the batch kernels' reach (longer ones
@@ -176,6 +180,8 @@ struct HipExec {
             int rr = batch_count_enqueue(j, s.ws, s.h_image, d_tot, d_csr, true, s.st);
             if (rr) return rr;
             HIP_OK(hipMemcpyAsync(s.h_csr, d_csr, ((uint64_t)P + 1) * 8, hipMemcpyDeviceToHost, s.st));
+            if (items)
+                HIP_OK(hipMemcpyAsync(s.h_stash_n, s.ws + j.L.mqstash_n, items * 4, hipMemcpyDeviceToHost, s.st));
             return SM_OK;
         });
         if (r) return r;
@@ -198,6 +204,7 @@ struct HipExec {
         TraceRange tr("serve.write.enqueue");
         HIP_OK(hipSetDevice(dev));
         BatchJob &j = s.job;
+        j.h_stash_n = batch_stash_items(j) ? s.h_stash_n : nullptr;
         uint64_t *d_tot = (uint64_t *)(s.ws + j.L.totals), *d_csr = (uint64_t *)(s.ws + j.L.csr);
         uint64_t nw = 0;
         int r = SM_OK;
@@ -243,6 +250,7 @@ void destroy_slots(std::vector<HipExec::Slot> &slots)
         if (s.pool) (void)hipFree(s.pool);
         if (s.h_image) (void)hipHostFree(s.h_image);
         if (s.h_csr) (void)hipHostFree(s.h_csr);
+        if (s.h_stash_n) (void)hipHostFree(s.h_stash_n);
         if (s.ev_count) (void)hipEventDestroy(s.ev_count);
         if (s.ev_done) (void)hipEventDestroy(s.ev_done);
         if (s.count_exec) (void)hipGraphExecDestroy(s.count_exec);

@@ -199,6 +199,37 @@ def test_batch_filter_write_overflowing_rounds(sm, policy):
     c.close()
 
 
+@pytest.mark.parametrize("policy", [0, 2])
+def test_batch_filter_stash_and_rescan_items(sm, policy):
+    """The filter's count step keeps each (chunk, group) item's hits when they fit; the
+    write pass copies those out and scans the other items again. A run of zero bytes
+    overflows the few items it covers (three zero patterns, sparse over the whole text,
+    hit every start there); every other item keeps its hits. Written whole and in
+    windows cut inside the zero patterns' slices."""
+    n = 16 << 20
+    t_np = dg.uniform_text(n, 4, seed=81)
+    t_np[(5 << 20):(5 << 20) + 40_000] = 0
+    pats = [dg.substring_pattern(t_np, 9 + i % 6, seed=82, idx=i)[0] for i in range(300)]
+    pats += [bytes(9), bytes(12), bytes(10)]
+    pats += pats[:5] + [bytes(12)]                                        # duplicates
+    sm.batch_set_write_policy(policy)
+    try:
+        c = sm.Corpus(t_np)
+        pos, off = c.batch_find_all(pats)
+        check_csr(sm, t_np, pats, pos, off)
+        assert off[301] - off[300] > 30_000                                 # the zero run
+        b = c.batch_open(pats)
+        d = torch.empty(b.total, dtype=torch.int64, device=DEV)
+        cuts = [0, int(off[300]) + 777, int(off[302]) + 5, b.total]
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            b.write_async(lo, hi, d[lo:hi])
+        assert np.array_equal(d.cpu().numpy(), pos)
+        b.close()
+        c.close()
+    finally:
+        sm.batch_set_write_policy(0)
+
+
 def test_batch_shared_write_dense_tile_of_one_pattern(sm):
     """A pattern sparse on average but with a hit at every start of one tile (a run
     of zero bytes): its tile overflows the shared write pass's list even alone and
