@@ -602,14 +602,18 @@ int sm::batch_write_plan(BatchJob &j, uint8_t *ws, const uint64_t *h_csr, uint64
         for (size_t g = 0; g < nmq; g++)
             if (used[g]) j.mqwlist.push_back((uint32_t)g);
     }
-    // filter pass groups of the heavy patterns: each q-class by length, in groups of MQ_G
-    for (uint32_t q = 1; q <= (uint32_t)MQ_QMAX; q++) {
+    // filter pass groups of the heavy patterns: every q-class together, by length, in
+    // groups of MQ_G, each hashing the prefix its shortest pattern has (q = min(m,
+    // MQ_QMAX)): a pass over the text costs per start whatever the group holds, so a
+    // window's few heavy patterns of several lengths share one pass
+    {
         std::vector<uint32_t> mem;
         for (uint32_t k = 0; k < j.bpats.size(); k++)
-            if (route[k] == 4 && std::min<uint32_t>(j.bpats[k].m, MQ_QMAX) == q) mem.push_back(k);
+            if (route[k] == 4) mem.push_back(k);
         std::stable_sort(mem.begin(), mem.end(), [&](uint32_t x, uint32_t y) { return j.bpats[x].m < j.bpats[y].m; });
         for (size_t b = 0; b < mem.size(); b += MQ_G) {
             const size_t e = std::min(mem.size(), b + (size_t)MQ_G);
+            const uint32_t q = std::min<uint32_t>(j.bpats[mem[b]].m, MQ_QMAX);
             MqGroup g;
             memset(&g, 0, sizeof g);
             g.count = (uint32_t)(e - b);
