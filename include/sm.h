@@ -59,14 +59,18 @@ enum sm_algo {
                               m - 49 verified (a start one period, <= 49, after an occurrence
                               without reading): linear on texts of one symbol, where the
                               planner takes it for every m */
-    SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3) */
+    SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3); with q = 2 or 4
+                              the window's last q bytes are read at once (BNDMq, Fig. 3) */
     SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
     SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
     SM_ALGO_BLOCK = 5,     /* 16-byte block fingerprint filter after SSEF (Fig. 1), 144 <= m <= 4096:
                               one 16-byte block per m - 15 text bytes is read and looked up among
                               the pattern's blocks, candidates verified byte-exactly */
-    SM_ALGO_BRUTE = 6      /* brute force (Fig. 1, BF) over packed bytes, m <= 8: the four starts of a
+    SM_ALGO_BRUTE = 6,     /* brute force (Fig. 1, BF) over packed bytes, m <= 8: the four starts of a
                               text word are compared with the pattern at once, byte-parallel */
+    SM_ALGO_FSBNDM = 7     /* Forward SBNDM (Fig. 3), m <= 63: SBNDM for the pattern followed by one
+                              position that matches any byte, so the byte after the window is read
+                              first as a look-ahead */
 };
 
 /*
@@ -81,7 +85,8 @@ enum sm_algo {
 typedef struct sm_opts {
     int32_t algo;         /* enum sm_algo */
     int32_t lane_bytes;   /* candidate starts per lane; a tile is 256 * lane_bytes starts */
-    int32_t q;            /* Hash-q gram length, 1..16; for SBNDM the q-gram read at once, 1, 2, 4 or 8 */
+    int32_t q;            /* Hash-q gram length, 1..16; for SBNDM the q-gram read at once, 1, 2, 4 or 8;
+                             for BNDM 1, 2 or 4 */
     int32_t sigma_hint;   /* expected alphabet size of the text (planner input only) */
     int32_t tiles_per_wg; /* consecutive tiles per workgroup, >= 1 */
     int32_t hbits;        /* Hash-q table has 2^hbits buckets */

@@ -14,13 +14,13 @@ import ctypes
 
 import numpy as np
 
-from ._native import (ALGO_AUTO, ALGO_BLOCK, ALGO_BNDM, ALGO_BRUTE, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
+from ._native import (ALGO_AUTO, ALGO_BLOCK, ALGO_BNDM, ALGO_BRUTE, ALGO_FSBNDM, ALGO_HASHQ, ALGO_NAMES, ALGO_SBNDM,
                       ALGO_SHIFT_AND, SM_OK, SM_TRUNCATED, Opts, PlanInfo, Prof, SmError,
                       TuneEntry, check, last_error, load)
 
 __all__ = ["pack_patterns", "find_all", "count", "find_all_async", "find_all_noalloc", "count_async", "workspace_size", "plan_query",
            "Corpus", "opts", "prof_enable", "prof_collect", "tune_get", "tune_set", "SmError", "ALGO_AUTO",
-           "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_BLOCK", "ALGO_BRUTE", "ALGO_NAMES", "version",
+           "ALGO_SHIFT_AND", "ALGO_BNDM", "ALGO_SBNDM", "ALGO_HASHQ", "ALGO_BLOCK", "ALGO_BRUTE", "ALGO_FSBNDM", "ALGO_NAMES", "version",
            "Batch", "Server", "batch_set_wave_bytes", "batch_set_write_policy", "now_ns", "workspace_size_upto"]
 
 

@@ -13,7 +13,9 @@ STATUS_NAMES = {0: "SM_OK", 1: "SM_TRUNCATED", -1: "SM_EINVAL", -2: "SM_ENOMEM",
                 -3: "SM_EDEVICE", -4: "SM_EBUSY"}
 
 ALGO_AUTO, ALGO_SHIFT_AND, ALGO_BNDM, ALGO_SBNDM, ALGO_HASHQ, ALGO_BLOCK, ALGO_BRUTE = 0, 1, 2, 3, 4, 5, 6
-ALGO_NAMES = {0: "auto", 1: "shift_and", 2: "bndm", 3: "sbndm", 4: "hashq", 5: "block", 6: "brute"}
+ALGO_FSBNDM = 7
+ALGO_NAMES = {0: "auto", 1: "shift_and", 2: "bndm", 3: "sbndm", 4: "hashq", 5: "block", 6: "brute",
+              7: "fsbndm"}
 
 
 class SmError(RuntimeError):

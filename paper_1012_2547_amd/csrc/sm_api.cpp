@@ -208,6 +208,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
                     (unsigned long long)m);
     if ((o->algo == ALGO_BNDM || o->algo == ALGO_SBNDM) && m > BP_MAX_M)
         return fail(SM_EINVAL, "BNDM and SBNDM need m <= %d (m = %llu)", BP_MAX_M, (unsigned long long)m);
+    if (o->algo == ALGO_FSBNDM && m > (uint64_t)FSBNDM_MAX_M)
+        return fail(SM_EINVAL, "FSBNDM needs m <= %d (m = %llu)", FSBNDM_MAX_M, (unsigned long long)m);
     if (o->q && (uint64_t)o->q > m)
         return fail(SM_EINVAL, "q = %d exceeds m = %llu", o->q, (unsigned long long)m);
 
@@ -223,6 +225,7 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && m > BP_MAX_M) algo = 0;
     if (algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M)) algo = 0;
     if (algo == ALGO_BRUTE && m > (uint64_t)BRUTE_MAX_M) algo = 0;
+    if (algo == ALGO_FSBNDM && m > (uint64_t)FSBNDM_MAX_M) algo = 0;
     if (have && te.algo == ALGO_HASHQ && te.q && (uint64_t)te.q > m) algo = 0;
     // the block filter expects varied 16-byte blocks: not on a text of (nearly) one symbol
     if (algo == ALGO_BLOCK && sigma < 2) algo = 0;
@@ -250,6 +253,11 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     if (algo == ALGO_SBNDM) {  // q-gram width of the window's first read
         const int q = o->q ? o->q : (use_entry ? te.q : 0);
         if (q > 1 && q != 2 && q != 4 && q != 8) return fail(SM_EINVAL, "SBNDM takes q in {1, 2, 4, 8} (got %d)", q);
+        p.q = (q > 1 && (uint64_t)q <= m) ? q : 0;
+    }
+    if (algo == ALGO_BNDM) {  // BNDMq: the window's last q bytes at once
+        const int q = o->q ? o->q : (use_entry ? te.q : 0);
+        if (q > 1 && q != 2 && q != 4) return fail(SM_EINVAL, "BNDM takes q in {1, 2, 4} (got %d)", q);
         p.q = (q > 1 && (uint64_t)q <= m) ? q : 0;
     }
     if (algo == ALGO_HASHQ) {

@@ -129,7 +129,7 @@ __device__ __forceinline__ uint32_t batch_lane(BatchShared<ALGO, VAR> &S, const 
                                                   boff, lo, hi, o);
     } else if (ALGO == ALGO_BNDM) {
         if (lo > hi) return 0u;
-        return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text),
+        return lane_bndm<1, WRITE>(reinterpret_cast<const uint8_t *>(S.text),
                                 reinterpret_cast<const uint64_t *>(tab), m, boff, lo, hi, o);
     } else if (ALGO == ALGO_SBNDM) {
         if (lo > hi) return 0u;

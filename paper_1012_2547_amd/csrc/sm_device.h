@@ -280,8 +280,11 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const MT *m
     return cnt;
 }
 
-// BNDM: masks B[c] bit i set iff p[m-1-i] == c.
-template <bool WRITE, class E>
+// BNDM: masks B[c] bit i set iff p[m-1-i] == c. Q > 1 is the q-gram form (BNDMq,
+// Fig. 3): the window's last Q bytes are read at once (Q independent mask lookups
+// combined by shifts); the suffixes shorter than Q are then not tested as prefixes of
+// p, so the shift of a window is at most m - Q + 1. Needs Q <= m.
+template <int Q, bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_t *B, int m,
                                              int li0, int lo, int hi, E &o)
 {
@@ -290,9 +293,32 @@ __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_
     uint32_t cnt = 0;
     int pos = lo;
     while (pos <= hi) {
+        const uint8_t *w = lds8 + li0 + pos;
+        if (Q > 1) {
+            // D after reading w[m - Q .. m - 1]: byte w[m-1-i] enters shifted by Q-1-i
+            uint64_t D = B[w[m - Q]];
+#pragma unroll
+            for (int i = 0; i < Q - 1; i++) D &= B[w[m - 1 - i]] << (Q - 1 - i);
+            int j = m - Q, last = m - Q + 1;
+            while (D != 0) {
+                if (D & HB) {
+                    if (j > 0) {
+                        last = j;
+                    } else {
+                        if (WRITE) o.put(pos); else cnt++;
+                        break;
+                    }
+                }
+                if (j == 0) break;
+                D <<= 1;
+                j--;
+                D &= B[w[j]];
+            }
+            pos += last;
+            continue;
+        }
         int j = m, last = m;
         uint64_t D = ALL;
-        const uint8_t *w = lds8 + li0 + pos;
         do {
             j--;
             D &= B[w[j]];
@@ -307,6 +333,39 @@ __device__ __forceinline__ uint32_t lane_bndm(const uint8_t *lds8, const uint64_
             D <<= 1;
         } while (D != 0 && j > 0);
         pos += last;
+    }
+    return cnt;
+}
+
+// FSBNDM (Forward SBNDM, Fig. 3): SBNDM for p' = p x, the pattern followed by one
+// position x that matches any byte, over windows of m + 1 bytes: the byte after
+// the window is read first (a look-ahead, as in Sunday's Quick Search). The masks of
+// p' are B'[c] = (B[c] << 1) | 1 (bit 0 is x). An occurrence of p' at pos is one of p;
+// a window whose last k bytes are not a factor of p' is left with a shift of
+// m + 2 - k. fwd_hi: the last start whose byte after the window lies in the text;
+// later starts take x alone. After an occurrence the shift is p's smallest period
+// (p and p' have the same periods). Needs m <= 63.
+template <bool WRITE, class E>
+__device__ __forceinline__ uint32_t lane_fsbndm(const uint8_t *lds8, const uint64_t *B, int m,
+                                               int period, int li0, int lo, int hi, int fwd_hi, E &o)
+{
+    const uint64_t HB = 1ull << m;  // the first byte of p in p'
+    uint32_t cnt = 0;
+    int pos = lo;
+    while (pos <= hi) {
+        const uint8_t *w = lds8 + li0 + pos;  // window w[0 .. m-1], look-ahead w[m]
+        uint64_t D = pos <= fwd_hi ? ((B[w[m]] << 1) | 1ull) : 1ull;
+        int k = 1;
+        while (D != 0 && k <= m) {
+            D = (D << 1) & ((B[w[m - k]] << 1) | 1ull);
+            k++;
+        }
+        if (D & HB) {  // all m + 1 positions read and matched
+            if (WRITE) o.put(pos); else cnt++;
+            pos += period;
+        } else {
+            pos += m + 2 - k;
+        }
     }
     return cnt;
 }
@@ -1029,7 +1088,7 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
         for (uint32_t j = 0; j < ms; j++)
             if (ps[j] != c) w |= 1ull << j;
         P->mask[c] = w;
-    } else if (algo == ALGO_BNDM || algo == ALGO_SBNDM) {
+    } else if (algo == ALGO_BNDM || algo == ALGO_SBNDM || algo == ALGO_FSBNDM) {
         const uint32_t c = tid;
         uint64_t w = 0;
         for (uint32_t i = 0; i < m; i++)

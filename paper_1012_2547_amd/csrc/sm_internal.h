@@ -19,12 +19,14 @@ enum Algo : int32_t {
     ALGO_BLOCK = 5,      // 16-byte block fingerprint filter, BF_MIN_M <= m <= BF_MAX_M (after
                          // SSEF, Fig. 1): reads one block per m - 15 text bytes
     ALGO_BRUTE = 6,      // brute force over packed bytes, m <= BRUTE_MAX_M (Fig. 1, BF)
-    ALGO_COUNT_ = 7
+    ALGO_FSBNDM = 7,     // SBNDM with the character after the window read first, m <= 63 (Fig. 3, FSBNDM)
+    ALGO_COUNT_ = 8
 };
 constexpr int BRUTE_MAX_M = 8;
 
 constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
 constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register
+constexpr int FSBNDM_MAX_M = BP_MAX_M - 1;  // FSBNDM: the pattern and one look-ahead position fit 64 bits
 constexpr int SA_SUFFIX = 49;      // Shift-And for m > SA_SUFFIX scans the pattern's last 49 bytes
 constexpr int SA_STAGE_MAX = 1024 + SA_SUFFIX;  // its tiles stage whole windows up to this m
 constexpr int Q_MAX = 16;          // longest hashed q-gram

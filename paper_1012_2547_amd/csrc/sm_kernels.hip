@@ -177,7 +177,8 @@ __device__ __forceinline__ TileGeom tile_geom(const ScanArgs &a, uint64_t t)
     g.hi_rel = lim >= (uint64_t)(T - 1) ? T - 1 : (int)lim;
     g.r0 = (ALGO == ALGO_HASHQ) ? (int)(a.m - a.q) : 0;
     g.x0 = g.s + (uint64_t)g.r0;
-    g.x1 = g.s + (uint64_t)g.hi_rel + a.m;  // one past the last byte any window reads
+    // one past the last byte any window reads (FSBNDM: and the byte after it)
+    g.x1 = g.s + (uint64_t)g.hi_rel + a.m + (ALGO == ALGO_FSBNDM ? 1u : 0u);
     if (g.x1 > a.n) g.x1 = a.n;
     return g;
 }
@@ -253,8 +254,14 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
         if (VAR == 1) return lane_shift_and<uint64_t, 16, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
         if (VAR == 2) return lane_shift_and<uint64_t, 4, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
         return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
-    } else if constexpr (ALGO == ALGO_BNDM) {
-        return lane_bndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
+    } else if constexpr (ALGO == ALGO_BNDM) {  // VAR selects the q-gram width 1, 2, 4
+        constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : 4);
+        return lane_bndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
+    } else if constexpr (ALGO == ALGO_FSBNDM) {
+        // the last relative start whose byte after the window lies in the text
+        const int64_t fh = (int64_t)a.n - (int64_t)m - 1 - (int64_t)s;
+        return lane_fsbndm<WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0, lo, hi,
+                                  fh < (int64_t)hi ? (int)fh : hi, o);
     } else if constexpr (ALGO == ALGO_BRUTE) {
         return lane_brute<WRITE>(S.text, bw.w, m, li0, lo, hi, o);
     } else if constexpr (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
@@ -1088,7 +1095,11 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
         if (m <= 17) return launch_l<ALGO_SHIFT_AND, 0, KIND>(p, a, grid, st);
         return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
     }
-    case ALGO_BNDM: return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
+    case ALGO_BNDM:
+        if (p.q == 2) return launch_l<ALGO_BNDM, 1, KIND>(p, a, grid, st);
+        if (p.q == 4) return launch_l<ALGO_BNDM, 2, KIND>(p, a, grid, st);
+        return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
+    case ALGO_FSBNDM: return launch_l<ALGO_FSBNDM, 0, KIND>(p, a, grid, st);
     case ALGO_BRUTE: return launch_l<ALGO_BRUTE, 0, KIND>(p, a, grid, st);
     case ALGO_SBNDM:
         if (p.q <= 1) return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);

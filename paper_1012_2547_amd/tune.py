@@ -2,7 +2,8 @@
 
 For each alphabet-size bucket (representative sigma in 2, 4, 16, 64, 256) and a
 grid of pattern lengths, every applicable configuration -- algorithm (Shift-And,
-BNDM, SBNDM, Hash-q with its gram length q, the block filter, brute force), starts per lane
+BNDM and BNDMq, SBNDM and SBNDMq, forward SBNDM, Hash-q with its gram length q, the block
+filter, brute force), starts per lane
 and tiles per workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
 benchmark's seed 1) with substring patterns, as whole find_all calls. The
 fastest configuration of each cell becomes a table entry. The paper's own
@@ -29,14 +30,14 @@ QS = (2, 3, 4, 5, 6, 8, 10, 12, 16)
 
 
 def candidates(m: int, sigma: int):
-    """Every option is explicit (plain SBNDM is q = 1), so that no entry of the
+    """Every option is explicit (plain BNDM and SBNDM are q = 1), so that no entry of the
     library's built-in table fills in a value left at 0."""
     out = []
     if m <= 64:
         for algo in (1, 2, 3):
             for L in (32, 64, 128):
                 for tpw in (1, 2, 4):
-                    out.append(dict(algo=algo, lane_bytes=L, q=1 if algo == 3 else 0, tiles_per_wg=tpw))
+                    out.append(dict(algo=algo, lane_bytes=L, q=1 if algo in (2, 3) else 0, tiles_per_wg=tpw))
         if m <= 8:  # brute force over packed bytes
             for L in (32, 64, 128):
                 for tpw in (1, 2, 4):
@@ -47,6 +48,15 @@ def candidates(m: int, sigma: int):
             for L in (32, 64, 128):
                 for tpw in (1, 2, 4):
                     out.append(dict(algo=3, lane_bytes=L, q=q, tiles_per_wg=tpw))
+        if m >= 8:
+            for q in (2, 4):  # BNDMq: the window's last q bytes read at once
+                for L in (32, 64, 128):
+                    for tpw in (1, 2, 4):
+                        out.append(dict(algo=2, lane_bytes=L, q=q, tiles_per_wg=tpw))
+            if m <= 63:  # forward SBNDM: one extra bit for the look-ahead byte
+                for L in (32, 64, 128):
+                    for tpw in (1, 2, 4):
+                        out.append(dict(algo=7, lane_bytes=L, q=0, tiles_per_wg=tpw))
     for q in QS:
         if q > m or sigma ** q < m:  # too few distinct q-grams to skip anything
             continue

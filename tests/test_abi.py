@@ -190,7 +190,7 @@ def test_tuning_table_roundtrip(L):
     import paper_1012_2547_amd as sm
     base = sm.tune_get()
     assert len(base) > 50
-    assert all(1 <= e["algo"] <= 6 and e["m_lo"] <= e["m_hi"] for e in base)
+    assert all(1 <= e["algo"] <= 7 and e["m_lo"] <= e["m_hi"] for e in base)
     # every (sigma, m) of the sweep grid is covered by some entry
     for s in (2, 4, 16, 64, 256):
         for m in (1, 2, 3, 5, 8, 63, 64, 65, 100, 1000, 5000):
@@ -208,7 +208,7 @@ def test_tuning_table_roundtrip(L):
     with pytest.raises(sm.SmError):
         sm.tune_set([dict(sigma_lo=1, sigma_hi=2, m_lo=5, m_hi=1, algo=1)])
     with pytest.raises(sm.SmError):
-        sm.tune_set([dict(sigma_lo=1, sigma_hi=2, m_lo=1, m_hi=5, algo=7)])
+        sm.tune_set([dict(sigma_lo=1, sigma_hi=2, m_lo=1, m_hi=5, algo=8)])
 
 
 def test_sigma_estimate_from_pattern_steers_plan(L):

@@ -25,7 +25,8 @@ def sm():
 
 DEV = "cuda:0"
 BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (m <= 64)
-ALL_ALGOS = (1, 2, 3, 4, 5, 6)   # + Hash-q, block filter (144 <= m <= 4096), brute force (m <= 8)
+ALL_ALGOS = (1, 2, 3, 4, 5, 6, 7)  # + Hash-q, block filter (144 <= m <= 4096), brute force (m <= 8),
+                                   # FSBNDM (m <= 63)
 
 
 def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0):
@@ -54,6 +55,8 @@ def applicable(algo, m, q=0):
         return 144 <= m <= 4096
     if algo == 6:
         return m <= 8
+    if algo == 7:
+        return m <= 63
     return m >= max(q, 1)
 
 
@@ -119,6 +122,44 @@ def test_sbndm_every_q(sm):
                     assert np.array_equal(got, want) and tot == want.size, (sigma, len(p), q, L)
     with pytest.raises(sm.SmError):
         gpu_find(sm, t_dev, b"abcdefgh", algo=3, lane=64, q=3)
+
+
+def test_bndm_q_and_fsbndm(sm):
+    """BNDMq (the window's last q = 2 or 4 bytes read at once; shifts capped at m - q + 1)
+    and FSBNDM (the byte after the window read first as a look-ahead) on small and large
+    alphabets, with periodic patterns, q = m, occurrences at both text ends (the last
+    windows have no look-ahead byte) and lanes of 16 and 64 starts."""
+    n = 40_000 + 13
+    for sigma in (2, 4, 64):
+        t_np = dg.uniform_text(n, sigma, seed=23)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        pats = [dg.substring_pattern(t_np, m, seed=29, idx=m)[0] for m in (2, 3, 4, 5, 8, 9, 17, 31, 50, 63, 64)]
+        pats += [b"\x01\x00" * 16, bytes(t_np[:8]), bytes(t_np[-12:]), bytes(t_np[-63:]), bytes(t_np[:2])]
+        for p in pats:
+            want = oracle.find_all(t_np, p)
+            for L, tpw in ((16, 1), (64, 2)):
+                for q in (2, 4):
+                    if q > len(p):
+                        continue
+                    got, tot = gpu_find(sm, t_dev, p, algo=2, lane=L, q=q, tpw=tpw)
+                    assert np.array_equal(got, want) and tot == want.size, ("bndm", sigma, len(p), q, L)
+                if len(p) <= 63:
+                    got, tot = gpu_find(sm, t_dev, p, algo=7, lane=L, tpw=tpw)
+                    assert np.array_equal(got, want) and tot == want.size, ("fsbndm", sigma, len(p), L)
+    # texts of one symbol: every window matches up to its end
+    a_n = np.full(5000, 7, dtype=np.uint8)
+    a_dev = torch.from_numpy(a_n).to(DEV)
+    for m in (2, 5, 33, 63):
+        want = oracle.find_all(a_n, bytes([7]) * m)
+        for a, q in ((2, 2), (2, 4), (7, 0)):
+            if q > m:
+                continue
+            got, tot = gpu_find(sm, a_dev, bytes([7]) * m, algo=a, lane=64, q=q)
+            assert np.array_equal(got, want), (a, q, m)
+    with pytest.raises(sm.SmError):
+        gpu_find(sm, t_dev, b"abcdefgh", algo=2, lane=64, q=8)
+    with pytest.raises(sm.SmError):
+        gpu_find(sm, t_dev, bytes(64), algo=7, lane=64)
 
 
 def test_block_filter(sm):
