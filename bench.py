@@ -51,17 +51,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {
+    "count": ("sm_kernels.hip", "sm_device.h", "sm_internal.h"),
+    "mq_count": ("sm_batch.hip", "sm_device.h", "sm_internal.h"),
+}
+# dense VALU issue of the chip: 256 CUs x 4 SIMD16 units x 16 lanes x 2.4 GHz (one wave64
+# instruction per CU per clock)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def kernel_source_hash(kernel: str = "count") -> str:
     h = hashlib.sha256()
-    for f in ("sm_kernels.hip", "sm_device.h", "sm_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1012_2547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source; else None."""
+def load_counters(kernel: str):
+    """Per-launch counter figures of a kernel from the committed rocprofv3 --pmc
+    summary, if they were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -69,9 +78,16 @@ def load_traffic(kernel: str):
     except OSError:
         return None
     e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(kernel):
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; else None."""
+    e = load_counters(kernel)
+    return e.get("bytes_per_launch") if e else None
 
 
 def main():
@@ -455,6 +471,34 @@ def batched_section(args, dev, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3 / reps
+    # the shared multi-pattern filter (mq_count_kernel) timed with HIP events on the
+    # stream it runs on, in passes of their own
+    sm.prof_collect()
+    sm.prof_enable(True, every=1)
+    for _ in range(reps):
+        corpus.batch_count_async(pats, d_b, work, stream)
+    torch.cuda.synchronize()
+    sm.prof_enable(False)
+    pr = sm.prof_collect()
+    filt_s = pr["filter_ms"] / max(pr["filter_launches"], 1) / 1e3
+    ctr = load_counters("mq_count")
+    roof = {"bound": "alu", "unit": "TOP/s", "peak": round(VALU_PEAK_TOPS, 2),
+            "kernel": "mq_count_kernel (shared multi-pattern q-gram filter)",
+            "launches": pr["filter_launches"], "avg_launch_us": round(filt_s * 1e6, 1),
+            "filter_share_of_pass": round(pr["filter_ms"] / max(pr["batch_ms"], 1e-9), 3),
+            "filter_pattern_GBps": round(pr["filter_pattern_bytes"] / max(pr["filter_ms"], 1e-9) / 1e6, 1),
+            "achieved": None, "frac": None, "traffic": None, "counters": None}
+    if ctr and filt_s > 0:
+        # VALU lane-operations issued per launch (SQ_INSTS_VALU x 64) over the live duration
+        ops = ctr["valu_insts_per_launch"] * 64
+        roof["achieved"] = round(ops / filt_s / 1e12, 2)
+        roof["frac"] = round(ops / filt_s / 1e12 / VALU_PEAK_TOPS, 4)
+        roof["traffic"] = ctr.get("bytes_per_launch")
+        roof["counters"] = {k: ctr[k] for k in ("valu_insts_per_launch", "lds_insts_per_launch",
+                                                "lds_bank_conflict_cycles_per_launch",
+                                                "gui_active_cycles_per_launch") if k in ctr}
+    log("batched: filter %d launches, %.1f us avg, %.0f%% of the count pass" % (
+        roof["launches"], roof["avg_launch_us"], 100 * roof["filter_share_of_pass"]))
     # plain: one single-pattern count per pattern
     w1 = torch.empty(sm.workspace_size_upto(n, 1024), dtype=torch.uint8,
                      device=dev)
@@ -483,7 +527,8 @@ def batched_section(args, dev, stream):
             "batched_pattern_GBps": round(P * n / t_batch / 1e9, 1),
             "plain_pattern_GBps": round(P * n / t_plain / 1e9, 1),
             "speedup_vs_plain": round(t_plain / t_batch, 2),
-            "occurrences": int(cb.sum()), "counts_agree_with_plain": agree}
+            "occurrences": int(cb.sum()), "counts_agree_with_plain": agree,
+            "roofline": roof}
 
 
 def batched_find_all_section(args, dev):

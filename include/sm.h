@@ -61,7 +61,10 @@ enum sm_algo {
                               planner takes it for every m */
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3); with q = 2 or 4
                               the window's last q bytes are read at once (BNDMq, Fig. 3) */
-    SM_ALGO_SBNDM = 3,     /* Simplified BNDM, m <= 64 (Fig. 3) */
+    SM_ALGO_SBNDM = 3,     /* Simplified BNDM (Fig. 3); any m: for m > 64 its factor form, in which
+                              the pattern's last 64 bytes are searched and the first m - 64 of each
+                              start found are verified (after the factor's own occurrences the
+                              window shifts by the factor's period) */
     SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
     SM_ALGO_BLOCK = 5,     /* 16-byte block fingerprint filter after SSEF (Fig. 1), 144 <= m <= 4096:
                               one 16-byte block per m - 15 text bytes is read and looked up among
@@ -75,8 +78,8 @@ enum sm_algo {
 
 /*
  * Tuning options. A NULL sm_opts*, or zero in a field, means "planner's choice".
- * Options change speed only, never results. Invalid combinations (BNDM or SBNDM
- * with m > 64, the block filter with m outside [144, 4096], brute force with
+ * Options change speed only, never results. Invalid combinations (BNDM with
+ * m > 64, FSBNDM with m > 63, the block filter with m outside [144, 4096], brute force with
  * m > 8, q > m or
  * q > 16, lane_bytes not in {16,32,64,128}, hbits outside [8,12]) are SM_EINVAL.
  * lane_bytes, q and hbits do not apply to the block filter (its tile is the
@@ -413,6 +416,13 @@ typedef struct sm_prof {
     uint64_t text_bytes;   /* sum of n over the calls */
     uint64_t sampled_calls;   /* of the calls, those whose count pass is the block filter, */
     double sampled_count_ms;  /* which reads one 16-byte block per m - 15 bytes, and its time */
+    /* batched count passes (sm_batch_count*, sm_batch_open): while recording is on,
+     * every pass not captured into a HIP graph is recorded, whatever the stride */
+    uint64_t batch_calls;          /* passes recorded */
+    double batch_ms;               /* their whole time: preparation, scanner groups, filter, scans */
+    uint64_t filter_launches;      /* shared multi-pattern filter launches (mq_count_kernel) in them */
+    double filter_ms;              /* time of those launches */
+    uint64_t filter_pattern_bytes; /* sum over the passes of n x patterns in the filter's groups */
 } sm_prof;
 int sm_prof_enable(int every);
 int sm_prof_collect(sm_prof *out);

@@ -452,4 +452,7 @@ def prof_collect() -> dict:
     check(load().sm_prof_collect(ctypes.byref(p)))
     return {"calls": p.calls, "count_ms": p.count_ms, "emit_ms": p.emit_ms,
             "total_ms": p.total_ms, "text_bytes": p.text_bytes,
-            "sampled_calls": p.sampled_calls, "sampled_count_ms": p.sampled_count_ms}
+            "sampled_calls": p.sampled_calls, "sampled_count_ms": p.sampled_count_ms,
+            "batch_calls": p.batch_calls, "batch_ms": p.batch_ms,
+            "filter_launches": p.filter_launches, "filter_ms": p.filter_ms,
+            "filter_pattern_bytes": p.filter_pattern_bytes}

@@ -48,7 +48,9 @@ class Prof(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_uint64), ("count_ms", ctypes.c_double),
                 ("emit_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("text_bytes", ctypes.c_uint64), ("sampled_calls", ctypes.c_uint64),
-                ("sampled_count_ms", ctypes.c_double)]
+                ("sampled_count_ms", ctypes.c_double), ("batch_calls", ctypes.c_uint64),
+                ("batch_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
+                ("filter_ms", ctypes.c_double), ("filter_pattern_bytes", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):

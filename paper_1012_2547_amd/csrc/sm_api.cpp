@@ -206,8 +206,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     if (o->algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M))
         return fail(SM_EINVAL, "the block filter needs %d <= m <= %d (m = %llu)", BF_MIN_M, BF_MAX_M,
                     (unsigned long long)m);
-    if ((o->algo == ALGO_BNDM || o->algo == ALGO_SBNDM) && m > BP_MAX_M)
-        return fail(SM_EINVAL, "BNDM and SBNDM need m <= %d (m = %llu)", BP_MAX_M, (unsigned long long)m);
+    if (o->algo == ALGO_BNDM && m > BP_MAX_M)
+        return fail(SM_EINVAL, "BNDM needs m <= %d (m = %llu)", BP_MAX_M, (unsigned long long)m);
     if (o->algo == ALGO_FSBNDM && m > (uint64_t)FSBNDM_MAX_M)
         return fail(SM_EINVAL, "FSBNDM needs m <= %d (m = %llu)", FSBNDM_MAX_M, (unsigned long long)m);
     if (o->q && (uint64_t)o->q > m)
@@ -222,7 +222,7 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     const bool have = tune_lookup(sigma, m, te);
     int algo = have ? te.algo : 0;
     // entries not applicable to this m
-    if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && m > BP_MAX_M) algo = 0;
+    if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && algo != ALGO_SBNDM && m > BP_MAX_M) algo = 0;
     if (algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M)) algo = 0;
     if (algo == ALGO_BRUTE && m > (uint64_t)BRUTE_MAX_M) algo = 0;
     if (algo == ALGO_FSBNDM && m > (uint64_t)FSBNDM_MAX_M) algo = 0;
@@ -304,7 +304,46 @@ std::mutex g_prof_mu;
 uint32_t g_prof_every = 0;  // 0: off; k: every k-th call is recorded
 uint64_t g_prof_seen = 0;   // calls since enabling
 std::vector<ProfRec> g_prof;
+std::vector<BatchProfRec> g_prof_batch;
 }  // namespace
+
+bool sm::prof_batch_begin(hipStream_t st, BatchProfRec &r)
+{
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_every) return false;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    memset(&r, 0, sizeof r);
+    hipEvent_t *ev[4] = {&r.e0, &r.e1, &r.e2, &r.e3};
+    for (int k = 0; k < 4; k++) {
+        if (hipEventCreate(ev[k]) != hipSuccess) {
+            for (int j = 0; j < k; j++) (void)hipEventDestroy(*ev[j]);
+            return false;
+        }
+    }
+    if (hipEventRecord(r.e0, st) != hipSuccess) {
+        prof_batch_discard(r);
+        return false;
+    }
+    return true;
+}
+
+void sm::prof_batch_push(const BatchProfRec &r)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_batch.push_back(r);
+}
+
+void sm::prof_batch_discard(BatchProfRec &r)
+{
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+    (void)hipEventDestroy(r.e2);
+    (void)hipEventDestroy(r.e3);
+    memset(&r, 0, sizeof r);
+}
 
 extern "C" int sm_prof_enable(int every)
 {
@@ -319,9 +358,11 @@ extern "C" int sm_prof_collect(sm_prof *out)
 {
     if (!out) return fail(SM_EINVAL, "out is NULL");
     std::vector<ProfRec> recs;
+    std::vector<BatchProfRec> brecs;
     {
         std::lock_guard<std::mutex> g(g_prof_mu);
         recs.swap(g_prof);
+        brecs.swap(g_prof_batch);
     }
     memset(out, 0, sizeof *out);
     int st = SM_OK;
@@ -345,6 +386,20 @@ extern "C" int sm_prof_collect(sm_prof *out)
         (void)hipEventDestroy(r.e1);
         (void)hipEventDestroy(r.e2);
         (void)hipEventDestroy(r.e3);
+    }
+    for (auto &r : brecs) {
+        float a = 0, b = 0;
+        if (hipEventSynchronize(r.e3) == hipSuccess && hipEventElapsedTime(&a, r.e1, r.e2) == hipSuccess &&
+            hipEventElapsedTime(&b, r.e0, r.e3) == hipSuccess) {
+            out->batch_calls++;
+            out->batch_ms += b;
+            out->filter_launches += r.filter_launches;
+            out->filter_ms += a;
+            out->filter_pattern_bytes += r.filter_pattern_bytes;
+        } else {
+            st = fail(SM_EDEVICE, "event timing failed");
+        }
+        prof_batch_discard(r);
     }
     return st;
 }

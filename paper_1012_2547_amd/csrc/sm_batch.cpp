@@ -290,8 +290,9 @@ int sm::batch_plan(sm_corpus *c, const uint8_t *pats, const uint64_t *pat_off, u
         int r = plan_pattern(pats + pat_off[i], m, sigma, p);
         if (r) return r;
         if (p.algo == ALGO_BLOCK || p.algo == ALGO_BRUTE || p.algo == ALGO_FSBNDM ||  // single-pattern
-            (p.algo == ALGO_SHIFT_AND && m > (uint64_t)BP_MAX_M)) {  // only: the batch takes Hash-q,
-            sm_opts o;                                               // Shift-And or SBNDM
+            ((p.algo == ALGO_SHIFT_AND || p.algo == ALGO_SBNDM) &&  // only: the batch takes Hash-q,
+             m > (uint64_t)BP_MAX_M)) {                              // Shift-And or SBNDM (m <= 64)
+            sm_opts o;
             memset(&o, 0, sizeof o);
             o.algo = p.algo == ALGO_BRUTE ? ALGO_SHIFT_AND : (p.algo == ALGO_FSBNDM ? ALGO_SBNDM : ALGO_HASHQ);
             o.sigma_hint = sigma;

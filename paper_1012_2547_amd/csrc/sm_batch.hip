@@ -901,8 +901,22 @@ hipError_t launch_csr_scan(const uint64_t *totals, uint64_t P, uint64_t *csr, hi
     return hipGetLastError();
 }
 
+namespace {
+// a batched count pass's timing record, discarded unless the pass reaches its end
+struct BatchProfGuard {
+    BatchProfRec r;
+    bool on = false;
+    ~BatchProfGuard()
+    {
+        if (on) prof_batch_discard(r);
+    }
+};
+}  // namespace
+
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
 {
+    BatchProfGuard bp;
+    if (!L.write) bp.on = prof_batch_begin(st, bp.r);
     BatchArgs a;
     memset(&a, 0, sizeof a);
     a.text = L.text;
@@ -1035,6 +1049,10 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
         // groups are ordered by q, so each launch takes a contiguous range
         uint32_t nexact = 0;
         while (nexact < L.nmq && L.host_mq[nexact].q <= 2) nexact++;
+        if (bp.on) {
+            if ((e = hipEventRecord(bp.r.e1, st)) != hipSuccess) return e;
+            for (uint32_t g = 0; g < L.nmq; g++) bp.r.filter_pattern_bytes += (uint64_t)L.host_mq[g].count * L.n;
+        }
         for (int pass = 0; pass < 2; pass++) {
             const uint32_t g0 = pass ? nexact : 0, g1 = pass ? L.nmq : nexact;
             if (g1 == g0) continue;
@@ -1048,7 +1066,12 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
             else
                 hipLaunchKernelGGL(mq_count_kernel<false>, dim3((uint32_t)grid), dim3(BLOCK), 0, st, m);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+            bp.r.filter_launches++;
         }
+        if (bp.on && (e = hipEventRecord(bp.r.e2, st)) != hipSuccess) return e;
+    } else if (bp.on) {  // no filter groups: an empty filter interval
+        if ((e = hipEventRecord(bp.r.e1, st)) != hipSuccess) return e;
+        if ((e = hipEventRecord(bp.r.e2, st)) != hipSuccess) return e;
     }
     if (!L.write) {
         hipLaunchKernelGGL(batch_seg_scan_kernel, dim3(L.npats), dim3(BLOCK), 0, st, L.pats, L.cnt,
@@ -1059,6 +1082,11 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t st)
                                (uint64_t)L.npats_total, L.csr_out);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
+    }
+    if (bp.on) {
+        if ((e = hipEventRecord(bp.r.e3, st)) != hipSuccess) return e;
+        prof_batch_push(bp.r);
+        bp.on = false;
     }
     return hipSuccess;
 }

@@ -473,18 +473,19 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
     return true;
 }
 
-// Shift-And for m > SA_SUFFIX (its suffix form): the scan finds the pattern's last
-// SA_SUFFIX bytes; each such start g is an occurrence when the first m - SA_SUFFIX
-// bytes match too, read from global memory. A start exactly one period (<=
-// SA_SUFFIX) after the lane's previous occurrence needs no reading: bytes [0, m -
-// period) repeat that occurrence shifted by the period, and the rest lie inside the suffix
-// (the memory idea of Apostolico-Giancarlo and Turbo-BM, Fig. 1). Starts come in
-// ascending order; they are passed on to the emitter o.
-template <class E>
+// Suffix forms for long patterns: the scan finds the pattern's last SFX bytes
+// (Shift-And for m > SA_SUFFIX; SBNDM for m > 64, its factor form); each such start
+// g is an occurrence when the first m - SFX bytes match too, read from global
+// memory. A start exactly one period (<= SFX) after the lane's previous occurrence
+// needs no reading: bytes [0, m - period) repeat that occurrence shifted by the
+// period, and the rest lie inside the suffix (the memory idea of Apostolico-Giancarlo
+// and Turbo-BM, Fig. 1). Starts come in ascending order; they are passed on to the
+// emitter o.
+template <class E, int SFX = SA_SUFFIX>
 struct SuffixVerify {
     E &o;
     const uint8_t *text0, *pat;
-    uint32_t m, period;    // period: the smallest when <= SA_SUFFIX, else 0
+    uint32_t m, period;    // period: the smallest when <= SFX, else 0 (no shortcut)
     uint64_t s;            // tile start (global start of tile-relative start 0)
     int lo;                // the lane's first tile-relative start (bitmap emitters)
     uint64_t last = ~0ull; // this lane's last occurrence
@@ -495,7 +496,7 @@ struct SuffixVerify {
         bool ok = period != 0 && last != ~0ull && g - last == period;
         if (!ok) {  // 64 bytes per round trip: four independent 16-byte loads of each
             ok = true;
-            const uint32_t len = m - (uint32_t)SA_SUFFIX;
+            const uint32_t len = m - (uint32_t)SFX;
             const uint8_t *tl = text0 + g + m - 1, *pl = pat + m + 15;
             for (uint32_t off = 0; off < len && ok; off += 64) {
                 uint32_t d = 0;

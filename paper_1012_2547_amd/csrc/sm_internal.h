@@ -14,7 +14,8 @@ enum Algo : int32_t {
     ALGO_AUTO = 0,
     ALGO_SHIFT_AND = 1,  // bit-parallel prefix automaton, m <= 64 (Fig. 3, SA/SO)
     ALGO_BNDM = 2,       // bit-parallel backward factor automaton, m <= 64 (Fig. 3, BNDM)
-    ALGO_SBNDM = 3,      // BNDM without prefix tracking, m <= 64 (Fig. 3, SBNDM)
+    ALGO_SBNDM = 3,      // BNDM without prefix tracking (Fig. 3, SBNDM); for m > 64 its factor
+                         // form: the pattern's last 64 bytes scanned, the rest verified
     ALGO_HASHQ = 4,      // hashed q-gram skip filter + verification, any m >= q (Fig. 1, HASHq)
     ALGO_BLOCK = 5,      // 16-byte block fingerprint filter, BF_MIN_M <= m <= BF_MAX_M (after
                          // SSEF, Fig. 1): reads one block per m - 15 text bytes
@@ -287,6 +288,22 @@ struct BatchLaunch {
     bool write, prep;
 };
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream);
+
+// Kernel timing of batched count passes (sm_prof_*): while recording is on, every
+// count pass of launch_batch that is not being captured into a graph records
+// events at its start (e0), around its shared-filter launches (e1, e2) and at its
+// end (e3).
+struct BatchProfRec {
+    hipEvent_t e0, e1, e2, e3;
+    uint64_t filter_pattern_bytes;  // n x patterns in the filter groups
+    uint32_t filter_launches;
+};
+// true: the events are created and e0 is recorded on st
+bool prof_batch_begin(hipStream_t st, BatchProfRec &r);
+// hands a finished record (e3 recorded) to sm_prof_collect
+void prof_batch_push(const BatchProfRec &r);
+// destroys the events of a record that will not be finished
+void prof_batch_discard(BatchProfRec &r);
 // csr[0..P] = exclusive scan of totals[0..P)
 hipError_t launch_csr_scan(const uint64_t *totals, uint64_t P, uint64_t *csr, hipStream_t stream);
 

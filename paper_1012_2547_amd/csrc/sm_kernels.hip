@@ -264,8 +264,17 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
                                   fh < (int64_t)hi ? (int)fh : hi, o);
     } else if constexpr (ALGO == ALGO_BRUTE) {
         return lane_brute<WRITE>(S.text, bw.w, m, li0, lo, hi, o);
-    } else if constexpr (ALGO == ALGO_SBNDM) {  // VAR selects the q-gram width 1, 2, 4, 8
-        constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : (VAR == 2 ? 4 : 8));
+    } else if constexpr (ALGO == ALGO_SBNDM) {  // VAR & 3 selects the q-gram width 1, 2, 4, 8
+        constexpr int Q = (VAR & 3) == 0 ? 1 : ((VAR & 3) == 1 ? 2 : ((VAR & 3) == 2 ? 4 : 8));
+        if constexpr (VAR >= 4) {
+            // factor form (m_full > 64): the scan runs over the text shifted by m_full - 64
+            // with the masks of the pattern's last 64 bytes and shifts by their period
+            // after a full read; each start found is an occurrence when the pattern's
+            // first m_full - 64 bytes match too
+            SuffixVerify<E, BP_MAX_M> sv{o, a.text0, a.pat, a.m_full, 0u, s, lo};
+            lane_sbndm<Q, true>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0, lo, hi, sv);
+            return sv.n;
+        }
         return lane_sbndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, period, li0,
                                     lo, hi, o);
     } else {
@@ -1008,8 +1017,10 @@ __global__ __launch_bounds__(BLOCK) void prep_kernel(PrepArgs a)
     // reads rather than generic ones for the inline copy)
     __shared__ uint32_t s_bad[PERIOD_MAX + 1];
     __shared__ __align__(16) uint32_t s_key[BF_BUILD_LDS];
-    if (a.inline_len) build_tables(s_pat, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
-    else build_tables(a.pat, m, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
+    // SBNDM's factor form (m > 64): masks and period of the pattern's last 64 bytes
+    const uint32_t fo = (a.algo == ALGO_SBNDM && m > (uint32_t)BP_MAX_M) ? m - BP_MAX_M : 0u;
+    if (a.inline_len) build_tables(s_pat + fo, m - fo, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
+    else build_tables(a.pat + fo, m - fo, a.algo, a.q, a.hbits, P, s_tab, s_bad, s_key);
 }
 
 __global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }
@@ -1101,7 +1112,13 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
         return launch_l<ALGO_BNDM, 0, KIND>(p, a, grid, st);
     case ALGO_FSBNDM: return launch_l<ALGO_FSBNDM, 0, KIND>(p, a, grid, st);
     case ALGO_BRUTE: return launch_l<ALGO_BRUTE, 0, KIND>(p, a, grid, st);
-    case ALGO_SBNDM:
+    case ALGO_SBNDM:  // variants 0..3: q = 1, 2, 4, 8; 4..7: the same, factor form (m > 64)
+        if (p.m > (uint64_t)BP_MAX_M) {
+            if (p.q <= 1) return launch_l<ALGO_SBNDM, 4, KIND>(p, a, grid, st);
+            if (p.q == 2) return launch_l<ALGO_SBNDM, 5, KIND>(p, a, grid, st);
+            if (p.q == 4) return launch_l<ALGO_SBNDM, 6, KIND>(p, a, grid, st);
+            return launch_l<ALGO_SBNDM, 7, KIND>(p, a, grid, st);
+        }
         if (p.q <= 1) return launch_l<ALGO_SBNDM, 0, KIND>(p, a, grid, st);
         if (p.q == 2) return launch_l<ALGO_SBNDM, 1, KIND>(p, a, grid, st);
         if (p.q == 4) return launch_l<ALGO_SBNDM, 2, KIND>(p, a, grid, st);
@@ -1144,6 +1161,14 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
             a.n = n - sh;
             a.m = SA_SUFFIX;
         }
+    }
+    if (plan.algo == ALGO_SBNDM && plan.m > (uint64_t)BP_MAX_M) {  // factor form (n >= m)
+        const uint64_t sh = plan.m - BP_MAX_M;
+        a.text0 = d_text;
+        a.m_full = (uint32_t)plan.m;
+        a.text = d_text + sh;
+        a.n = n - sh;
+        a.m = BP_MAX_M;
     }
     return a;
 }

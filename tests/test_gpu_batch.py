@@ -246,3 +246,33 @@ def test_batch_shared_write_dense_tile_of_one_pattern(sm):
         c.close()
     finally:
         sm.batch_set_write_policy(0)
+
+
+def test_batch_count_profiling_records(sm):
+    """While kernel timing is on, each batched count pass is recorded with its shared
+    filter launches and the n x patterns they cover; the counts stay exact; recording
+    off leaves nothing to collect."""
+    t_np = dg.uniform_text(300_000, 4, seed=91)
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    pats = [dg.random_pattern(3 + i % 5, 4, seed=92, idx=i) for i in range(400)]
+    c = sm.Corpus(t_dev)
+    work = torch.empty(c.batch_workspace_size(pats), dtype=torch.uint8, device=DEV)
+    d_counts = torch.zeros(len(pats), dtype=torch.int64, device=DEV)
+    want = np.array([oracle.count(t_np, p) for p in pats], dtype=np.uint64)
+    sm.prof_collect()
+    sm.prof_enable(True, every=5)  # batched passes are recorded whatever the stride
+    try:
+        for _ in range(3):
+            c.batch_count_async(pats, d_counts, work)
+    finally:
+        sm.prof_enable(False)
+    pr = sm.prof_collect()
+    assert np.array_equal(d_counts.cpu().numpy().astype(np.uint64), want)
+    assert pr["batch_calls"] == 3
+    assert pr["filter_launches"] >= 3 and pr["filter_ms"] > 0
+    assert 0 < pr["filter_ms"] <= pr["batch_ms"]
+    assert pr["filter_pattern_bytes"] > 0 and pr["filter_pattern_bytes"] % t_np.size == 0
+    assert pr["filter_pattern_bytes"] <= 3 * len(pats) * t_np.size
+    c.batch_count_async(pats, d_counts, work)
+    assert sm.prof_collect()["batch_calls"] == 0
+    c.close()

@@ -67,8 +67,8 @@ PLANS = {
     12: [(SA, 128, 0, 1), (BNDM, 16, 0, 1), (SBNDM, 64, 2, 2), (HASHQ, 64, 0, 1)],
     40: [(SA, 32, 0, 1), (BNDM, 64, 0, 1), (SBNDM, 64, 8, 1), (HASHQ, 16, 0, 1)],
     64: [(SA, 64, 0, 1), (BNDM, 64, 0, 1), (SBNDM, 128, 8, 1), (HASHQ, 64, 0, 2)],
-    100: [(SA, 128, 0, 1), (SA, 16, 0, 1), (HASHQ, 64, 0, 1)],
-    300: [(BLOCK, 0, 0, 2), (HASHQ, 64, 0, 1), (SA, 64, 0, 1)],
+    100: [(SA, 128, 0, 1), (SA, 16, 0, 1), (HASHQ, 64, 0, 1), (SBNDM, 64, 8, 1)],
+    300: [(BLOCK, 0, 0, 2), (HASHQ, 64, 0, 1), (SA, 64, 0, 1), (SBNDM, 128, 4, 2)],
     1024: [(BLOCK, 0, 0, 1), (HASHQ, 128, 0, 1)],
 }
 
@@ -166,7 +166,7 @@ def test_many_tiles_every_scanner(sm):
         m = len(p)
         w = oracle.find_all(t_np, p, threads=THREADS)
         algos = [a for a in (SA, BNDM, SBNDM, HASHQ, BLOCK, BRUTE)
-                 if (a in (SA, HASHQ)) or (a in (BNDM, SBNDM) and m <= 64)
+                 if (a in (SA, SBNDM, HASHQ)) or (a == BNDM and m <= 64)
                  or (a == BLOCK and 144 <= m <= 4096) or (a == BRUTE and m <= 8)]
         for a in algos:
             for lane in ((0,) if a == BLOCK else (16, 64, 128)):

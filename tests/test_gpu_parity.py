@@ -24,7 +24,7 @@ def sm():
 
 
 DEV = "cuda:0"
-BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (m <= 64)
+BP_ALGOS = (1, 2, 3)          # Shift-And, BNDM, SBNDM (beyond m = 64: suffix / factor forms)
 ALL_ALGOS = (1, 2, 3, 4, 5, 6, 7)  # + Hash-q, block filter (144 <= m <= 4096), brute force (m <= 8),
                                    # FSBNDM (m <= 63)
 
@@ -49,8 +49,10 @@ def gpu_find(sm, text_t, pat, algo=0, lane=0, q=0, cap=None, tpw=0, sigma_hint=0
 
 
 def applicable(algo, m, q=0):
-    if algo in BP_ALGOS:
+    if algo == 2:
         return m <= 64
+    if algo in BP_ALGOS:  # Shift-And and SBNDM take any m
+        return True
     if algo == 5:
         return 144 <= m <= 4096
     if algo == 6:
@@ -122,6 +124,45 @@ def test_sbndm_every_q(sm):
                     assert np.array_equal(got, want) and tot == want.size, (sigma, len(p), q, L)
     with pytest.raises(sm.SmError):
         gpu_find(sm, t_dev, b"abcdefgh", algo=3, lane=64, q=3)
+
+
+def test_sbndm_factor_form(sm):
+    """SBNDM for m > 64, its factor form: the pattern's last 64 bytes searched over the
+    text shifted by m - 64, the first m - 64 bytes of each start found verified. Every q,
+    lanes of 16, 64 and 128 starts, lengths 65 .. 3100 (beyond 3072 the pattern reaches
+    the preparation kernel through the workspace), occurrences at both text ends,
+    patterns whose last 64 bytes occur without the rest, and periodic patterns with
+    many overlapping occurrences (dense tiles, written by the emit pass's rescan)."""
+    n = 60_000 + 11
+    rng = np.random.default_rng(37)
+    for sigma in (2, 4, 64):
+        t_np = dg.uniform_text(n, sigma, seed=31 + sigma)
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        pats = [dg.substring_pattern(t_np, m, seed=41, idx=m)[0]
+                for m in (65, 66, 97, 128, 143, 200, 1100, 3100)]
+        pats += [bytes(t_np[:70]), bytes(t_np[-129:])]
+        for m in (80, 300):  # the factor occurs, the prefix does not
+            sub = dg.substring_pattern(t_np, m, seed=43, idx=m)[0]
+            pre = bytes((rng.integers(0, sigma, m - 64) + 1) % 256)
+            pats.append(pre + sub[-64:])
+        for p in pats:
+            want = oracle.find_all(t_np, p)
+            for q in (1, 2, 4, 8):
+                for L, tpw in ((16, 1), (64, 2), (128, 1)):
+                    got, tot = gpu_find(sm, t_dev, p, algo=3, lane=L, q=q, tpw=tpw)
+                    assert np.array_equal(got, want) and tot == want.size, (sigma, len(p), q, L)
+    # periodic text and patterns: every second (third) start an occurrence
+    for unit, reps, tail in ((b"ab", 40, b""), (b"ab", 60, b"a"), (b"abc", 43, b"ab")):
+        t_np = np.frombuffer(unit * (n // len(unit)), dtype=np.uint8).copy()
+        t_np[5000:5003] = ord("z")  # one break in the period
+        t_dev = torch.from_numpy(t_np).to(DEV)
+        p = unit * reps + tail
+        want = oracle.find_all(t_np, p)
+        assert want.size > 10_000
+        for q in (1, 8):
+            for L in (16, 128):
+                got, tot = gpu_find(sm, t_dev, p, algo=3, lane=L, q=q)
+                assert np.array_equal(got, want) and tot == want.size, (len(p), q, L)
 
 
 def test_bndm_q_and_fsbndm(sm):
