@@ -214,7 +214,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
 
     # dominant kernel: the count kernel, one pass over the text (n bytes per launch).
-    # Calls planned on the block filter read one 16-byte block per m - 15 bytes;
+    # Calls planned on the block filter read one aligned 16-byte block per S <= m - 15 bytes;
     # they are reported apart and left out of the roofline figure.
     calls_n = max(prof["calls"], 1)
     full_n = max(prof["calls"] - prof["sampled_calls"], 1)
@@ -223,7 +223,7 @@ def main():
     sampled = None
     if prof["sampled_calls"]:
         avg_s = prof["sampled_count_ms"] / prof["sampled_calls"] / 1e3
-        sampled = {"kernel": "block_count_kernel (one 16-byte block per m - 15 text bytes)",
+        sampled = {"kernel": "block_count_kernel (one aligned 16-byte block per 16*floor((m - 15)/16) text bytes)",
                    "launches": prof["sampled_calls"], "avg_launch_us": round(avg_s * 1e6, 2),
                    "text_equivalent_gbs": round(n / avg_s / 1e9, 1)}
     algo_bytes_call = (n * len(calls) + 8 * occ_total) / len(calls)

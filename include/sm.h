@@ -67,7 +67,8 @@ enum sm_algo {
                               window shifts by the factor's period) */
     SM_ALGO_HASHQ = 4,     /* Hash-q: hashed q-gram skip + verification, any m >= q (Fig. 1) */
     SM_ALGO_BLOCK = 5,     /* 16-byte block fingerprint filter after SSEF (Fig. 1), 144 <= m <= 4096:
-                              one 16-byte block per m - 15 text bytes is read and looked up among
+                              one aligned 16-byte block per S text bytes (S the largest multiple of 16
+                              <= m - 15) is read and looked up among
                               the pattern's blocks, candidates verified byte-exactly */
     SM_ALGO_BRUTE = 6,     /* brute force (Fig. 1, BF) over packed bytes, m <= 8: the four starts of a
                               text word are compared with the pattern at once, byte-parallel */
@@ -415,7 +416,7 @@ typedef struct sm_prof {
     double total_ms;       /* whole calls: pattern preparation + all kernels */
     uint64_t text_bytes;   /* sum of n over the calls */
     uint64_t sampled_calls;   /* of the calls, those whose count pass is the block filter, */
-    double sampled_count_ms;  /* which reads one 16-byte block per m - 15 bytes, and its time */
+    double sampled_count_ms;  /* which reads one 16-byte block per about m - 15 bytes, and its time */
     /* batched count passes (sm_batch_count*, sm_batch_open): while recording is on,
      * every pass not captured into a HIP graph is recorded, whatever the stride */
     uint64_t batch_calls;          /* passes recorded */

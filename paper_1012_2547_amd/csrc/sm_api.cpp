@@ -269,7 +269,7 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     // at n = 2^30 for m = 4 .. 1000: the best or within 2 % of it at every m)
     p.lane_bytes = o->lane_bytes ? o->lane_bytes
                                  : (use_entry && te.lane_bytes ? te.lane_bytes : (one_symbol ? 128 : 64));
-    if (algo == ALGO_BLOCK) p.lane_bytes = (int32_t)(m - 15);  // starts per sampled block
+    if (algo == ALGO_BLOCK) p.lane_bytes = (int32_t)bf_stride(m);  // starts per sampled block
     p.tiles_per_wg = o->tiles_per_wg ? o->tiles_per_wg
                                      : (use_entry && te.tiles_per_wg ? te.tiles_per_wg : (one_symbol ? 2 : 1));
     // a tile of 256 * L starts expects 256 * L * sigma^-m hits on an i.i.d. text: at
@@ -432,16 +432,24 @@ static bool plan_keeps_bitmap(const Plan &p)
     return p.m <= (uint64_t)BP_MAX_M || p.algo == ALGO_SHIFT_AND;
 }
 
+static uint64_t plan_lead(const Plan &p) { return p.algo == ALGO_BLOCK ? BF_LEAD : 0; }
+
 extern "C" uint64_t sm_workspace_size(uint64_t n, uint64_t m, const sm_opts *opts)
 {
     // explicit lanes, else the smallest the planner could pick for this m (the
-    // block filter's tiles of 256 (m - 15) starts are larger than any lanes' tiles)
-    int lb = (opts && opts->lane_bytes) ? opts->lane_bytes : min_auto_lane(m);
-    if (opts && opts->algo == ALGO_BLOCK && m >= (uint64_t)BF_MIN_M && m <= (uint64_t)BF_MAX_M)
-        lb = (int)(m - 15);
+    const bool block_range = m >= (uint64_t)BF_MIN_M && m <= (uint64_t)BF_MAX_M;
     Plan p;
-    p.lane_bytes = lb;
-    return ws_layout(n, m, tile_starts(p), may_keep_bitmap(m, opts)).need;
+    p.lane_bytes = (opts && opts->lane_bytes) ? opts->lane_bytes : min_auto_lane(m);
+    uint64_t need = 0;
+    if (!(opts && opts->algo == ALGO_BLOCK && block_range))
+        need = ws_layout(n, m, tile_starts(p), may_keep_bitmap(m, opts)).need;
+    // the block filter, when forced or when the planner may take it (its tiles of
+    // 256 blocks may start BF_LEAD starts early)
+    if (block_range && (!opts || opts->algo == ALGO_AUTO || opts->algo == ALGO_BLOCK)) {
+        p.lane_bytes = (int32_t)bf_stride(m);
+        need = std::max(need, ws_layout(n, m, tile_starts(p), false, BF_LEAD).need);
+    }
+    return need;
 }
 
 extern "C" uint64_t sm_workspace_size_upto(uint64_t n, uint64_t m_max, const sm_opts *opts)
@@ -487,7 +495,7 @@ static int run_async(const uint8_t *d_text, uint64_t n, const uint8_t *pat, uint
         HIP_TRY(launch_set_u64(d_count, 0, st));
         return SM_OK;
     }
-    const WsLayout w = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan));
+    const WsLayout w = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan), plan_lead(plan));
     const uint64_t need = write ? w.need : w.need_count;
     if (!d_work || work_bytes < need)
         return fail(SM_EINVAL, "workspace too small: need %llu bytes", (unsigned long long)need);
@@ -600,7 +608,7 @@ extern "C" int sm_find_all_noalloc(const uint8_t *d_text, uint64_t n, const uint
     Plan plan;
     if ((r = make_plan(pat, m, opts, 0, plan))) return r;
     if (n > 0 && m <= n) {
-        const uint64_t need = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan)).need;
+        const uint64_t need = ws_layout(n, m, tile_starts(plan), plan_keeps_bitmap(plan), plan_lead(plan)).need;
         if (need > (uint64_t)SM_NOALLOC_SCRATCH_BYTES)
             return fail(SM_EINVAL,
                         "sm_find_all_noalloc: n = %llu, m = %llu needs %llu bytes of workspace, more than "

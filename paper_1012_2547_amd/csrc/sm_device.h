@@ -773,49 +773,30 @@ __device__ __forceinline__ uint32_t lane_brute(const uint4 *lds, const uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Block filter (after SSEF, Fig. 1). With S = m - 15, an occurrence at i contains
-// the 16-byte block at x whenever i <= x <= i + m - 16, an interval of S starts; so
-// the blocks at x_b = b S + S - 1 meet every occurrence, and block b is the only
-// one to test for the starts it owns, [b S, b S + S): i = x_b - j for an alignment
-// j < S with p[j, j + 16) equal to the block. The text is read at one block per S
-// bytes; the pattern's alignments are bucketed by the block hash.
+// Block filter (after SSEF, Fig. 1). An occurrence at i contains the 16-byte block
+// at x whenever i <= x <= i + m - 16, an interval of m - 15 starts; so blocks
+// spaced S <= m - 15 apart meet every occurrence. With S a multiple of 16 they can
+// all sit on aligned 16-byte chunks of memory (one load each, never two chunks), at
+// x_b = b S + S - 1 - phi for the text's alignment phi; block b is the only one to
+// test for the starts it owns, (x_b - S, x_b]: i = x_b - j for an alignment
+// j <= x_b - ilo with p[j, j + 16) equal to the block. The text is read at one block
+// per S bytes; the pattern's alignments j < m - 15 are bucketed by the block hash.
 // ---------------------------------------------------------------------------
-// The 16 bytes at p, any alignment, from the one or two aligned 16-byte chunks
-// that hold them (both lie inside the buffer when the 16 bytes do).
-__device__ __forceinline__ uint4 load16_chunks(const uint8_t *p)
-{
-    const uintptr_t a = (uintptr_t)p;
-    const uint4 *c = reinterpret_cast<const uint4 *>(a & ~(uintptr_t)15);
-    const uint32_t r = (uint32_t)(a & 15);
-    const uint4 c0 = c[0];
-    const uint4 c1 = r ? c[1] : uint4{0u, 0u, 0u, 0u};
-    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    const uint32_t q = r >> 2, sh = r & 3;
-    uint32_t v[5];
-#pragma unroll
-    for (int k = 0; k < 5; k++)
-        v[k] = q == 0 ? w[k] : (q == 1 ? w[k + 1] : (q == 2 ? w[k + 2] : w[k + 3]));
-    uint4 o;
-    o.x = alignbyte(v[1], v[0], sh);
-    o.y = alignbyte(v[2], v[1], sh);
-    o.z = alignbyte(v[3], v[2], sh);
-    o.w = alignbyte(v[4], v[3], sh);
-    return o;
-}
-
-// Occurrences among the starts [ilo, ihi] of sampled block x (ihi <= x, x - ilo < S,
-// x + 16 <= n); blk = the block's 16 bytes. Wave-cooperative: all 64 lanes of the
-// wave call it (lanes without starts pass active = false). A lane walks its
-// bucket in descending j, i.e. ascending start i = x - j, and keeps the candidates
+// Occurrences among the starts [ilo, ihi] of sampled block x (ilo <= ihi <= x,
+// x - ilo < S <= m - 15, x + 16 <= n); blk = the block's 16 bytes. Wave-cooperative:
+// all 64 lanes of the wave call it (lanes without starts pass active = false). A lane
+// walks its bucket in descending j, i.e. ascending start i = x - j, skips the
+// alignments whose start lies before ilo (another block's), and keeps the candidates
 // whose p[j, j + 16) equals the block; the wave verifies them 1024 bytes per round
 // trip. An occurrence v already found rules out starts closer than the pattern's
 // smallest period, and one exactly a period away needs only its last period bytes.
 template <bool WRITE, class E>
 __device__ __forceinline__ uint32_t lane_block(const uint8_t *text, const uint8_t *pat, uint32_t m,
                                                const Params *prm, uint32_t period, uint32_t period_lb,
-                                               uint64_t x, uint64_t ihi, uint4 blk, bool active,
-                                               uint64_t base, E &o)
+                                               uint64_t x, uint64_t ilo, uint64_t ihi, uint4 blk,
+                                               bool active, uint64_t base, E &o)
 {
+    const uint32_t jmax = active ? (uint32_t)(x - ilo) : 0u;  // start x - j >= ilo
     uint32_t k = 0, k1 = 0;
     if (active) {
         const uint32_t h = bf_hash(blk.x, blk.y, blk.z, blk.w);
@@ -832,7 +813,11 @@ __device__ __forceinline__ uint32_t lane_block(const uint8_t *text, const uint8_
         uint64_t i = 0;
         while (active && !cand) {
             const uint32_t j = prm->bf_js[k++];
-            i = x - j;  // >= ilo since j < S
+            if (j > jmax) {  // the start is owned by an earlier block
+                if (k >= k1) active = false;
+                continue;
+            }
+            i = x - j;
             if (i > ihi) {
                 active = false;  // j descending: the remaining starts are larger still
                 break;
@@ -959,7 +944,8 @@ __device__ __forceinline__ uint32_t lane_hashq(const uint32_t *lds32, const uint
 // LDS the block filter's table build takes (32-bit words)
 constexpr int BF_BUILD_LDS = 2 * BF_MAX_M + 64;
 
-// Block filter tables: the hash of every alignment j < S = m - 15, counts per
+// Block filter tables: the hash of every alignment j < S = m - 15 (every block a
+// sampled block can meet), counts per
 // bucket, their exclusive scan (bf_start); then each j goes to its bucket in any
 // order (LDS atomics) and every bucket is sorted in descending j: buckets of at
 // most 32 by one thread each (insertion sort), larger ones (periodic or

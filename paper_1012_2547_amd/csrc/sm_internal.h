@@ -18,7 +18,7 @@ enum Algo : int32_t {
                          // form: the pattern's last 64 bytes scanned, the rest verified
     ALGO_HASHQ = 4,      // hashed q-gram skip filter + verification, any m >= q (Fig. 1, HASHq)
     ALGO_BLOCK = 5,      // 16-byte block fingerprint filter, BF_MIN_M <= m <= BF_MAX_M (after
-                         // SSEF, Fig. 1): reads one block per m - 15 text bytes
+                         // SSEF, Fig. 1): reads one aligned block per bf_stride(m) text bytes
     ALGO_BRUTE = 6,      // brute force over packed bytes, m <= BRUTE_MAX_M (Fig. 1, BF)
     ALGO_FSBNDM = 7,     // SBNDM with the character after the window read first, m <= 63 (Fig. 3, FSBNDM)
     ALGO_COUNT_ = 8
@@ -39,6 +39,11 @@ constexpr int BF_H = 12;             // block filter: bucket bits of the block h
 constexpr int BF_MIN_M = 144;        // block filter pattern lengths (a tile of 256 blocks then
                                      // holds more starts than one of the widest lanes, 128)
 constexpr int BF_MAX_M = 4096;
+// Block filter stride: starts owned per sampled block, a multiple of 16 so that every
+// sampled block is one aligned 16-byte chunk. The block of start 0 lies up to 15
+// bytes early (BF_LEAD), which may take one more tile.
+inline uint64_t bf_stride(uint64_t m) { return 16 * ((m - 15) / 16); }
+constexpr uint64_t BF_LEAD = 15;
 
 constexpr uint32_t STASH_K = 256;  // hits per tile kept as u16 offsets by the count pass
 constexpr uint32_t EMIT_GRID = 4096;  // workgroups of the emit kernel (grid-stride over tiles)
@@ -70,7 +75,7 @@ static_assert(sizeof(Params) % 16 == 0, "Params must keep the pattern 16-byte al
 struct Plan {
     int32_t algo;
     int32_t lane_bytes;   // L: candidate starts per lane; tile = BLOCK * L starts (block
-                          // filter: m - 15, the starts of one sampled block)
+                          // filter: bf_stride(m), the starts of one sampled block)
     int32_t q;            // Hash-q gram length
     int32_t hbits;        // Hash-q table bits
     int32_t tiles_per_wg; // consecutive tiles per workgroup (count kernel)
@@ -109,10 +114,11 @@ inline uint64_t num_tiles(uint64_t n, uint64_t m, uint64_t tile)
 
 inline uint64_t num_super(uint64_t ntiles) { return (ntiles + (1ull << SUPER_SHIFT) - 1) >> SUPER_SHIFT; }
 
-inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile, bool bitmap)
+// lead: starts before start 0 that the first tile may cover (the block filter's BF_LEAD)
+inline WsLayout ws_layout(uint64_t n, uint64_t m, uint64_t tile, bool bitmap, uint64_t lead = 0)
 {
     WsLayout w;
-    w.ntiles = num_tiles(n, m, tile);
+    w.ntiles = (m == 0 || m > n) ? 0 : num_tiles(n + lead, m, tile);
     uint64_t o = 0;
     w.params = o;
     o = align_up(o + sizeof(Params), 256);

@@ -55,7 +55,7 @@ struct ScanArgs {
     const uint8_t *pat;
     uint32_t m, q, hbits, tiles_per_wg;
     uint32_t slots;       // find: lanes keep their first hits while counting
-    uint32_t bs;          // block filter: starts per sampled block (m - 15)
+    uint32_t bs;          // block filter: starts per sampled block (bf_stride(m))
     uint64_t ntiles;
     uint64_t *total;      // count mode: occurrences are added here
     uint32_t *tile_cnt;   // per-tile counts (count kernel writes, tile scan and emit read)
@@ -623,8 +623,10 @@ __global__ __launch_bounds__(BLOCK) void emit_kernel(ScanArgs a)
 
 // ---------------------------------------------------------------------------
 // Block filter kernels. A tile is 256 sampled blocks, one per lane: lane l of
-// tile t tests block b = 256 t + l at x = b S + S - 1 for the starts [b S, b S + S).
-// Only the sampled blocks are read from the text (plus the bytes of candidates).
+// tile t tests block b = 256 t + l at x = b S + S - 1 - phi for the starts
+// [b S - phi, b S + S - phi) (from 0 on), where S is a multiple of 16 and phi in
+// [0, 15] puts every sampled block on an aligned 16-byte chunk of memory. Only the
+// sampled blocks are read from the text (plus the bytes of candidates).
 // ---------------------------------------------------------------------------
 struct BlockLane {
     uint64_t x, ilo, ihi;  // the block, and the starts it owns (ilo > ihi: none)
@@ -634,11 +636,18 @@ __device__ __forceinline__ BlockLane block_lane(const ScanArgs &a, uint64_t t)
 {
     BlockLane L;
     const uint64_t S = a.bs, b = t * BLOCK + threadIdx.x;
-    L.ilo = b * S;
-    L.x = L.ilo + S - 1;
+    const uint64_t phi = ((uint64_t)(uintptr_t)a.text + 15) & 15;  // text + x is 16-byte aligned
+    L.x = b * S + S - 1 - phi;  // >= 0: S >= 16
+    L.ilo = b * S >= phi ? b * S - phi : 0;
     const uint64_t last = a.n - a.m;  // n >= m
     L.ihi = L.x < last ? L.x : last;
     return L;
+}
+
+// the sampled block: one aligned chunk
+__device__ __forceinline__ uint4 block_load(const ScanArgs &a, const BlockLane &L)
+{
+    return L.ilo <= L.ihi ? *reinterpret_cast<const uint4 *>(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
 }
 
 // Count pass (count and find modes alike: the emit pass tests the tiles with hits
@@ -654,21 +663,21 @@ __global__ __launch_bounds__(BLOCK) void block_count_kernel(ScanArgs a)
     const uint32_t period = a.prm->period, period_lb = a.prm->period_lb;
     uint64_t sup_i = ~0ull, sup_v = 0;
     BlockLane L = block_lane(a, t_begin);
-    uint4 blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+    uint4 blk = block_load(a, L);
     for (uint64_t t = t_begin; t < t_end; t++) {
         if (!PREFETCH && t != t_begin) {
             L = block_lane(a, t);
-            blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+            blk = block_load(a, L);
         }
         const BlockLane cur = L;
         const uint4 cb = blk;
         if (PREFETCH && t + 1 < t_end) {
             L = block_lane(a, t + 1);
-            blk = L.ilo <= L.ihi ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+            blk = block_load(a, L);
         }
         NoEmit ne;
         const uint32_t c = lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, cur.x,
-                                             cur.ihi, cb, cur.ilo <= cur.ihi, 0, ne);
+                                             cur.ilo, cur.ihi, cb, cur.ilo <= cur.ihi, 0, ne);
         uint32_t tot;
         block_excl_scan(c, s_w, tot);
         if (threadIdx.x == 0) {
@@ -692,10 +701,10 @@ __global__ __launch_bounds__(BLOCK) void block_emit_kernel(ScanArgs a)
         if (te.off >= a.lo + a.cap || te.off + te.cnt <= a.lo) continue;  // outside the window
         const BlockLane L = block_lane(a, te.t);
         const bool any = L.ilo <= L.ihi;
-        const uint4 blk = any ? load16_chunks(a.text + L.x) : uint4{0u, 0u, 0u, 0u};
+        const uint4 blk = block_load(a, L);
         NoEmit ne;
-        const uint32_t c = lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ihi,
-                                             blk, any, 0, ne);
+        const uint32_t c = lane_block<false>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ilo,
+                                             L.ihi, blk, any, 0, ne);
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, s_w, tot);
         PosEmit pe;
@@ -704,7 +713,7 @@ __global__ __launch_bounds__(BLOCK) void block_emit_kernel(ScanArgs a)
         pe.lo = a.lo;
         pe.span = a.cap;
         pe.base = te.t * T;
-        lane_block<true>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ihi, blk, c != 0,
+        lane_block<true>(a.text, a.pat, a.m, a.prm, period, period_lb, L.x, L.ilo, L.ihi, blk, c != 0,
                          te.t * T, pe);
     }
 }

@@ -126,7 +126,7 @@ def test_planner_choices(L):
     assert p2["q"] < p["q"]
     # long patterns: the block filter, one block per m - 15 starts; not on one symbol
     b = sm.plan_query(bytes(range(4)) * 64)
-    assert b["algo"] == "block" and b["lane_bytes"] == 256 - 15
+    assert b["algo"] == "block" and b["lane_bytes"] == 240  # 16-byte multiple <= m - 15
     assert sm.plan_query(b"a" * 300)["algo"] != "block"
     assert sm.plan_query(bytes(range(4)) * 25)["algo"] != "block"  # m = 100 < 144
     f = sm.plan_query(b"x" * 30, sm.opts(algo=sm.ALGO_BNDM, lane_bytes=32))

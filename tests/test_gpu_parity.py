@@ -204,9 +204,11 @@ def test_bndm_q_and_fsbndm(sm):
 
 
 def test_block_filter(sm):
-    """The block filter reads one 16-byte block per m - 15 text bytes: every length
-    from its smallest (144: a block per 129 starts) to its largest (4096), pattern
-    lengths around block boundaries, small and large alphabets, planted
+    """The block filter reads one aligned 16-byte block per S text bytes (S the largest
+    multiple of 16 <= m - 15): every length from its smallest (144: a block per 128
+    starts) to its largest (4096), lengths where S = m - 15 and where S = m - 30 (a
+    block's bucket then holds alignments of the previous block's starts), every text
+    alignment (the sampled blocks move with it), small and large alphabets, planted
     occurrences at both text ends, periodic patterns (the period rule), patterns
     whose blocks recur in the text without an occurrence, tiles per workgroup, and
     truncation. Out-of-range lengths are rejected."""
@@ -215,7 +217,7 @@ def test_block_filter(sm):
         n = 300_001
         t_np = dg.uniform_text(n, sigma, seed=40 + sigma)
         t_dev = torch.from_numpy(t_np).to(DEV)
-        for i, m in enumerate((144, 145, 159, 160, 200, 255, 256, 257, 1000, 1024, 4096)):
+        for i, m in enumerate((144, 145, 159, 160, 174, 175, 200, 255, 256, 257, 1000, 1024, 4096)):
             pats = [dg.substring_pattern(t_np, m, seed=41, idx=i)[0], bytes(t_np[:m]),
                     bytes(t_np[n - m:]), bytes(rng.integers(0, sigma, m, dtype=np.uint8))]
             for p in pats:
@@ -223,6 +225,17 @@ def test_block_filter(sm):
                 for tpw in (1, 2, 3):
                     got, tot = gpu_find(sm, t_dev, p, algo=5, tpw=tpw)
                     assert tot == want.size and np.array_equal(got, want), (sigma, m, tpw)
+    # every alignment of the text in memory: the blocks sampled differ with it
+    base_np = dg.uniform_text(200_000 + 16, 4, seed=47)
+    base = torch.from_numpy(base_np).to(DEV)
+    for off in range(16):
+        t_np = base_np[off:off + 200_000]
+        t_dev = base[off:off + 200_000]
+        for m in (144, 174, 175, 600):
+            for p in (bytes(t_np[:m]), bytes(t_np[-m:]), bytes(t_np[777:777 + m])):
+                want = oracle.find_all(t_np, p)
+                got, tot = gpu_find(sm, t_dev, p, algo=5, tpw=1 + off % 3)
+                assert tot == want.size and np.array_equal(got, want), (off, m)
     # periodic texts and patterns: many candidates per block, dense occurrences
     for per in (1, 2, 3, 7, 16, 17, 40, 64, 65):
         base = bytes(rng.integers(0, 4, per, dtype=np.uint8))
