@@ -25,7 +25,7 @@ import time
 
 SIGMAS = (2, 4, 16, 64, 256)
 SIGMA_RANGES = {2: (1, 2), 4: (3, 7), 16: (8, 31), 64: (32, 127), 256: (128, 256)}
-M_GRID = (1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 32, 48, 64, 65, 96, 128, 192, 256, 384, 512, 768, 1024)
+M_GRID = (1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 32, 48, 64, 65, 96, 128, 144, 192, 256, 384, 512, 768, 1024)
 QS = (2, 3, 4, 5, 6, 8, 10, 12, 16)
 
 
