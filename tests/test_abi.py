@@ -213,10 +213,10 @@ def test_tuning_table_roundtrip(L):
 
 def test_sigma_estimate_from_pattern_steers_plan(L):
     import paper_1012_2547_amd as sm
-    # a 200-byte pattern over 2 symbols plans long q-grams; over 200 symbols the table
+    # a 150-byte pattern over 2 symbols plans long q-grams; over 150 symbols the table
     # entry of the largest alphabet bucket applies instead
-    lo = sm.plan_query(bytes([0, 1]) * 100)
-    hi = sm.plan_query(bytes(range(200)))
+    lo = sm.plan_query(bytes([0, 1]) * 75)
+    hi = sm.plan_query(bytes(range(150)))
     assert lo["algo"] == "hashq" and lo["q"] >= 8
     assert (hi["algo"], hi["q"]) != (lo["algo"], lo["q"])
-    assert sm.plan_query(bytes(range(200)), sm.opts(sigma_hint=2)) == lo
+    assert sm.plan_query(bytes(range(150)), sm.opts(sigma_hint=2)) == lo
