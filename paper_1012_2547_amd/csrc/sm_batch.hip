@@ -263,8 +263,19 @@ struct MqArgs {
 static_assert(256 * BT <= (1 << MQ_REL_BITS), "a chunk's relative starts fit MQ_REL_BITS");
 static_assert(MQ_G <= (1 << (32 - MQ_REL_BITS)), "counter ids fit above the relative start");
 
+// The filter's count pass scans each tile in MQ_SUB sub-tiles of MQ_BT starts: it reads
+// at most 20 bytes past a start from LDS (the q-gram key, then bytes [q, q + 8) of a
+// candidate; longer patterns are checked from global memory), so a sub-tile stages
+// MQ_BT + 32 bytes, and the smaller LDS tile lets three workgroups share a CU (two
+// with whole tiles).
+constexpr int MQ_SUB = 2;
+constexpr int MQ_BT = BT / MQ_SUB, MQ_BL = BL / MQ_SUB;
+constexpr int MQ_STAGE = MQ_BT + 32;
+constexpr int MQ_CHUNKS = (((MQ_STAGE + 15) / 16 + 1) + 7) & ~7;
+constexpr int MQ_PER = (MQ_CHUNKS + BLOCK - 1) / BLOCK;
+
 struct MqShared {
-    uint4 text[B_CHUNKS];
+    uint4 text[MQ_CHUNKS];
     uint4 tab[MQ_LDS_BYTES / 16];
     uint32_t acc[MQ_G];
     uint32_t nst;  // hits of the item so far (the stash keeps the first MQ_STASH)
@@ -393,32 +404,34 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
     const uint32_t mlo = byte_mask(q < 4 ? (int)q : 4), mhi = byte_mask(q > 4 ? (int)q - 4 : 0);
     const uint64_t sitem = chunk * a.nmq + a.group_base + item % a.ngroups;
     uint32_t *stash = a.stash ? a.stash + sitem * MQ_STASH : nullptr;
-    const uint64_t t0 = chunk * a.chunk_tiles;
-    uint64_t t1 = t0 + a.chunk_tiles;
-    if (t1 > a.ntiles) t1 = a.ntiles;
-    // tiles with a start of some pattern of the group: s + min_m <= n
-    const uint64_t tl = a.n >= g.min_m ? (a.n - g.min_m) / BT + 1 : 0;
+    // the chunk's sub-tiles (MQ_BT starts each); its first start is c0
+    const uint64_t c0 = chunk * a.chunk_tiles * (uint64_t)BT;
+    const uint64_t t0 = chunk * a.chunk_tiles * MQ_SUB;
+    uint64_t t1 = t0 + a.chunk_tiles * MQ_SUB;
+    if (t1 > a.ntiles * MQ_SUB) t1 = a.ntiles * MQ_SUB;
+    // sub-tiles with a start of some pattern of the group: s + min_m <= n
+    const uint64_t tl = a.n >= g.min_m ? (a.n - g.min_m) / MQ_BT + 1 : 0;
     if (t1 > tl) t1 = tl;
-    Staged<B_PER> st;
+    Staged<MQ_PER> st;
     if (t0 < t1) {
-        uint64_t x1 = t0 * (uint64_t)BT + (uint64_t)BT + g.max_m - 1;
-        stage_issue(st, a.text, t0 * (uint64_t)BT, x1 < a.n ? x1 : a.n);
+        const uint64_t x1 = t0 * (uint64_t)MQ_BT + MQ_STAGE;
+        stage_issue(st, a.text, t0 * (uint64_t)MQ_BT, x1 < a.n ? x1 : a.n);
     }
     for (uint64_t t = t0; t < t1; t++) {
-        const uint64_t s = t * (uint64_t)BT;
-        __syncthreads();  // previous tile's readers are done; tables visible
+        const uint64_t s = t * (uint64_t)MQ_BT;
+        __syncthreads();  // previous sub-tile's readers are done; tables visible
         stage_commit<true>(st, S.text);
         const int boff = st.boff;
         __syncthreads();
-        if (t + 1 < t1) {  // next tile's loads fly while this one is scanned
-            const uint64_t s2 = s + (uint64_t)BT;
-            const uint64_t x1 = s2 + (uint64_t)BT + g.max_m - 1;
+        if (t + 1 < t1) {  // next sub-tile's loads fly while this one is scanned
+            const uint64_t s2 = s + (uint64_t)MQ_BT;
+            const uint64_t x1 = s2 + MQ_STAGE;
             stage_issue(st, a.text, s2, x1 < a.n ? x1 : a.n);
         }
         const uint64_t lim = a.n - g.min_m - s;  // largest relative start of the group
-        const int hi_rel = lim >= (uint64_t)(BT - 1) ? BT - 1 : (int)lim;
-        const int lo = tid * BL;
-        const int hi = (lo + BL - 1) < hi_rel ? (lo + BL - 1) : hi_rel;
+        const int hi_rel = lim >= (uint64_t)(MQ_BT - 1) ? MQ_BT - 1 : (int)lim;
+        const int lo = tid * MQ_BL;
+        const int hi = (lo + MQ_BL - 1) < hi_rel ? (lo + MQ_BL - 1) : hi_rel;
         if (lo > hi) continue;
         const int u0 = (boff + lo) >> 4, u1 = (boff + hi) >> 4;
         uint4 nx = S.text[swz((uint32_t)u0)];
@@ -460,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                 }
                 if (stash && hm) {
                     uint32_t at = mq_stash_take(S, (uint32_t)__builtin_popcount(hm));
-                    const uint32_t rel0 = (uint32_t)(s - t0 * (uint64_t)BT) + (uint32_t)r0;
+                    const uint32_t rel0 = (uint32_t)(s - c0) + (uint32_t)r0;
 #pragma unroll
                     for (int b = 0; b < 16; b++)
                         if ((hm >> b) & 1u) {
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(BLOCK) void mq_count_kernel(MqArgs a)
                 const uint32_t x = (uint32_t)(16 * u + b);
                 uint32_t klo, khi, h;
                 mq_key_at<EXACT>(S.text, x, mlo, mhi, klo, khi, h);
-                const uint32_t rel = (uint32_t)(s - t0 * (uint64_t)BT) + (uint32_t)r;
+                const uint32_t rel = (uint32_t)(s - c0) + (uint32_t)r;
                 auto rec = [&](uint32_t ctr) {
                     if (atomicAdd(&S.acc[ctr], 1u) < MQ_CAP && stash) {
                         const uint32_t at = mq_stash_take(S, 1u);
