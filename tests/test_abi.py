@@ -114,6 +114,40 @@ def test_invalid_options(L):
         sm.plan_query(b"abc", sm.opts(algo=9))
     with pytest.raises(sm.SmError):
         sm.plan_query(b"a" * 100, sm.opts(algo=sm.ALGO_HASHQ, hbits=20))
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"a" * 64, sm.opts(algo=sm.ALGO_FSBNDM))      # FSBNDM needs m <= 63
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"a" * 30, sm.opts(algo=sm.ALGO_BNDM, q=8))   # BNDMq: q in {1, 2, 4}
+    with pytest.raises(sm.SmError):
+        sm.plan_query(b"a" * 143, sm.opts(algo=sm.ALGO_BLOCK))      # block filter: 144 <= m
+
+
+def test_long_pattern_scanner_plans(L):
+    """SBNDM takes any m (its factor form beyond 64 bytes), with every q; FSBNDM up to 63;
+    BNDM up to 64 with q = 2 or 4."""
+    import paper_1012_2547_amd as sm
+    for m in (65, 100, 1000, 5000):
+        for q in (0, 2, 4, 8):
+            p = sm.plan_query(bytes(range(4)) * (m // 4) + bytes(m % 4), sm.opts(algo=sm.ALGO_SBNDM, q=q))
+            assert p["algo"] == "sbndm" and (p["q"] == q if q > 1 else p["q"] in (0, 2, 4, 8)), (m, q)
+    assert sm.plan_query(b"x" * 63, sm.opts(algo=sm.ALGO_FSBNDM))["algo"] == "fsbndm"
+    for q in (2, 4):
+        assert sm.plan_query(b"x" * 64, sm.opts(algo=sm.ALGO_BNDM, q=q))["q"] == q
+
+
+def test_block_filter_workspace(L):
+    """The block filter's tiles of 256 sampled blocks (a 16-byte multiple of starts each)
+    may begin up to 15 starts before the text: the planner's workspace (auto) covers the
+    forced block filter's at every length of its range, and both grow with n."""
+    import paper_1012_2547_amd as sm
+    blk = sm.opts(algo=sm.ALGO_BLOCK)
+    for n in (144, 145, 4096, 32768 + 15, 1 << 20, (1 << 20) + 7):
+        for m in (144, 145, 159, 160, 175, 176, 1000, 4096):
+            if m > n:
+                continue
+            fb = sm.workspace_size(n, m, blk)
+            assert fb > 0 and sm.workspace_size(n, m) >= fb, (n, m)
+            assert sm.workspace_size(n + (1 << 20), m, blk) >= fb, (n, m)
 
 
 def test_planner_choices(L):
