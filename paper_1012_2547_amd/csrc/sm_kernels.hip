@@ -912,6 +912,20 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, co
     __shared__ uint32_t s_b[16];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t c0 = (uint64_t)blockIdx.x * SCAN_CHUNK;
+    // this chunk's counts, SCAN_CHUNK / 1024 consecutive ones per thread, loaded first so
+    // that they are in flight with the super-chunk totals below
+    constexpr int PER = (int)(SCAN_CHUNK / 1024);
+    static_assert(PER % 4 == 0, "whole 16-byte loads");
+    const uint64_t i = c0 + PER * (uint64_t)tid;
+    uint32_t c[PER];
+#pragma unroll
+    for (int k = 0; k < PER / 4; k++) {
+        const uint4 v = load_cnt4(cnt, i + 4 * k, nt);
+        c[4 * k] = v.x;
+        c[4 * k + 1] = v.y;
+        c[4 * k + 2] = v.z;
+        c[4 * k + 3] = v.w;
+    }
     // 1. occurrences and listed tiles before this chunk, from the super-chunk totals
     static_assert(SCAN_CHUNK % (1ull << SUPER_SHIFT) == 0, "chunks of whole super-chunks");
     uint64_t pre = 0;
@@ -931,19 +945,7 @@ __global__ __launch_bounds__(1024) void tile_scan_kernel(const uint32_t *cnt, co
         }
     }
     block_sum2_1024(pre, pnz, s_a, s_b);
-    // 2. this chunk: SCAN_CHUNK / 1024 consecutive counts per thread
-    constexpr int PER = (int)(SCAN_CHUNK / 1024);
-    static_assert(PER % 4 == 0, "whole 16-byte loads");
-    const uint64_t i = c0 + PER * (uint64_t)tid;
-    uint32_t c[PER];
-#pragma unroll
-    for (int k = 0; k < PER / 4; k++) {
-        const uint4 v = load_cnt4(cnt, i + 4 * k, nt);
-        c[4 * k] = v.x;
-        c[4 * k + 1] = v.y;
-        c[4 * k + 2] = v.z;
-        c[4 * k + 3] = v.w;
-    }
+    // 2. this chunk's scan
     uint64_t my = 0;
     uint32_t mz = 0;
 #pragma unroll
