@@ -10,7 +10,9 @@ substring patterns), with the tile-count scan spread over many workgroups (more 
 are checked on the same patterns. The oracle is the naive definition on 16 host
 threads; the lists must be equal, so any slip in 64-bit position arithmetic shows.
 A second test covers every scanner and lane width on a 64 MiB text (more than 4096
-tiles of 4096 starts), with truncation inside the list.
+tiles of 4096 starts), with truncation inside the list; a third takes the serving
+workload's largest corpus size, 2^33 + 4099 bytes, through the single-pattern, batched and
+served forms.
 """
 import os
 
@@ -151,6 +153,55 @@ def test_served_past_2_32(sm, big):
         assert np.array_equal(srv.result(tk), want[p]), len(p)
     srv.close()
     c.close()
+
+
+N_HUGE = (1 << 33) + 4099
+B33 = 1 << 33
+
+
+def test_positions_past_2_33(sm):
+    """The serving workload's largest corpus (sigma 4, 8 GiB): a text of 2^33 + 4099 bytes
+    with zero runs across 2^33 and at its end. The planner's scanners, a forced dense
+    Shift-And (hit bitmaps), the batched form and a served query, each against the oracle
+    element by element."""
+    print("fullsize: generating n = 2^33 + 4099 (sigma 4, seed 65)", flush=True)
+    t_np = dg.uniform_text(N_HUGE, 4, seed=65)
+    for a in (B33 - RUN // 2, N_HUGE - RUN):
+        t_np[a:a + RUN] = 0
+    pats = [bytes(9), bytes(t_np[B33 + 1000:B33 + 1064]), bytes(t_np[(3 << 31) + 17:(3 << 31) + 217]),
+            dg.substring_pattern(t_np, 16, seed=66, idx=0)[0], bytes(t_np[N_HUGE - 700:N_HUGE - 600])]
+    want = {}
+    for p in pats:
+        want[p] = oracle.find_all(t_np, p, threads=THREADS)
+        print("fullsize: oracle m=%d: %d occurrences" % (len(p), want[p].size), flush=True)
+    z = want[bytes(9)]
+    for x in (B33 - 1, B33, N_HUGE - 9):
+        k = int(np.searchsorted(z, x))
+        assert k < z.size and z[k] == x, x
+    t_dev = torch.from_numpy(t_np).to(DEV)
+    try:
+        for p in pats:
+            print("fullsize 2^33: planner's scanner, m=%d" % len(p), flush=True)
+            got, tot = gpu_find(sm, t_dev, p)
+            assert tot == want[p].size and np.array_equal(got, want[p]), len(p)
+        print("fullsize 2^33: forced Shift-And, 128-start lanes", flush=True)
+        got, tot = gpu_find(sm, t_dev, bytes(9), algo=SA, lane=128)
+        assert tot == z.size and np.array_equal(got, z)
+        print("fullsize 2^33: batched and served", flush=True)
+        c = sm.Corpus(t_dev)
+        pos, off = c.batch_find_all(pats)
+        for i, p in enumerate(pats):
+            assert np.array_equal(pos[off[i]:off[i + 1]], want[p]), ("batched", i)
+        srv = sm.Server(pool_bytes=64 << 20, host_bytes=256 << 20, max_batch=4)
+        cid = srv.add_corpus(c)
+        tickets = [(p, srv.submit(cid, p)) for p in pats]
+        for p, tk in tickets:
+            assert np.array_equal(srv.result(tk), want[p]), ("served", len(p))
+        srv.close()
+        c.close()
+    finally:
+        del t_dev
+        torch.cuda.empty_cache()
 
 
 def test_many_tiles_every_scanner(sm):
