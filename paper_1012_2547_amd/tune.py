@@ -74,6 +74,16 @@ def candidates(m: int, sigma: int):
     return out
 
 
+def write_json(f, d):
+    """The tuner's record, one table entry and one cell (with every candidate's timing)
+    per line."""
+    f.write('{"n": %d, "device": %s,\n"entries": [\n' % (d["n"], json.dumps(d["device"])))
+    f.write(",\n".join(json.dumps(e) for e in d["entries"]))
+    f.write('\n],\n"cells": [\n')
+    f.write(",\n".join(json.dumps(c) for c in d["cells"]))
+    f.write("\n]}\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="tune_out")
@@ -169,8 +179,8 @@ def main():
                             lane_bytes=b["lane_bytes"], q=b["q"], tiles_per_wg=b["tiles_per_wg"],
                             hbits=0, gbs=b["gbs"]))
     with open(os.path.join(args.out, "tune.json"), "w") as f:
-        json.dump({"n": n, "device": torch.cuda.get_device_name(0), "entries": entries,
-                   "cells": results}, f, indent=1)
+        write_json(f, {"n": n, "device": torch.cuda.get_device_name(0), "entries": entries,
+                       "cells": results})
     with open(os.path.join(args.out, "tune_table.inc"), "w") as f:
         f.write("// generated by paper_1012_2547_amd/tune.py on %s, n = 2^%d, tuning seed 2\n"
                 % (torch.cuda.get_device_name(0), args.n_log2))
