@@ -654,3 +654,29 @@ def test_corpus_async_paths(sm):
             assert int(dc.item()) == want.size
             assert np.array_equal(out[:want.size].cpu().numpy(), want), m
         c.close()
+
+
+def test_every_tuning_table_entry(sm):
+    """Every entry of the shipped planner table, at both ends of its pattern-length range
+    (up to 1100 bytes) and an alphabet size inside its range, planned by the planner itself
+    (alphabet hint, no forced option): the configurations the benchmark and the batched and
+    served paths run, against the oracle."""
+    n = 200_003
+    texts = {}
+    checked = set()
+    for e in sm.tune_get():
+        sigma = min(e["sigma_hi"], 256)  # 2, 7, 31, 127, 256: inside each bucket
+        if sigma not in texts:
+            t_np = dg.uniform_text(n, sigma, seed=71 + sigma)
+            texts[sigma] = (t_np, torch.from_numpy(t_np).to(DEV))
+        t_np, t_dev = texts[sigma]
+        for m in {e["m_lo"], min(e["m_hi"], 1100)}:
+            if (sigma, m) in checked:
+                continue
+            checked.add((sigma, m))
+            plan = sm.plan_query(bytes(m), sm.opts(sigma_hint=sigma))
+            p = dg.substring_pattern(t_np, m, seed=72, idx=m)[0]
+            want = oracle.find_all(t_np, p)
+            got, tot = gpu_find(sm, t_dev, p, sigma_hint=sigma)
+            assert tot == want.size and np.array_equal(got, want), (sigma, m, plan)
+    assert len(checked) > 150
