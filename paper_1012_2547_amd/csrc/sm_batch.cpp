@@ -11,6 +11,8 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <string_view>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/sm.h"
@@ -685,15 +687,38 @@ int sm::batch_write_enqueue(BatchJob &j, uint8_t *ws, const uint64_t *d_csr, con
     }
     if ((!j.longp.empty() || !j.singlep.empty()) && !h_csr)
         return err(SM_EINVAL, "single-pattern searches need the host offsets");
-    // one search each, into the window's part of its slice
+    // one search each, into the window's part of its slice. Identical patterns have
+    // identical position lists (short patterns over a small alphabet necessarily repeat
+    // in a large batch): a pattern whose ranks in this window were already written for an
+    // identical one is copied from there, device to device, instead of searched again.
+    std::unordered_map<std::string_view, uint32_t> written;  // pattern bytes -> written index
     for (const auto *list : {&j.longp, &j.singlep}) {
         for (uint32_t i : *list) {
             const uint64_t a = std::max(h_csr[i], lo), b = std::min(h_csr[i + 1], hi);
             if (a >= b) continue;
             const uint64_t m = j.pat_off[i + 1] - j.pat_off[i];
+            const std::string_view key(reinterpret_cast<const char *>(j.pats + j.pat_off[i]), (size_t)m);
+            const auto it = written.find(key);
+            if (it != written.end()) {
+                // rank a - h_csr[i] of this pattern is CSR entry src of the written one
+                const uint64_t src = h_csr[it->second] + (a - h_csr[i]);
+                if (src >= lo && src + (b - a) <= hi) {
+                    HIP_OK(hipMemcpyAsync(d_out + (a - lo), d_out + (src - lo), (b - a) * sizeof(int64_t),
+                                          hipMemcpyDeviceToDevice, st));
+                    continue;
+                }
+            }
             int r = corpus_find_window_async(j.c, j.pats + j.pat_off[i], m, d_out + (a - lo), a - h_csr[i], b - a,
                                              d_totals + i, ws + j.L.single, j.L.need - j.L.single, st);
             if (r) return r;
+            // keep as the source the identical pattern with the most ranks in the window
+            if (it == written.end()) {
+                written.emplace(key, i);
+            } else {
+                const uint32_t w = it->second;
+                const uint64_t wa = std::max(h_csr[w], lo), wb = std::min(h_csr[w + 1], hi);
+                if (b - a > wb - wa) it->second = i;
+            }
         }
     }
     return SM_OK;
