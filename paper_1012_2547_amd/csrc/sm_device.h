@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sm_internal.h"
 
 namespace sm {
@@ -228,56 +230,116 @@ struct is_no_emit<NoEmit> {
 // hit checks (requires m - 1 + CHECK <= bits of W). MT = mask table entry: W, or
 // a byte when m <= 8 (the masks' bits >= m are clear), so that the table index is
 // the text byte itself, with no scaling.
-template <typename W, int CHECK, bool WRITE, class E, typename MT = W>
-__device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const MT *mask, int m, int li0,
-                                                  int lo, int hi, E &o)
+//
+// The lane reads 16-byte units ub + k, k = 0..K, where ub holds its first start's
+// byte, r bytes into the unit, and nl is its number of starts; unit k ends the
+// windows at relative ends lo - r + 16k + [0, 16). Units whose 16 ends all lie in
+// the lane's range [lo + m - 1, lo + nl + m - 2] (k in [kf0, kf1]) take every hit;
+// only the units before and after them mask the ends of other lanes' starts
+// (SPLIT: with these bounds uniform; otherwise every unit is masked).
+template <typename W, int CHECK, bool WRITE, bool SPLIT, class E, typename MT>
+__device__ __forceinline__ uint32_t shift_and_units(const uint4 *lds, const MT *mask, int m, int li0, int lo,
+                                                   int ub, int r, int nl, E &o)
 {
-    const int e_lo = lo + m - 1, e_hi = hi + m - 1;  // relative ends owned by this lane
-    const int u0 = (lo + li0) >> 4, u1 = (e_hi + li0) >> 4;
+    const int e_lo = lo + m - 1, e_hi = lo + nl - 1 + m - 1;  // relative ends owned by this lane
+    const int K = (r + nl + m - 2) >> 4;
+    const int kf0 = (m - 1 + r + 15) >> 4, kf1 = (nl + m - 17 + r) >> 4;
     W D = ~(W)0;
     uint32_t cnt = 0;
-    for (int u = u0; u <= u1; u++) {
+    auto unit = [&](int k, auto interior) {
+        const int u = ub + k;
         const uint4 v = lds[swz((uint32_t)u)];
         const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int g = 0; g < 16 / CHECK; g++) {
+            if constexpr (CHECK == 16 && sizeof(W) == 4) {
+                // the 16 steps D = (D << 1) | B[c] at once: D << 16 | OR_b B[c_b] << (15 - b),
+                // the masks merged pairwise (one shift-or each)
+                // Each half's 8 lookups are merged before the next half's are issued, so
+                // that at most 8 masks are held at once.
+                W x[16];
 #pragma unroll
-            for (int b = 0; b < CHECK; b++) {
-                const int k = g * CHECK + b;
-                const uint32_t c = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                D = (D << 1) | (W)mask[c];
+                for (int h = 0; h < 16; h += 8) {
+#pragma unroll
+                    for (int b = h; b < h + 8; b++) x[b] = (W)mask[(wd[b >> 2] >> (8 * (b & 3))) & 0xFFu];
+#pragma unroll
+                    for (int w = 1; w < 8; w *= 2) {
+#pragma unroll
+                        for (int b = h; b < h + 8; b += 2 * w) {
+                            x[b] = (x[b] << w) | x[b + w];
+                            // kept as one shift-or each: without this the compiler distributes
+                            // the shifts (a shift per mask plus three-input ORs, 25 ops, not 15)
+                            asm("" : "+v"(x[b]));
+                        }
+                    }
+                    asm volatile("" : "+v"(x[h])::"memory");
+                }
+                x[0] = (x[0] << 8) | x[8];
+                asm("" : "+v"(x[0]));
+                D = (D << 16) | x[0];
+            } else {
+#pragma unroll
+                for (int b = 0; b < CHECK; b++) {
+                    const int k2 = g * CHECK + b;
+                    const uint32_t c = (wd[k2 >> 2] >> (8 * (k2 & 3))) & 0xFFu;
+                    D = (D << 1) | (W)mask[c];
+                }
             }
             // relative end of the last byte consumed
             const int e_last = 16 * u + g * CHECK + CHECK - 1 - li0;
-            int jlo = e_last - e_hi, jhi = e_last - e_lo;
-            jlo = jlo < 0 ? 0 : jlo;
-            jhi = jhi > CHECK - 1 ? CHECK - 1 : jhi;
-            if (jlo <= jhi) {
-                uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
-                hits &= ((2u << jhi) - 1u) & ~((1u << jlo) - 1u);
-                if (hits) {
-                    if constexpr (takes_masks<E>::value) {
-                        // reversed, bit i <-> end e_last - CHECK + 1 + i, i.e. start
-                        // lo + (e_last - CHECK + 1 - e_lo) + i
-                        o.put_mask(e_last - CHECK + 1 - e_lo, __builtin_bitreverse32(hits) >> (32 - CHECK));
-                        cnt += __builtin_popcount(hits);
-                    } else if (WRITE && o.saturated()) {
-                        o.add((uint32_t)__builtin_popcount(hits));
-                    } else if (WRITE) {
-                        // bit j <-> end e_last - j; ascending positions = descending j
-                        while (hits) {
-                            const int j = 31 - __builtin_clz(hits);
-                            hits &= ~(1u << j);
-                            o.put(e_last - j - m + 1);
-                        }
-                    } else {
-                        cnt += __builtin_popcount(hits);
+            uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
+            if constexpr (!decltype(interior)::value) {
+                int jlo = e_last - e_hi, jhi = e_last - e_lo;
+                jlo = jlo < 0 ? 0 : jlo;
+                jhi = jhi > CHECK - 1 ? CHECK - 1 : jhi;
+                hits = jlo <= jhi ? hits & ((2u << jhi) - 1u) & ~((1u << jlo) - 1u) : 0u;
+            }
+            if (hits) {
+                if constexpr (takes_masks<E>::value) {
+                    // reversed, bit i <-> end e_last - CHECK + 1 + i, i.e. start
+                    // lo + (e_last - CHECK + 1 - e_lo) + i
+                    o.put_mask(e_last - CHECK + 1 - e_lo, __builtin_bitreverse32(hits) >> (32 - CHECK));
+                    cnt += __builtin_popcount(hits);
+                } else if (WRITE && o.saturated()) {
+                    o.add((uint32_t)__builtin_popcount(hits));
+                } else if (WRITE) {
+                    // bit j <-> end e_last - j; ascending positions = descending j
+                    while (hits) {
+                        const int j = 31 - __builtin_clz(hits);
+                        hits &= ~(1u << j);
+                        o.put(e_last - j - m + 1);
                     }
+                } else {
+                    cnt += __builtin_popcount(hits);
                 }
             }
         }
+    };
+    using Edge = std::integral_constant<bool, false>;
+    using Inner = std::integral_constant<bool, true>;
+    int k = 0;
+    if constexpr (SPLIT) {
+        for (; k < kf0; k++) unit(k, Edge{});
+        for (; k <= kf1; k++) unit(k, Inner{});
     }
+    for (; k <= K; k++) unit(k, Edge{});
     return cnt;
+}
+
+// LN > 0 with full: a lane of LN starts at a multiple of 16 (a whole tile of the count
+// pass), so r, K, kf0 and kf1 are the same in every lane and the loops are uniform.
+template <typename W, int CHECK, bool WRITE, int LN = 0, class E, typename MT = W>
+__device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const MT *mask, int m, int li0,
+                                                  int lo, int hi, E &o, bool full = false)
+{
+    if constexpr (LN > 0) {
+        static_assert(LN % 16 == 0, "lanes start at multiples of 16");
+        if (full)
+            return shift_and_units<W, CHECK, WRITE, true>(lds, mask, m, li0, lo, (lo + li0) >> 4, li0 & 15, LN, o);
+    }
+    if (lo > hi) return 0u;
+    return shift_and_units<W, CHECK, WRITE, false>(lds, mask, m, li0, lo, (lo + li0) >> 4, (lo + li0) & 15,
+                                                   hi - lo + 1, o);
 }
 
 // BNDM: masks B[c] bit i set iff p[m-1-i] == c. Q > 1 is the q-gram form (BNDMq,

@@ -216,7 +216,7 @@ template <int ALGO, int L, int VAR, bool WRITE, class E>
 __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanArgs &a, int m,
                                              int sh1, int period, int period_lb, uint64_t s,
                                              int li0, int lo, int hi, E &o, const BruteWords &bw,
-                                             uint4 ppre = uint4{0u, 0u, 0u, 0u})
+                                             uint4 ppre = uint4{0u, 0u, 0u, 0u}, bool full = false)
 {
     if constexpr (ALGO == ALGO_SHIFT_AND && VAR == 5 && (takes_masks<E>::value || is_no_emit<E>::value)) {
         // m > SA_SUFFIX: candidates (the last SA_SUFFIX bytes match) as a bitmap first,
@@ -226,7 +226,7 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
         constexpr int NW = L > 64 ? L / 64 : 1;
         BitAcc<NW> cand;
         const int sli0 = li0 + (int)a.sfx_off;  // LDS index of the suffix of start 0
-        if (lo <= hi) lane_shift_and<uint64_t, 16, false>(S.text, S.mask, SA_SUFFIX, sli0, lo, hi, cand);
+        lane_shift_and<uint64_t, 16, false, L>(S.text, S.mask, SA_SUFFIX, sli0, lo, hi, cand, full);
         const SuffixCtx sc{a.text0, a.pat, S.text, sli0, s, a.m_full, per, ppre};
         const uint32_t c = suffix_resolve<L>(cand, sc, lo);
         if constexpr (takes_masks<E>::value) {
@@ -241,19 +241,19 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
             const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
             {  // hits one by one: checked as they come
                 SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full, per, s, lo};
-                lane_shift_and<uint64_t, 16, true>(S.text, S.mask, SA_SUFFIX, li0 + (int)a.sfx_off, lo, hi, sv);
+                lane_shift_and<uint64_t, 16, true, L>(S.text, S.mask, SA_SUFFIX, li0 + (int)a.sfx_off, lo, hi, sv, full);
                 return sv.n;
             }
         }
         if (VAR == 4)
-            return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint8_t *>(S.mask), m,
-                                                       li0, lo, hi, o);
+            return lane_shift_and<uint32_t, 16, WRITE, L>(S.text, reinterpret_cast<const uint8_t *>(S.mask), m,
+                                                          li0, lo, hi, o, full);
         if (VAR == 0)
-            return lane_shift_and<uint32_t, 16, WRITE>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
-                                                       m, li0, lo, hi, o);
-        if (VAR == 1) return lane_shift_and<uint64_t, 16, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
-        if (VAR == 2) return lane_shift_and<uint64_t, 4, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
-        return lane_shift_and<uint64_t, 1, WRITE>(S.text, S.mask, m, li0, lo, hi, o);
+            return lane_shift_and<uint32_t, 16, WRITE, L>(S.text, reinterpret_cast<const uint32_t *>(S.mask),
+                                                          m, li0, lo, hi, o, full);
+        if (VAR == 1) return lane_shift_and<uint64_t, 16, WRITE, L>(S.text, S.mask, m, li0, lo, hi, o, full);
+        if (VAR == 2) return lane_shift_and<uint64_t, 4, WRITE, L>(S.text, S.mask, m, li0, lo, hi, o, full);
+        return lane_shift_and<uint64_t, 1, WRITE, L>(S.text, S.mask, m, li0, lo, hi, o, full);
     } else if constexpr (ALGO == ALGO_BNDM) {  // VAR selects the q-gram width 1, 2, 4
         constexpr int Q = VAR == 0 ? 1 : (VAR == 1 ? 2 : 4);
         return lane_bndm<Q, WRITE>(reinterpret_cast<const uint8_t *>(S.text), S.mask, m, li0, lo, hi, o);
@@ -370,18 +370,21 @@ __device__ __forceinline__ void count_body(const ScanArgs &a)
         }
         const int lo = threadIdx.x * L;
         const int hi = (lo + L - 1) < cur.hi_rel ? (lo + L - 1) : cur.hi_rel;
+        const bool full = cur.hi_rel >= G::T - 1;  // every lane has L starts (uniform)
         constexpr int NW = L > 64 ? L / 64 : 1;
         uint32_t c;
         [[maybe_unused]] CapEmit ce;
         [[maybe_unused]] BitAcc<NW> ba;
         if constexpr (MODE == CM_BITS) {
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba, bw, ppre);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ba, bw, ppre,
+                                              full);
         } else if constexpr (MODE == CM_CAP) {
-            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce, bw);
+            run_lane<ALGO, L, VAR, true>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ce, bw, ppre, full);
             c = ce.n;
         } else {
             NoEmit ne;
-            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne, bw, ppre);
+            c = run_lane<ALGO, L, VAR, false>(S, a, m, sh1, period, period_lb, cur.s, li0, lo, hi, ne, bw, ppre,
+                                              full);
         }
         uint32_t tot;
         const uint32_t before = block_excl_scan(c, S.w, tot);
