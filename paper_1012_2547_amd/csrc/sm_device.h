@@ -234,14 +234,13 @@ struct is_no_emit<NoEmit> {
 // The lane reads 16-byte units ub + k, k = 0..K, where ub holds its first start's
 // byte, r bytes into the unit, and nl is its number of starts; unit k ends the
 // windows at relative ends lo - r + 16k + [0, 16). Units whose 16 ends all lie in
-// the lane's range [lo + m - 1, lo + nl + m - 2] (k in [kf0, kf1]) take every hit;
+// the lane's range [e_lo, e_hi] = [lo + m - 1, lo + nl + m - 2] (k in [kf0, kf1]) take every hit;
 // only the units before and after them mask the ends of other lanes' starts
 // (SPLIT: with these bounds uniform; otherwise every unit is masked).
 template <typename W, int CHECK, bool WRITE, bool SPLIT, class E, typename MT>
 __device__ __forceinline__ uint32_t shift_and_units(const uint4 *lds, const MT *mask, int m, int li0, int lo,
                                                    int ub, int r, int nl, E &o)
 {
-    const int e_lo = lo + m - 1, e_hi = lo + nl - 1 + m - 1;  // relative ends owned by this lane
     const int K = (r + nl + m - 2) >> 4;
     const int kf0 = (m - 1 + r + 15) >> 4, kf1 = (nl + m - 17 + r) >> 4;
     W D = ~(W)0;
@@ -285,20 +284,22 @@ __device__ __forceinline__ uint32_t shift_and_units(const uint4 *lds, const MT *
                     D = (D << 1) | (W)mask[c];
                 }
             }
-            // relative end of the last byte consumed
+            // relative end of the last byte consumed, and its distance past the lane's first
+            // and last ends (16 u - li0 = lo + 16 k - r: with r and nl uniform, so are these)
             const int e_last = 16 * u + g * CHECK + CHECK - 1 - li0;
+            const int past_lo = 16 * k - r + g * CHECK + CHECK - 1 - (m - 1);  // e_last - e_lo
+            const int past_hi = past_lo - (nl - 1);                            // e_last - e_hi
             uint32_t hits = (uint32_t)((~D) >> (m - 1)) & ((1u << CHECK) - 1u);
             if constexpr (!decltype(interior)::value) {
-                int jlo = e_last - e_hi, jhi = e_last - e_lo;
-                jlo = jlo < 0 ? 0 : jlo;
-                jhi = jhi > CHECK - 1 ? CHECK - 1 : jhi;
+                const int jlo = past_hi < 0 ? 0 : past_hi;
+                const int jhi = past_lo > CHECK - 1 ? CHECK - 1 : past_lo;
                 hits = jlo <= jhi ? hits & ((2u << jhi) - 1u) & ~((1u << jlo) - 1u) : 0u;
             }
             if (hits) {
                 if constexpr (takes_masks<E>::value) {
                     // reversed, bit i <-> end e_last - CHECK + 1 + i, i.e. start
                     // lo + (e_last - CHECK + 1 - e_lo) + i
-                    o.put_mask(e_last - CHECK + 1 - e_lo, __builtin_bitreverse32(hits) >> (32 - CHECK));
+                    o.put_mask(past_lo - CHECK + 1, __builtin_bitreverse32(hits) >> (32 - CHECK));
                     cnt += __builtin_popcount(hits);
                 } else if (WRITE && o.saturated()) {
                     o.add((uint32_t)__builtin_popcount(hits));
