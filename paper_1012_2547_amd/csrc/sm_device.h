@@ -231,15 +231,15 @@ struct is_no_emit<NoEmit> {
 // a byte when m <= 8 (the masks' bits >= m are clear), so that the table index is
 // the text byte itself, with no scaling.
 //
-// The lane reads 16-byte units ub + k, k = 0..K, where ub holds its first start's
-// byte, r bytes into the unit, and nl is its number of starts; unit k ends the
-// windows at relative ends lo - r + 16k + [0, 16). Units whose 16 ends all lie in
-// the lane's range [e_lo, e_hi] = [lo + m - 1, lo + nl + m - 2] (k in [kf0, kf1]) take every hit;
-// only the units before and after them mask the ends of other lanes' starts
+// The lane owns the nl tile-relative starts lo .. lo + nl - 1 and reads 16-byte units
+// ub + k, k = 0..K, where unit ub holds its first start's byte r bytes in; unit k ends
+// the windows at relative ends lo - r + 16k + [0, 16). Units whose 16 ends all lie in
+// the lane's range [e_lo, e_hi] = [lo + m - 1, lo + nl + m - 2] (k in [kf0, kf1]) take
+// every hit; only the units before and after them mask the ends of other lanes' starts
 // (SPLIT: with these bounds uniform; otherwise every unit is masked).
 template <typename W, int CHECK, bool WRITE, bool SPLIT, class E, typename MT>
-__device__ __forceinline__ uint32_t shift_and_units(const uint4 *lds, const MT *mask, int m, int li0, int lo,
-                                                   int ub, int r, int nl, E &o)
+__device__ __forceinline__ uint32_t shift_and_units(const uint4 *lds, const MT *mask, int m, int li0, int ub,
+                                                   int r, int nl, E &o)
 {
     const int K = (r + nl + m - 2) >> 4;
     const int kf0 = (m - 1 + r + 15) >> 4, kf1 = (nl + m - 17 + r) >> 4;
@@ -336,11 +336,11 @@ __device__ __forceinline__ uint32_t lane_shift_and(const uint4 *lds, const MT *m
     if constexpr (LN > 0) {
         static_assert(LN % 16 == 0, "lanes start at multiples of 16");
         if (full)
-            return shift_and_units<W, CHECK, WRITE, true>(lds, mask, m, li0, lo, (lo + li0) >> 4, li0 & 15, LN, o);
+            return shift_and_units<W, CHECK, WRITE, true>(lds, mask, m, li0, (lo + li0) >> 4, li0 & 15, LN, o);
     }
     if (lo > hi) return 0u;
-    return shift_and_units<W, CHECK, WRITE, false>(lds, mask, m, li0, lo, (lo + li0) >> 4, (lo + li0) & 15,
-                                                   hi - lo + 1, o);
+    return shift_and_units<W, CHECK, WRITE, false>(lds, mask, m, li0, (lo + li0) >> 4, (lo + li0) & 15, hi - lo + 1,
+                                                   o);
 }
 
 // BNDM: masks B[c] bit i set iff p[m-1-i] == c. Q > 1 is the q-gram form (BNDMq,
