@@ -377,6 +377,28 @@ def test_dense_bitmap_form_mixed_tiles(sm):
             assert tot == want.size and np.array_equal(got, want[:cap]), (p, cap)
 
 
+def test_shift_and_whole_tiles_at_every_alignment(sm):
+    """In whole tiles the Shift-And lanes run with wave-uniform unit bounds: the units
+    whose 16 window ends all belong to the lane take every hit unmasked, the first and
+    last ones mask their neighbours' ends. Where a lane's first start falls inside its
+    16-byte unit follows from the text's device address, so every offset 0..15 is run,
+    with dense and sparse hits, every state width (byte, 32-bit and 64-bit masks, checks
+    every 16, 4 and 1 bytes) and lane width, in count and find mode, against the oracle."""
+    base_np = np.concatenate([dg.uniform_text(60_000, 2, seed=41), np.zeros(7_001, np.uint8),
+                              dg.uniform_text(60_000, 4, seed=42)])
+    base = torch.from_numpy(base_np).to(DEV)
+    for off in range(16):
+        t_np = base_np[off:]
+        t_dev = base[off:]  # device pointer offset by `off` bytes
+        pats = [bytes(t_np[1000:1000 + m]) for m in (1, 3, 8, 9, 16, 17, 30, 49, 50, 57, 64)]
+        pats += [bytes(m) for m in (1, 8, 17)]  # every start of the zero run
+        for p in pats:
+            want = oracle.find_all(t_np, p)
+            for L, tpw in ((32, 1), (64, 1), (64, 2), (128, 1)):
+                got, tot = gpu_find(sm, t_dev, p, algo=1, lane=L, tpw=tpw)
+                assert tot == want.size and np.array_equal(got, want), (off, len(p), L, tpw)
+
+
 def test_edges_and_alignment(sm):
     rng = np.random.default_rng(0)
     base_np = rng.integers(0, 3, 20_000, dtype=np.uint8)
