@@ -277,7 +277,18 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     p.slots = (double)m * std::log((double)sigma) >= std::log((double)p.lane_bytes) ? 1 : 0;
     // the suffix form of Shift-And (m > 49) verifies each hit from global memory: lanes
     // keep their first hits so that tiles with few hits are not scanned twice
-    if (algo == ALGO_SHIFT_AND && m > (uint64_t)SA_SUFFIX) p.slots = 1;
+    if (algo == ALGO_SHIFT_AND && m > (uint64_t)SA_SUFFIX) {
+        p.slots = 1;
+        // The last 17 bytes on a 32-bit state scan in about half the operations of the
+        // last 49 on a 64-bit one, and a start one period after an occurrence is still
+        // taken without reading when the period is at most 17. A pattern whose smallest
+        // period lies in (17, 49] keeps the 49-byte suffix, so that such starts (every
+        // period of a periodic text) are not read in full.
+        uint32_t per = 0;
+        for (uint32_t d = 1; d <= (uint32_t)SA_SUFFIX && !per; d++)
+            if (memcmp(pat, pat + d, m - d) == 0) per = d;
+        p.sfx = (per > (uint32_t)SA_SHORT) ? SA_SUFFIX : SA_SHORT;
+    }
     return SM_OK;
 }
 

@@ -537,7 +537,8 @@ __device__ __forceinline__ bool verify_wave(const uint8_t *text, uint64_t g, con
 }
 
 // Suffix forms for long patterns: the scan finds the pattern's last SFX bytes
-// (Shift-And for m > SA_SUFFIX; SBNDM for m > 64, its factor form); each such start
+// (Shift-And for m > SA_SUFFIX, SFX = SA_SUFFIX or SA_SHORT; SBNDM for m > 64, its
+// factor form); each such start
 // g is an occurrence when the first m - SFX bytes match too, read from global
 // memory. A start exactly one period (<= SFX) after the lane's previous occurrence
 // needs no reading: bytes [0, m - period) repeat that occurrence shifted by the
@@ -613,17 +614,17 @@ __device__ __forceinline__ uint4 readlane4(uint4 v, int k)
     return r;
 }
 
-// Where the suffix form reads a candidate's first m - SA_SUFFIX bytes: the LDS tile
-// holds the (shifted) text from tile-relative position -li0 on, so a candidate at
-// tile-relative start rel has them in LDS from byte index li0 + rel - (m - SA_SUFFIX)
-// when that is >= 0; the pattern's first 1024 bytes sit in registers, 16 per lane
-// (lane k: bytes [16 k, 16 k + 16)).
+// Where the suffix form reads a candidate's first m - sfx bytes (sfx: the suffix the
+// scan matched): the LDS tile holds the (shifted) text from tile-relative position -li0
+// on, so a candidate at tile-relative start rel has them in LDS from byte index
+// li0 + rel - (m - sfx) when that is >= 0; the pattern's first 1024 bytes sit in
+// registers, 16 per lane (lane k: bytes [16 k, 16 k + 16)).
 struct SuffixCtx {
     const uint8_t *text0, *pat;  // original text, pattern copy (zero padded)
     const uint4 *lds;            // the staged tile
     int li0;                     // LDS byte index of tile-relative start 0 (shifted text)
     uint64_t s;                  // global start of tile-relative start 0
-    uint32_t m, period;          // period: the smallest when <= SA_SUFFIX, else 0
+    uint32_t m, sfx, period;     // period: the smallest when <= sfx, else 0
     uint4 ppre;                  // pattern bytes [16 lane, 16 lane + 16)
 };
 
@@ -631,7 +632,7 @@ struct SuffixCtx {
 // lanes call it with the same rel.
 __device__ __forceinline__ bool suffix_check_wave(const SuffixCtx &c, int rel)
 {
-    const uint32_t len = c.m - (uint32_t)SA_SUFFIX;
+    const uint32_t len = c.m - c.sfx;
     const int b0 = c.li0 + rel - (int)len;  // LDS index of the candidate's first byte
     const uint32_t lane = threadIdx.x & 63;
     if (b0 < 0 || len > 1024) return verify_wave(c.text0, c.s + (uint64_t)rel, c.pat, c.m, 0, len);
@@ -644,7 +645,7 @@ __device__ __forceinline__ bool suffix_check_wave(const SuffixCtx &c, int rel)
 // The same check by one lane for its own candidate (uniform loop bounds).
 __device__ __forceinline__ bool suffix_check_lane(const SuffixCtx &c, int rel, bool active)
 {
-    const uint32_t len = c.m - (uint32_t)SA_SUFFIX;
+    const uint32_t len = c.m - c.sfx;
     const int b0 = c.li0 + rel - (int)len;
     bool ok = true;
     if (active && b0 >= 0 && len <= 1024) {
@@ -671,11 +672,11 @@ __device__ __forceinline__ bool suffix_check_lane(const SuffixCtx &c, int rel, b
 }
 
 // The suffix form's candidates, settled after the scan: ba holds the lane's starts
-// whose last SA_SUFFIX bytes match (bit i <-> tile-relative start lo + i) and keeps
+// whose last sfx bytes match (bit i <-> tile-relative start lo + i) and keeps
 // those that are occurrences. Each lane walks its candidates in ascending order; a
-// start exactly one period (<= SA_SUFFIX) after the lane's previous occurrence is
+// start exactly one period (<= sfx) after the lane's previous occurrence is
 // one without reading (as in SuffixVerify). The others compare their first
-// m - SA_SUFFIX bytes with the pattern, from the LDS tile where it holds them:
+// m - sfx bytes with the pattern, from the LDS tile where it holds them:
 // when few lanes of the wave have such a candidate at once the whole wave checks
 // each of them, 16 bytes per lane; when many do (a text of one symbol: every lane's
 // first candidate), each lane checks its own. Wave-cooperative: all 64 lanes call
@@ -1129,10 +1130,10 @@ __device__ __forceinline__ void build_tables(const uint8_t *pp, uint32_t m, uint
     const int tid = threadIdx.x;
     if (algo == ALGO_SHIFT_AND) {
         // complemented masks: bit j clear iff p[j] == c (j < m); bits >= m clear. With
-        // q_ = SA_SUFFIX (single-pattern suffix form, m > SA_SUFFIX) the masks are those
-        // of the pattern's last SA_SUFFIX bytes.
+        // q_ = SA_SUFFIX or SA_SHORT (single-pattern suffix form, m > SA_SUFFIX) the masks
+        // are those of the pattern's last q_ bytes.
         const uint32_t c = tid;
-        const uint32_t ms = (q_ == (uint32_t)SA_SUFFIX && m > q_) ? q_ : m;
+        const uint32_t ms = ((q_ == (uint32_t)SA_SUFFIX || q_ == (uint32_t)SA_SHORT) && m > (uint32_t)SA_SUFFIX) ? q_ : m;
         const uint8_t *ps = pp + (m - ms);
         uint64_t w = 0;
         for (uint32_t j = 0; j < ms; j++)

@@ -29,6 +29,8 @@ constexpr int BLOCK = 256;         // threads per workgroup (4 wave64)
 constexpr int BP_MAX_M = 64;       // bit-parallel state lives in one 64-bit lane register
 constexpr int FSBNDM_MAX_M = BP_MAX_M - 1;  // FSBNDM: the pattern and one look-ahead position fit 64 bits
 constexpr int SA_SUFFIX = 49;      // Shift-And for m > SA_SUFFIX scans the pattern's last 49 bytes
+constexpr int SA_SHORT = 17;       // ... or its last 17 bytes (32-bit state) when no period of the
+                                   // pattern lies in (SA_SHORT, SA_SUFFIX]
 constexpr int SA_STAGE_MAX = 1024 + SA_SUFFIX;  // its tiles stage whole windows up to this m
 constexpr int Q_MAX = 16;          // longest hashed q-gram
 constexpr int H_MIN = 8;           // hash table bits range
@@ -81,6 +83,7 @@ struct Plan {
     int32_t tiles_per_wg; // consecutive tiles per workgroup (count kernel)
     int32_t slots;        // find: keep lanes' first hits while counting (tiles expected sparse)
     uint64_t m;
+    int32_t sfx = 0;      // Shift-And, m > SA_SUFFIX: the suffix scanned (SA_SUFFIX or SA_SHORT)
 };
 
 // A tile with hits, as the tile-count scan lists it for the emit pass.

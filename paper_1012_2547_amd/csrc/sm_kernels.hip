@@ -66,12 +66,12 @@ struct ScanArgs {
     uint32_t *bits;       // find, bitmap form: hit bitmaps of the dense tiles (T / 32 words per tile)
     int64_t *out;         // emit: hit number k of the pattern goes to out[k - lo]
     uint64_t lo, cap;     // emit: window [lo, lo + cap) of hit numbers
-    // Shift-And for m > SA_SUFFIX (the scan finds the pattern's last SA_SUFFIX bytes; text0
-    // and m_full are the original text and m, for the check of the first m - SA_SUFFIX
-    // bytes). Up to SA_STAGE_MAX, text/n/m above are the originals too and the tiles
-    // stage whole windows: the scan reads them from sfx_off = m - SA_SUFFIX bytes on.
-    // Longer patterns: text/n above are the text shifted by m - SA_SUFFIX, m above is
-    // SA_SUFFIX and sfx_off is 0.
+    // Shift-And for m > SA_SUFFIX (the scan finds the pattern's last sfx bytes, sfx =
+    // SA_SUFFIX or SA_SHORT as planned; text0 and m_full are the original text and m, for
+    // the check of the first m - sfx bytes). Up to SA_STAGE_MAX, text/n/m above are the
+    // originals too and the tiles stage whole windows: the scan reads them from sfx_off =
+    // m - sfx bytes on. Longer patterns: text/n above are the text shifted by m - sfx, m
+    // above is sfx and sfx_off is 0.
     const uint8_t *text0;
     uint32_t m_full, sfx_off;
 };
@@ -145,7 +145,7 @@ __device__ __forceinline__ void tables_commit(uint4 r, uint64_t *s_mask, uint8_t
     const uint32_t tid = threadIdx.x;
     if (ALGO == ALGO_HASHQ) {
         if (tid < ((1u << hbits) >> 4)) reinterpret_cast<uint4 *>(s_shift)[tid] = r;
-    } else if (ALGO == ALGO_SHIFT_AND && VAR == 0) {
+    } else if (ALGO == ALGO_SHIFT_AND && (VAR == 0 || VAR == 6)) {  // 32-bit masks
         reinterpret_cast<uint32_t *>(s_mask)[tid] = r.x;
     } else if (ALGO == ALGO_SHIFT_AND && VAR == 4) {  // m <= 8: the masks fit a byte
         reinterpret_cast<uint8_t *>(s_mask)[tid] = (uint8_t)r.x;
@@ -218,16 +218,22 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
                                              int li0, int lo, int hi, E &o, const BruteWords &bw,
                                              uint4 ppre = uint4{0u, 0u, 0u, 0u}, bool full = false)
 {
-    if constexpr (ALGO == ALGO_SHIFT_AND && VAR == 5 && (takes_masks<E>::value || is_no_emit<E>::value)) {
-        // m > SA_SUFFIX: candidates (the last SA_SUFFIX bytes match) as a bitmap first,
-        // settled after the scan by the whole wave (every lane takes part)
-        static_assert(SA_SUFFIX - 1 + 16 <= 64, "hits checked every 16 bytes");
-        const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
+    // suffix forms (m > SA_SUFFIX): variant 5 scans the pattern's last SA_SUFFIX bytes on a
+    // 64-bit state, variant 6 its last SA_SHORT bytes on a 32-bit one (32-bit masks)
+    constexpr bool SUFFIX_FORM = ALGO == ALGO_SHIFT_AND && (VAR == 5 || VAR == 6);
+    constexpr int SFX = VAR == 6 ? SA_SHORT : SA_SUFFIX;
+    using SW = std::conditional_t<VAR == 6, uint32_t, uint64_t>;
+    static_assert(SFX - 1 + 16 <= 8 * (int)sizeof(SW), "hits checked every 16 bytes");
+    if constexpr (SUFFIX_FORM && (takes_masks<E>::value || is_no_emit<E>::value)) {
+        // candidates (the last SFX bytes match) as a bitmap first, settled after the scan
+        // by the whole wave (every lane takes part)
+        const uint32_t per = period > 0 && period <= SFX ? (uint32_t)period : 0u;
         constexpr int NW = L > 64 ? L / 64 : 1;
         BitAcc<NW> cand;
         const int sli0 = li0 + (int)a.sfx_off;  // LDS index of the suffix of start 0
-        lane_shift_and<uint64_t, 16, false, L>(S.text, S.mask, SA_SUFFIX, sli0, lo, hi, cand, full);
-        const SuffixCtx sc{a.text0, a.pat, S.text, sli0, s, a.m_full, per, ppre};
+        lane_shift_and<SW, 16, false, L>(S.text, reinterpret_cast<const SW *>(S.mask), SFX, sli0, lo, hi, cand,
+                                         full);
+        const SuffixCtx sc{a.text0, a.pat, S.text, sli0, s, a.m_full, (uint32_t)SFX, per, ppre};
         const uint32_t c = suffix_resolve<L>(cand, sc, lo);
         if constexpr (takes_masks<E>::value) {
 #pragma unroll
@@ -237,11 +243,12 @@ __device__ __forceinline__ uint32_t run_lane(TileShared<ALGO, L> &S, const ScanA
     }
     if (ALGO != ALGO_HASHQ && lo > hi) return 0u;  // Hash-q lanes take part in wave checks
     if constexpr (ALGO == ALGO_SHIFT_AND) {
-        if constexpr (VAR == 5) {  // m > SA_SUFFIX: the last SA_SUFFIX bytes, then the rest verified
-            const uint32_t per = period > 0 && period <= SA_SUFFIX ? (uint32_t)period : 0u;
+        if constexpr (SUFFIX_FORM) {  // m > SA_SUFFIX: the last SFX bytes, then the rest verified
+            const uint32_t per = period > 0 && period <= SFX ? (uint32_t)period : 0u;
             {  // hits one by one: checked as they come
-                SuffixVerify<E> sv{o, a.text0, a.pat, a.m_full, per, s, lo};
-                lane_shift_and<uint64_t, 16, true, L>(S.text, S.mask, SA_SUFFIX, li0 + (int)a.sfx_off, lo, hi, sv, full);
+                SuffixVerify<E, SFX> sv{o, a.text0, a.pat, a.m_full, per, s, lo};
+                lane_shift_and<SW, 16, true, L>(S.text, reinterpret_cast<const SW *>(S.mask), SFX,
+                                                li0 + (int)a.sfx_off, lo, hi, sv, full);
                 return sv.n;
             }
         }
@@ -349,9 +356,10 @@ __device__ __forceinline__ void count_body(const ScanArgs &a)
     uint64_t sup_i = ~0ull, sup_v = 0;  // this workgroup's pending super-chunk total (thread 0)
     // suffix form: the pattern's first 1024 bytes, 16 per lane, for the candidates' checks
     uint4 ppre = {0u, 0u, 0u, 0u};
-    if constexpr (ALGO == ALGO_SHIFT_AND && VAR == 5) {
+    if constexpr (ALGO == ALGO_SHIFT_AND && (VAR == 5 || VAR == 6)) {
         const uint32_t lane = threadIdx.x & 63;
-        if (16 * lane < a.m_full - (uint32_t)SA_SUFFIX) ppre = reinterpret_cast<const uint4 *>(a.pat)[lane];
+        const uint32_t sfx = VAR == 6 ? (uint32_t)SA_SHORT : (uint32_t)SA_SUFFIX;
+        if (16 * lane < a.m_full - sfx) ppre = reinterpret_cast<const uint4 *>(a.pat)[lane];
     }
 
     for (uint64_t t = t_begin; t < t_end; t++) {
@@ -1140,9 +1148,13 @@ hipError_t launch_any(const Plan &p, const ScanArgs &a, uint32_t grid, hipStream
         // variants: 4 = 32-bit state, byte masks (m <= 8); 0 = 32-bit state and masks;
         // 1 = 64-bit state, hits checked every 16 bytes (m <= 49); 5 = m > 49: the last
         // SA_SUFFIX bytes scanned as variant 1 does, the rest verified (faster than
-        // checking hits every 4 or every byte, which m = 50..64 would need)
+        // checking hits every 4 or every byte, which m = 50..64 would need); 6 = the same
+        // with the last SA_SHORT bytes scanned as variant 0 does (the plan's choice)
         static_assert(SA_SUFFIX == 49, "variant 1 covers m <= 49");
-        if (m > SA_SUFFIX) return launch_l<ALGO_SHIFT_AND, 5, KIND>(p, a, grid, st);
+        if (m > SA_SUFFIX) {
+            if (p.sfx == SA_SHORT) return launch_l<ALGO_SHIFT_AND, 6, KIND>(p, a, grid, st);
+            return launch_l<ALGO_SHIFT_AND, 5, KIND>(p, a, grid, st);
+        }
         if (m <= 8) return launch_l<ALGO_SHIFT_AND, 4, KIND>(p, a, grid, st);
         if (m <= 17) return launch_l<ALGO_SHIFT_AND, 0, KIND>(p, a, grid, st);
         return launch_l<ALGO_SHIFT_AND, 1, KIND>(p, a, grid, st);
@@ -1192,7 +1204,8 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
     a.bs = plan.algo == ALGO_BLOCK ? (uint32_t)plan.lane_bytes : 0u;
     a.ntiles = ntiles;
     if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)SA_SUFFIX) {  // suffix form (n >= m)
-        const uint64_t sh = plan.m - SA_SUFFIX;
+        const uint32_t sfx = plan.sfx == SA_SHORT ? (uint32_t)SA_SHORT : (uint32_t)SA_SUFFIX;
+        const uint64_t sh = plan.m - sfx;
         a.text0 = d_text;
         a.m_full = (uint32_t)plan.m;
         if (plan.m <= (uint64_t)SA_STAGE_MAX) {  // whole windows in LDS
@@ -1200,7 +1213,7 @@ ScanArgs make_args(const Plan &plan, const uint8_t *d_text, uint64_t n, const Pa
         } else {
             a.text = d_text + sh;
             a.n = n - sh;
-            a.m = SA_SUFFIX;
+            a.m = sfx;
         }
     }
     if (plan.algo == ALGO_SBNDM && plan.m > (uint64_t)BP_MAX_M) {  // factor form (n >= m)
@@ -1234,7 +1247,8 @@ hipError_t launch_prep(const Plan &plan, const uint8_t *pat_host, Params *d_para
     a.m = (uint32_t)plan.m;
     a.algo = (uint32_t)plan.algo;
     a.q = (uint32_t)plan.q;
-    if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)SA_SUFFIX) a.q = SA_SUFFIX;  // suffix masks
+    if (plan.algo == ALGO_SHIFT_AND && plan.m > (uint64_t)SA_SUFFIX)  // suffix masks
+        a.q = plan.sfx == SA_SHORT ? (uint32_t)SA_SHORT : (uint32_t)SA_SUFFIX;
     a.hbits = (uint32_t)plan.hbits;
     if (plan.m <= PREP_INLINE) {
         a.inline_len = (uint32_t)plan.m;

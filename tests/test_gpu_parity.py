@@ -553,6 +553,23 @@ def _suffix_check(sm, t_np, pats, lanes=(16, 64, 128), tpws=(1, 2)):
             assert total == want.size and np.array_equal(got, want[:want.size // 2])
 
 
+def test_shift_and_suffix_form_by_period(sm):
+    """The suffix form scans the pattern's last 17 bytes (32-bit state) unless the
+    pattern's smallest period lies in (17, 49], when it scans the last 49: a start one
+    period after an occurrence is then taken without reading. Patterns of smallest period
+    1..64 on texts repeating them (every period a candidate, most of them occurrences),
+    with the repetition broken here and there, against the oracle."""
+    rng = np.random.default_rng(77)
+    for P in (1, 5, 17, 18, 30, 49, 50, 64):
+        unit = rng.integers(0, 4, P, dtype=np.uint8)
+        unit[0] = 7  # no smaller period
+        t_np = np.tile(unit, 70_000 // P + 2)[:70_000 + P % 7].copy()
+        for k in range(0, t_np.size, 9_973):  # broken repeats
+            t_np[k] = 9
+        pats = [bytes(t_np[20:20 + m]) for m in (50, 64, 65, 130, 1000)]
+        _suffix_check(sm, t_np, pats, lanes=(16, 64, 128), tpws=(1,))
+
+
 @pytest.mark.parametrize("sigma", [2, 4, 256])
 def test_shift_and_suffix_form_random(sm, sigma):
     """Shift-And with m > 64 (the last 49 bytes scanned, the first m - 49 verified), forced,
