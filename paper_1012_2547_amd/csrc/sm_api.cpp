@@ -222,7 +222,8 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
     const bool have = tune_lookup(sigma, m, te);
     int algo = have ? te.algo : 0;
     // entries not applicable to this m
-    if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && algo != ALGO_SBNDM && m > BP_MAX_M) algo = 0;
+    if (algo != ALGO_HASHQ && algo != ALGO_BLOCK && algo != ALGO_SBNDM && algo != ALGO_SHIFT_AND && m > BP_MAX_M)
+        algo = 0;
     if (algo == ALGO_BLOCK && (m < (uint64_t)BF_MIN_M || m > (uint64_t)BF_MAX_M)) algo = 0;
     if (algo == ALGO_BRUTE && m > (uint64_t)BRUTE_MAX_M) algo = 0;
     if (algo == ALGO_FSBNDM && m > (uint64_t)FSBNDM_MAX_M) algo = 0;
@@ -429,12 +430,16 @@ static int validate_common(const uint8_t *text, uint64_t n, const uint8_t *pat, 
 
 // Whether a plan for a pattern of length m under opts may keep hit bitmaps beyond
 // m <= 64: Shift-And's suffix form does, which the planner takes on texts of one
-// dominant symbol (sigma < 2) or when it is forced.
+// dominant symbol (sigma < 2), where the tuning table picks it, or when it is forced.
 static bool may_keep_bitmap(uint64_t m, const sm_opts *o)
 {
     if (m <= (uint64_t)BP_MAX_M) return true;
     if (o && o->algo) return o->algo == ALGO_SHIFT_AND;
-    if (o && o->sigma_hint > 0) return o->sigma_hint < 2;
+    if (o && o->sigma_hint > 0) {  // Shift-And on a text of one symbol, or where the table says
+        if (o->sigma_hint < 2) return true;
+        sm_tune_entry te;
+        return tune_lookup(std::min(o->sigma_hint, 256), m, te) && te.algo == ALGO_SHIFT_AND;
+    }
     return true;
 }
 

@@ -1,9 +1,10 @@
 """Autotuner for the planner's (alphabet size, pattern length) -> kernel table.
 
 For each alphabet-size bucket (representative sigma in 2, 4, 16, 64, 256) and a
-grid of pattern lengths, every applicable configuration -- algorithm (Shift-And,
-BNDM and BNDMq, SBNDM and SBNDMq (beyond m = 64 in their factor form), forward SBNDM, Hash-q with its gram length q, the block
-filter, brute force), starts per lane
+grid of pattern lengths, every applicable configuration -- algorithm (Shift-And, beyond
+m = 49 in its suffix form; BNDM and BNDMq; SBNDM and SBNDMq, beyond m = 64 in their
+factor form; forward SBNDM; Hash-q with its gram length q; the block filter; brute
+force), starts per lane
 and tiles per workgroup -- is timed on an i.i.d. uniform text (tuning seed 2, distinct from the
 benchmark's seed 1) with substring patterns, as whole find_all calls. The
 fastest configuration of each cell becomes a table entry. The paper's own
@@ -57,6 +58,10 @@ def candidates(m: int, sigma: int):
                 for L in (32, 64, 128):
                     for tpw in (1, 2, 4):
                         out.append(dict(algo=7, lane_bytes=L, q=0, tiles_per_wg=tpw))
+    if m > 64:  # Shift-And's suffix form: the last 17 (or 49) bytes scanned, the rest verified
+        for L in (64, 128):
+            for tpw in (1, 2):
+                out.append(dict(algo=1, lane_bytes=L, q=0, tiles_per_wg=tpw))
     if m > 64:  # SBNDM's factor form: the last 64 bytes searched, the rest verified
         for q in (1, 2, 4, 8):
             for L in (64, 128):

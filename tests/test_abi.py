@@ -150,6 +150,34 @@ def test_block_filter_workspace(L):
             assert sm.workspace_size(n + (1 << 20), m, blk) >= fb, (n, m)
 
 
+def test_workspace_covers_table_shift_and_beyond_64(L):
+    """Shift-And keeps hit bitmaps at any m (its suffix form beyond 49): where the tuning
+    table picks it for m > 64, the planner's workspace under that alphabet hint covers the
+    forced configuration's, at both ends of the entry's length range."""
+    import paper_1012_2547_amd as sm
+    n = (1 << 20) + 7
+    seen = 0
+    for e in sm.tune_get():
+        if e["algo"] != sm.ALGO_SHIFT_AND or e["m_hi"] <= 64:
+            continue
+        sigma = min(e["sigma_hi"], 256)
+        for m in {max(e["m_lo"], 65), min(e["m_hi"], 4000)}:
+            forced = sm.opts(algo=sm.ALGO_SHIFT_AND, lane_bytes=e["lane_bytes"],
+                             tiles_per_wg=e["tiles_per_wg"], sigma_hint=sigma)
+            assert sm.workspace_size(n, m, sm.opts(sigma_hint=sigma)) >= sm.workspace_size(n, m, forced), (e, m)
+            seen += 1
+    # the same with a table that puts Shift-And at every length of one alphabet bucket
+    try:
+        sm.tune_set([dict(sigma_lo=3, sigma_hi=7, m_lo=1, m_hi=0xFFFFFFFF, algo=sm.ALGO_SHIFT_AND,
+                          lane_bytes=32, q=0, tiles_per_wg=1, hbits=0)])
+        forced = sm.opts(algo=sm.ALGO_SHIFT_AND, lane_bytes=32, tiles_per_wg=1, sigma_hint=4)
+        for m in (65, 100, 1000, 5000):
+            assert sm.workspace_size(n, m, sm.opts(sigma_hint=4)) >= sm.workspace_size(n, m, forced), m
+            assert sm.plan_query(bytes(range(4)) * (m // 4 + 1), sm.opts(sigma_hint=4))["algo"] == "shift_and"
+    finally:
+        sm.tune_set([])  # the built-in table again
+
+
 def test_planner_choices(L):
     import paper_1012_2547_amd as sm
     assert sm.plan_query(b"ab")["algo"] in ("shift_and", "bndm", "sbndm")
