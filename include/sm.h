@@ -55,10 +55,11 @@ typedef struct sm_corpus sm_corpus;
 enum sm_algo {
     SM_ALGO_AUTO = 0,
     SM_ALGO_SHIFT_AND = 1, /* Shift-And / Shift-Or, bit-parallel (Fig. 3), one step per text byte;
-                              for m > 49 the pattern's last 49 bytes are scanned and the first
-                              m - 49 verified (a start one period, <= 49, after an occurrence
-                              without reading): linear on texts of one symbol, where the
-                              planner takes it for every m */
+                              for m > 49 the pattern's last 17 bytes are scanned (its last 49
+                              when its smallest period lies in 18..49) and the rest verified (a
+                              start one period after an occurrence, the period inside the
+                              scanned suffix, without reading): linear on texts of one symbol,
+                              where the planner takes it for every m */
     SM_ALGO_BNDM = 2,      /* Backward Nondeterministic DAWG Matching, m <= 64 (Fig. 3); with q = 2 or 4
                               the window's last q bytes are read at once (BNDMq, Fig. 3) */
     SM_ALGO_SBNDM = 3,     /* Simplified BNDM (Fig. 3); any m: for m > 64 its factor form, in which
