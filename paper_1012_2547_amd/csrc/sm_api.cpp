@@ -284,11 +284,13 @@ static int make_plan(const uint8_t *pat, uint64_t m, const sm_opts *o, int sigma
         // last 49 on a 64-bit one, and a start one period after an occurrence is still
         // taken without reading when the period is at most 17. A pattern whose smallest
         // period lies in (17, 49] keeps the 49-byte suffix, so that such starts (every
-        // period of a periodic text) are not read in full.
+        // period of a periodic text) are not read in full. Beyond 16 MiB the pattern is not
+        // compared with itself on the host (49 passes over it): the 49-byte suffix is kept.
         uint32_t per = 0;
-        for (uint32_t d = 1; d <= (uint32_t)SA_SUFFIX && !per; d++)
+        const bool look = m <= (1ull << 24);
+        for (uint32_t d = 1; look && d <= (uint32_t)SA_SUFFIX && !per; d++)
             if (memcmp(pat, pat + d, m - d) == 0) per = d;
-        p.sfx = (per > (uint32_t)SA_SHORT) ? SA_SUFFIX : SA_SHORT;
+        p.sfx = (!look || per > (uint32_t)SA_SHORT) ? SA_SUFFIX : SA_SHORT;
     }
     return SM_OK;
 }
