@@ -98,9 +98,11 @@ typedef struct sm_opts {
     int32_t reserved[2];  /* must be zero */
 } sm_opts;
 
-/* What the planner chose for a pattern of length m (introspection). */
+/* What the planner chose for a pattern of length m (introspection). suffix: for
+ * Shift-And with m > 49, the length of the pattern's suffix the scan matches (17, or
+ * 49 when the pattern's smallest period lies in 18..49 or m exceeds 2^24), else 0. */
 typedef struct sm_plan_info {
-    int32_t algo, lane_bytes, q, hbits, tiles_per_wg, reserved;
+    int32_t algo, lane_bytes, q, hbits, tiles_per_wg, suffix;
 } sm_plan_info;
 
 const char *sm_version(void);

@@ -74,7 +74,7 @@ def plan_query(pat, o: Opts | None = None) -> dict:
     check(load().sm_plan_query(_pat_ptr(b), m, ctypes.byref(o) if o is not None else None,
                                ctypes.byref(info)))
     return {"algo": ALGO_NAMES[info.algo], "lane_bytes": info.lane_bytes, "q": info.q,
-            "hbits": info.hbits, "tiles_per_wg": info.tiles_per_wg}
+            "hbits": info.hbits, "tiles_per_wg": info.tiles_per_wg, "suffix": info.suffix}
 
 
 def find_all_async(text, pat, out, d_count, work, o: Opts | None = None, stream=None) -> int:

@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("lane_bytes", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("hbits", ctypes.c_int32), ("tiles_per_wg", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("suffix", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):

@@ -653,7 +653,7 @@ extern "C" int sm_plan_query(const uint8_t *pat, uint64_t m, const sm_opts *opts
     info->q = p.q;
     info->hbits = p.hbits;
     info->tiles_per_wg = p.tiles_per_wg;
-    info->reserved = 0;
+    info->suffix = p.sfx;
     return SM_OK;
 }
 

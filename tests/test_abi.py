@@ -178,6 +178,27 @@ def test_workspace_covers_table_shift_and_beyond_64(L):
         sm.tune_set([])  # the built-in table again
 
 
+def test_shift_and_suffix_by_period(L):
+    """Shift-And beyond m = 49 scans the pattern's last 17 bytes, or its last 49 when the
+    pattern's smallest period lies in 18..49 (a start one period after an occurrence is
+    then still taken without reading); shorter patterns have no suffix form; beyond
+    2^24 bytes the pattern is not searched for a period and keeps 49."""
+    import numpy as np
+    import paper_1012_2547_amd as sm
+    sa = sm.opts(algo=sm.ALGO_SHIFT_AND)
+    rng = np.random.default_rng(5)
+    for P, want in ((1, 17), (5, 17), (17, 17), (18, 49), (30, 49), (49, 49), (50, 17), (64, 17)):
+        unit = rng.integers(0, 4, P, dtype=np.uint8)
+        unit[0] = 7  # no smaller period
+        for m in (50, 64, 300):
+            p = bytes(np.tile(unit, m // P + 1)[:m])
+            assert sm.plan_query(p, sa)["suffix"] == want, (P, m)
+    assert sm.plan_query(bytes(range(200)), sa)["suffix"] == 17   # aperiodic
+    assert sm.plan_query(b"ab" * 24, sa)["suffix"] == 0            # m = 48: no suffix form
+    assert sm.plan_query(bytes(40), sm.opts(algo=sm.ALGO_SBNDM))["suffix"] == 0
+    assert sm.plan_query(bytes((1 << 24) + 1), sa)["suffix"] == 49  # too long to look
+
+
 def test_planner_choices(L):
     import paper_1012_2547_amd as sm
     assert sm.plan_query(b"ab")["algo"] in ("shift_and", "bndm", "sbndm")
